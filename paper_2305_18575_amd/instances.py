@@ -1,0 +1,227 @@
+"""Seeded synthetic REI instances (specifications (P, N) over an alphabet).
+
+This module holds no part of the inference method itself: it only draws
+inputs.  Both the GPU path and the CPU oracle are fed from here, so it must
+stay free of the language-cache / characteristic-sequence arithmetic.
+
+Recipe (the paper's own instance files are not available; these stand in):
+
+* A target regular expression is drawn uniformly among all expressions of a
+  drawn cost, over the grammar  a | r? | r* | r.r | r+r  with unit costs
+  (cost homomorphism (1,1,1,1,1), Definition of cost homomorphism, Sec. 3).
+  Uniformity comes from a counting table over costs.
+* Positive examples are drawn uniformly without replacement from the target's
+  language restricted to the length window; negative examples from the
+  complement in the same window.  Membership is decided by Python's ``re``
+  module on a translation of the target, which is independent of both
+  implementations under test.
+* If either side is too small, or the instance breaks a size bound, the
+  target is redrawn from the same random stream.
+
+All randomness comes from ``numpy.random.Generator(PCG64(seed))``.
+"""
+from __future__ import annotations
+
+import itertools
+import re
+from dataclasses import dataclass, field
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+# AST nodes are tuples: ('c', ch) | ('?', x) | ('*', x) | ('.', x, y) | ('+', x, y)
+
+
+def _ast_counts(nsym: int, kmax: int) -> List[int]:
+    """Number of ASTs of each exact cost 0..kmax under unit costs."""
+    cnt = [0] * (kmax + 1)
+    for k in range(1, kmax + 1):
+        if k == 1:
+            cnt[k] = nsym
+            continue
+        pair = sum(cnt[a] * cnt[k - 1 - a] for a in range(1, k - 1))
+        cnt[k] = 2 * cnt[k - 1] + 2 * pair
+    return cnt
+
+
+def random_ast(rng: np.random.Generator, sigma: str, cost: int):
+    """Uniformly random AST of exactly ``cost`` under unit costs."""
+    cnt = _ast_counts(len(sigma), cost)
+
+    def draw(k):
+        if k == 1:
+            return ('c', sigma[int(rng.integers(len(sigma)))])
+        total = cnt[k]
+        r = int(rng.integers(total))
+        # unary: '?' then '*'
+        if r < cnt[k - 1]:
+            return ('?', draw(k - 1))
+        r -= cnt[k - 1]
+        if r < cnt[k - 1]:
+            return ('*', draw(k - 1))
+        r -= cnt[k - 1]
+        for op in ('.', '+'):
+            for a in range(1, k - 1):
+                b = k - 1 - a
+                block = cnt[a] * cnt[b]
+                if r < block:
+                    return (op, draw(a), draw(b))
+                r -= block
+        raise AssertionError("unreachable")
+
+    return draw(cost)
+
+
+def ast_to_pyre(ast) -> str:
+    """Translate an AST into Python ``re`` syntax (non-capturing groups)."""
+    t = ast[0]
+    if t == 'c':
+        return re.escape(ast[1])
+    if t == '?':
+        return '(?:' + ast_to_pyre(ast[1]) + ')?'
+    if t == '*':
+        return '(?:' + ast_to_pyre(ast[1]) + ')*'
+    if t == '.':
+        return '(?:' + ast_to_pyre(ast[1]) + ')(?:' + ast_to_pyre(ast[2]) + ')'
+    if t == '+':
+        return '(?:' + ast_to_pyre(ast[1]) + '|' + ast_to_pyre(ast[2]) + ')'
+    raise ValueError(t)
+
+
+def ast_to_text(ast) -> str:
+    t = ast[0]
+    if t == 'c':
+        return ast[1]
+    if t in '?*':
+        return '(' + ast_to_text(ast[1]) + ')' + t
+    if t == '.':
+        return '(' + ast_to_text(ast[1]) + ast_to_text(ast[2]) + ')'
+    return '(' + ast_to_text(ast[1]) + '+' + ast_to_text(ast[2]) + ')'
+
+
+def words(sigma: str, lo: int, hi: int) -> List[str]:
+    """All strings over ``sigma`` with length in [lo, hi], length-major order."""
+    out = []
+    for n in range(lo, hi + 1):
+        out.extend(''.join(p) for p in itertools.product(sigma, repeat=n))
+    return out
+
+
+def n_infixes(strings) -> int:
+    """Size of the set of all substrings (used only as a rejection bound)."""
+    s = set()
+    for w in strings:
+        for i in range(len(w) + 1):
+            for j in range(i, len(w) + 1):
+                s.add(w[i:j])
+    return len(s)
+
+
+@dataclass
+class Instance:
+    alphabet: str
+    pos: List[str]
+    neg: List[str]
+    target: str = ""              # target regex in readable form (provenance only)
+    target_cost: int = 0
+    seed: int = 0
+    kind: str = ""
+    costs: Tuple[int, int, int, int, int] = (1, 1, 1, 1, 1)
+    max_cost: int = 30
+    meta: dict = field(default_factory=dict)
+
+
+def _draw_spec(rng, sigma, cost_lo, cost_hi, npos, nneg, len_lo, len_hi,
+               max_ic: Optional[int], universe=None):
+    universe = universe if universe is not None else words(sigma, len_lo, len_hi)
+    while True:
+        cost = int(rng.integers(cost_lo, cost_hi + 1))
+        ast = random_ast(rng, sigma, cost)
+        pat = re.compile(ast_to_pyre(ast))
+        inl = [w for w in universe if pat.fullmatch(w)]
+        outl = [w for w in universe if not pat.fullmatch(w)]
+        if len(inl) < npos or len(outl) < nneg:
+            continue
+        pi = rng.choice(len(inl), size=npos, replace=False)
+        ni = rng.choice(len(outl), size=nneg, replace=False)
+        pos = sorted(inl[int(i)] for i in pi)
+        neg = sorted(outl[int(i)] for i in ni)
+        if max_ic is not None and n_infixes(pos + neg) > max_ic:
+            continue
+        return ast, cost, pos, neg
+
+
+def plain_instance(seed: int) -> Instance:
+    """Small single instance: Sigma={0,1}, target cost 1..8, 4+4 strings of
+    length 1..5 (at most 63 distinct infixes, one 64-bit word per language)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ast, cost, pos, neg = _draw_spec(rng, "01", 1, 8, 4, 4, 1, 5, 63)
+    return Instance("01", pos, neg, ast_to_text(ast), cost, seed, "plain",
+                    (1, 1, 1, 1, 1), 30)
+
+
+def single_instance(seed: int, costs=(1, 1, 1, 1, 1)) -> Instance:
+    """Single instance: Sigma={0,1}, target cost 10..14 (unit costs), 10+10
+    strings of length 0..7 (at most 255 distinct infixes, four 64-bit words).
+    ``max_cost`` is the target's cost under ``costs``: the target is precise,
+    so the answer never costs more."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ast, cost, pos, neg = _draw_spec(rng, "01", 10, 14, 10, 10, 0, 7, 255)
+    return Instance("01", pos, neg, ast_to_text(ast), cost, seed, "single",
+                    tuple(costs), ast_cost(ast, costs))
+
+
+def large_instance(seed: int) -> Instance:
+    """Large single instance: Sigma={0,1,2}, target cost 14..18, 20+20 strings
+    of length 0..10, at most 2048 distinct infixes (32 words)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ast, cost, pos, neg = _draw_spec(rng, "012", 14, 18, 20, 20, 0, 10, 2048)
+    return Instance("012", pos, neg, ast_to_text(ast), cost, seed, "large",
+                    (1, 1, 1, 1, 1), cost)
+
+
+def batched_instances(master_seed: int, count: int) -> List[Instance]:
+    """Many small uneven instances: |Sigma| in {2,3,4}, 2..16 positive and
+    2..16 negative strings of length 0..6, target cost 4..12, at most 512
+    distinct infixes."""
+    mrng = np.random.Generator(np.random.PCG64(master_seed))
+    seeds = mrng.integers(0, 2**63 - 1, size=count)
+    out = []
+    universes = {}
+    for s in seeds:
+        rng = np.random.Generator(np.random.PCG64(int(s)))
+        k = int(rng.integers(2, 5))
+        sigma = "0123"[:k]
+        npos = int(rng.integers(2, 17))
+        nneg = int(rng.integers(2, 17))
+        if sigma not in universes:
+            universes[sigma] = words(sigma, 0, 6)
+        ast, cost, pos, neg = _draw_spec(rng, sigma, 4, 12, npos, nneg, 0, 6,
+                                         512, universes[sigma])
+        out.append(Instance(sigma, pos, neg, ast_to_text(ast), cost, int(s),
+                            "batched", (1, 1, 1, 1, 1), cost))
+    return out
+
+
+def ast_cost(ast, costs) -> int:
+    c1, c2, c3, c4, c5 = costs
+    t = ast[0]
+    if t == 'c':
+        return c1
+    if t == '?':
+        return ast_cost(ast[1], costs) + c2
+    if t == '*':
+        return ast_cost(ast[1], costs) + c3
+    if t == '.':
+        return ast_cost(ast[1], costs) + ast_cost(ast[2], costs) + c4
+    return ast_cost(ast[1], costs) + ast_cost(ast[2], costs) + c5
+
+
+def row_cap(cache_bytes: int, n_ic: int) -> int:
+    """Rows that fit ``cache_bytes``: each row is one language bitvector of
+    W 64-bit words (W = smallest power of two with 64*W >= n_ic) plus one
+    64-bit back-pointer word."""
+    w = 1
+    while 64 * w < n_ic:
+        w *= 2
+    return cache_bytes // (8 * w + 8)
