@@ -1,0 +1,175 @@
+"""Benchmark: unique languages enumerated per second on one MI355X.
+
+A step solves one batch of synthetic single instances (alphabet {0,1}, target
+expression of cost 10..14, 10 positive and 10 negative strings of length
+0..7, seeds 0..31, under the cost functions (1,1,1,1,1) and (1,1,5,1,2)),
+each through rei_solve on the current stream.  Instances are staged
+(rei_create: host staging + upload) before the timed region, so their
+tables are resident in HBM when timing starts.
+
+value = sum over the batch of unique languages enumerated / wall time of the
+batch.  The JSON line also carries the time-to-minimal-regex distribution,
+the dominant kernel's roofline figures (HIP events recorded by the library
+around each launch, on the stream the kernel runs on) and the CPU oracle's
+rate on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per work unit of each kernel class:
+# a generator must probe the dedup table once per candidate; a probe is a
+# random access, and the smallest HBM transaction is 64 bytes.
+PROBE_BYTES = 64
+
+
+def workload(name: str):
+    from paper_2305_18575_amd import instances
+    if name == "single":
+        out = []
+        for costs in ((1, 1, 1, 1, 1), (1, 1, 5, 1, 2)):
+            for seed in range(32):
+                out.append(instances.single_instance(seed, costs))
+        desc = ("single instance: alphabet {0,1}, target cost 10-14, 10+10 strings of length 0-7, "
+                "seeds 0-31 x cost functions (1,1,1,1,1) and (1,1,5,1,2), 64 solves per step")
+        return out, desc
+    if name == "plain":
+        out = [instances.plain_instance(s) for s in range(200)]
+        return out, "plain instance: alphabet {0,1}, target cost 1-8, 4+4 strings of length 1-5, seeds 0-199"
+    if name == "row1":
+        t = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_examples.json")))["table1_row1"]
+        inst = instances.Instance(t["alphabet"], t["pos"], t["neg"], "", 0, 0, "row1",
+                                  (1, 1, 1, 1, 1), 30)
+        return [inst], "Table 1 row 1 specification (10+12 strings), cost function (1,1,1,1,1)"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="single")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--max-errors", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the search is "
+              "not sharded across GPUs", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2305_18575_amd as rei
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    torch.cuda.set_device(0)
+    insts, desc = workload(args.workload)
+    handles = []
+    for it in insts:
+        h = rei.Instance(it.alphabet, it.pos, it.neg, it.costs, it.max_cost, cache_bytes=64 << 30)
+        if args.max_errors:
+            h.set_max_errors(args.max_errors)
+        handles.append(h)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def step():
+        res = []
+        for h in handles:
+            res.append(h.solve(stream))
+        return res
+
+    for _ in range(args.warmup):
+        step()
+    for h in handles:
+        h.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(args.steps):
+        results.append(step())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    uniq = sum(r.total_unique for batch in results for r in batch)
+    value = uniq / elapsed
+    solve_ms = sorted(r.seconds_solve * 1e3 for batch in results for r in batch)
+
+    def pct(p):
+        return solve_ms[min(len(solve_ms) - 1, int(p * len(solve_ms)))]
+
+    # kernel statistics from the library's HIP events
+    classes = {}
+    for k, name in enumerate(rei.KERNEL_CLASSES):
+        n = ms = units = 0
+        for h in handles:
+            a, b, c = h.kernel_stats(k)
+            n += a
+            ms += b
+            units += c
+        classes[name] = {"launches": n, "ms": ms, "units": units}
+    gen = {k: v for k, v in classes.items() if k.startswith("gen_")}
+    dom = max(gen, key=lambda k: gen[k]["ms"])
+    d = classes[dom]
+    avg_ms = d["ms"] / max(1, d["launches"])
+    bytes_per_launch = PROBE_BYTES * d["units"] / max(1, d["launches"])
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
+                "avg_launch_us": round(avg_ms * 1e3, 3), "launches": d["launches"],
+                "candidates_per_launch": round(d["units"] / max(1, d["launches"]), 1)}
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        threads = min(16, os.cpu_count() or 1)
+        t1 = time.perf_counter()
+        cu = 0
+        done = 0
+        while time.perf_counter() - t1 < args.cpu_seconds and done < 10 * len(insts):
+            it = insts[done % len(insts)]
+            r = oracle.solve(it.alphabet, it.pos, it.neg, it.costs, it.max_cost, 1 << 40,
+                             args.max_errors, threads)
+            cu += sum(r.unique)
+            done += 1
+        ct = time.perf_counter() - t1
+        cpu = {"value": round(cu / ct, 3), "unit": "languages/s", "cores": threads, "kind": "oracle",
+               "sample": f"{done} solves of the same instance list in order ({ct:.1f} s)"}
+
+    line = {
+        "metric": "unique languages enumerated/sec",
+        "value": round(value, 3),
+        "unit": "languages/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": desc, "instances_per_step": len(insts)},
+        "time_to_minimal_regex_ms": {"mean": round(sum(solve_ms) / len(solve_ms), 4),
+                                     "p50": round(pct(0.5), 4), "p99": round(pct(0.99), 4)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3), "units": v["units"]}
+                    for k, v in classes.items()},
+    }
+    print(json.dumps(line), flush=True)
+    for h in handles:
+        h.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,166 @@
+/* rei.h -- C ABI of the MI355X regular-expression-inference library.
+ *
+ * Search-based regular expression inference (Valizadeh & Berger, PLDI 2023):
+ * given positive examples P, negative examples N and a cost homomorphism,
+ * return a regular expression of minimal cost whose language contains every
+ * string of P and none of N (Sec. 3, Definition of specification, Definition
+ * of cost homomorphism, Algorithm 1).
+ *
+ * Languages are characteristic sequences over the infix closure ic(P u N),
+ * ordered shortlex (Definition of infix power series, Example 1); the search
+ * builds them bottom-up by cost (Lemma "build up", Algorithm 1) with the
+ * constructors ?, *, concatenation (guide-table fold, Algorithm 2) and union,
+ * keeps each language once (global uniqueness check) and stops at the first
+ * one that satisfies (P, N).
+ *
+ * Conventions
+ *   - Every function returns a status; no C++ exception crosses the ABI.
+ *   - Strings are NUL-terminated byte strings.  Inputs are copied; the caller
+ *     keeps ownership of everything it passes in.
+ *   - Results (strings, arrays) are owned by the instance and stay valid
+ *     until the next rei_solve on it or rei_destroy.
+ *   - An instance is used by one host thread at a time.  Different instances
+ *     may be solved concurrently on different streams.
+ *   - Device memory is allocated by the library (hipMalloc) on the device
+ *     that is current when rei_create is called, and freed by rei_destroy.
+ *
+ * Enumeration order inside a cost level (the paper leaves it open; this is
+ * the order the returned expression and per-level counts refer to):
+ *   level c_char: one candidate per alphabet character, in argument order;
+ *   level c > c_char: Q (r? over level c-c_question), S (r* over level
+ *   c-c_star), C (for left cost L = c_char, c_char+1, ... with right cost
+ *   R = c-c_concat-L: x in level L outer, y in level R inner: x.y), U (for
+ *   L <= R = c-c_union-L ascending: all pairs if L < R, pairs x before y if
+ *   L == R: x+y).  The enumeration index e of a candidate is its position in
+ *   that sequence.  New languages are appended to their level in order of
+ *   first occurrence; the answer is the first precise candidate.
+ */
+#ifndef REI_H
+#define REI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  REI_OK = 0,                /* a minimal precise expression was found          */
+  REI_NOT_FOUND = 1,         /* none of cost <= max_cost (Algorithm 1 output)   */
+  REI_OUT_OF_MEMORY = 2,     /* the language cache row cap was reached          */
+  REI_ERR_INVALID_ARG = -1,  /* null pointer, cost < 1, bad alphabet, ...       */
+  REI_ERR_INCONSISTENT = -2, /* a string is both in P and in N                  */
+  REI_ERR_BAD_CHAR = -3,     /* an example uses a character outside the alphabet*/
+  REI_ERR_TOO_LARGE = -4,    /* |ic(P u N)| > 2048 (more than 32 words per row) */
+  REI_ERR_DEVICE = -5,       /* a HIP call failed (message in rei_last_error)   */
+  REI_ERR_HOST_ALLOC = -6    /* host allocation failed                          */
+} rei_status;
+
+/* Cost homomorphism (c1..c5) = (character, ?, *, concatenation, union), all
+ * at least 1 (Definition of cost homomorphism).  cost(eps) = cost(empty set)
+ * = c_char. */
+typedef struct {
+  uint32_t c_char, c_question, c_star, c_concat, c_union;
+} rei_costs;
+
+typedef struct rei_instance rei_instance;
+
+/* Stage one specification.
+ *   alphabet    distinct bytes in 0x01..0x7f, none of ( ) + * ? ; its order
+ *               is the shortlex character order and the level-c_char order.
+ *   pos, neg    n_pos / n_neg NUL-terminated strings ("" is the empty word);
+ *               duplicates are ignored (a specification is a pair of sets).
+ *   costs       the cost homomorphism.
+ *   max_cost    largest cost searched, inclusive.
+ *   cache_bytes language-cache budget: at most floor(cache_bytes / (8W + 8))
+ *               languages are kept (W = 64-bit words per language, the
+ *               smallest power of two with 64W >= |ic|); beyond that the
+ *               search stops with REI_OUT_OF_MEMORY.  The dedup table and
+ *               per-chunk staging buffers are allocated beside it.
+ * Staging (infix closure, shortlex order, guide table, P/N masks) runs on the
+ * host and is copied to the device once.  On success *out owns the instance;
+ * on failure *out is NULL and the status says why. */
+rei_status rei_create(const char *alphabet, const char *const *pos, size_t n_pos,
+                      const char *const *neg, size_t n_neg, rei_costs costs,
+                      uint32_t max_cost, uint64_t cache_bytes, rei_instance **out);
+
+typedef struct {
+  rei_status status;         /* REI_OK, REI_NOT_FOUND or REI_OUT_OF_MEMORY      */
+  uint32_t cost;             /* minimal cost when REI_OK                        */
+  const char *regex;         /* UTF-8; "∅" / "ε" only for the trivial
+                                specifications P = {} and P = {eps}             */
+  uint32_t first_level;      /* = c_char                                        */
+  uint32_t n_levels;         /* levels first_level .. first_level+n_levels-1    */
+  const uint64_t *unique_per_level;     /* new languages per level; the last
+                                           level counts those up to the answer */
+  const uint64_t *candidates_per_level; /* candidates generated per level      */
+  uint64_t total_unique;     /* sum of unique_per_level                         */
+  uint32_t ic_size;          /* |ic(P u N)|                                     */
+  uint32_t cs_words;         /* W                                               */
+  double seconds_stage;      /* rei_create wall time                            */
+  double seconds_solve;      /* rei_solve wall time                             */
+} rei_result;
+
+/* Run the search on `hip_stream` (a hipStream_t; NULL = the null stream).
+ * Blocks until the search ends.  Repeated calls restart from scratch and give
+ * identical results. */
+rei_status rei_solve(rei_instance *inst, void *hip_stream, rei_result *out);
+
+/* Free the instance and its device memory.  NULL is ignored. */
+void rei_destroy(rei_instance *inst);
+
+const char *rei_status_str(rei_status s);
+/* Last error message of the instance (empty string if none). */
+const char *rei_last_error(const rei_instance *inst);
+/* Last error of a failed rei_create on this thread. */
+const char *rei_create_error(void);
+
+/* ---- inspection, valid after rei_solve (used by the tests) ---------------- */
+
+/* Word i of ic(P u N) in shortlex order, copied into buf (cap bytes). */
+rei_status rei_ic_word(const rei_instance *inst, uint32_t i, char *buf, size_t cap);
+/* Number of languages stored in level `cost`. */
+rei_status rei_level_size(const rei_instance *inst, uint32_t cost, uint64_t *out);
+/* The W words of row i of level `cost` (bit k of word k/64 = membership of
+ * ic word k), copied to host memory words_out[W]. */
+rei_status rei_row_bits(rei_instance *inst, uint32_t cost, uint64_t i, uint64_t *words_out);
+/* A minimal expression for row i of level `cost`, printed as the answer is. */
+rei_status rei_row_regex(rei_instance *inst, uint32_t cost, uint64_t i, char *buf, size_t cap);
+
+/* ---- tuning and measurement ------------------------------------------------ */
+
+/* Largest number of candidates processed per chunk (0 = default).  Results
+ * do not depend on it; tests vary it to check that. */
+rei_status rei_set_chunk(rei_instance *inst, uint64_t max_candidates);
+/* Misclassified examples allowed (REI with error, Sec. 7); 0 = precise. */
+rei_status rei_set_max_errors(rei_instance *inst, uint32_t max_errors);
+
+/* Kernel classes timed with HIP events when profiling is on. */
+typedef enum {
+  REI_K_GEN_CHAR = 0,
+  REI_K_GEN_QUESTION,
+  REI_K_GEN_STAR,
+  REI_K_GEN_CONCAT,
+  REI_K_GEN_UNION,
+  REI_K_INSERT,
+  REI_K_COMPACT,
+  REI_K_OTHER,
+  REI_K_COUNT
+} rei_kernel_class;
+
+/* Record a HIP event pair around every kernel launch of the next solves. */
+rei_status rei_set_profiling(rei_instance *inst, int enable);
+/* Launch count, total device milliseconds and work units (candidates for the
+ * generator classes, survivors for REI_K_INSERT) of one kernel class,
+ * accumulated over the solves since profiling was enabled. */
+rei_status rei_kernel_stats(const rei_instance *inst, rei_kernel_class k, uint64_t *launches,
+                            double *ms, uint64_t *units);
+/* Kernel symbol name of a class (for matching profiler output). */
+const char *rei_kernel_name(rei_kernel_class k);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REI_H */

@@ -1,0 +1,250 @@
+"""Python binding of the MI355X regular-expression-inference library.
+
+Argument marshalling only: every step of the search runs in ``librei.so``
+(host staging in C++, the search in HIP kernels).  The names follow the C ABI
+declared in ``include/rei.h``.  PyTorch, when present, only supplies the HIP
+stream the search is launched on.
+
+If the library has not been built this module raises on first use; there is
+no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librei.so")
+
+STATUS = {0: "OK", 1: "NOT_FOUND", 2: "OUT_OF_MEMORY", -1: "INVALID_ARG",
+          -2: "INCONSISTENT", -3: "BAD_CHAR", -4: "TOO_LARGE", -5: "DEVICE",
+          -6: "HOST_ALLOC"}
+
+KERNEL_CLASSES = ["gen_char", "gen_question", "gen_star", "gen_concat", "gen_union",
+                  "insert_survivors", "compact_winners", "other"]
+
+# exported symbols, as declared in include/rei.h
+EXPORTS = ["rei_create", "rei_solve", "rei_destroy", "rei_status_str", "rei_last_error",
+           "rei_create_error", "rei_ic_word", "rei_level_size", "rei_row_bits",
+           "rei_row_regex", "rei_set_chunk", "rei_set_max_errors", "rei_set_profiling",
+           "rei_kernel_stats", "rei_kernel_name"]
+
+
+class ReiError(RuntimeError):
+    def __init__(self, status: int, msg: str = ""):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.status_name = STATUS.get(status, str(status))
+
+
+class _Costs(ctypes.Structure):
+    _fields_ = [("c_char", ctypes.c_uint32), ("c_question", ctypes.c_uint32),
+                ("c_star", ctypes.c_uint32), ("c_concat", ctypes.c_uint32),
+                ("c_union", ctypes.c_uint32)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("cost", ctypes.c_uint32),
+                ("regex", ctypes.c_char_p), ("first_level", ctypes.c_uint32),
+                ("n_levels", ctypes.c_uint32),
+                ("unique_per_level", ctypes.POINTER(ctypes.c_uint64)),
+                ("candidates_per_level", ctypes.POINTER(ctypes.c_uint64)),
+                ("total_unique", ctypes.c_uint64), ("ic_size", ctypes.c_uint32),
+                ("cs_words", ctypes.c_uint32), ("seconds_stage", ctypes.c_double),
+                ("seconds_solve", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load ``librei.so`` (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "or python -m paper_2305_18575_amd._build")
+    # torch ships its own HIP runtime with the same soname; loading it first
+    # makes librei.so bind to that one, so the process has a single runtime
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, cp = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_char_p
+    strarr = ctypes.POINTER(ctypes.c_char_p)
+    lib.rei_create.restype = ctypes.c_int
+    lib.rei_create.argtypes = [cp, strarr, ctypes.c_size_t, strarr, ctypes.c_size_t, _Costs,
+                               u32, u64, ctypes.POINTER(vp)]
+    lib.rei_solve.restype = ctypes.c_int
+    lib.rei_solve.argtypes = [vp, vp, ctypes.POINTER(_Result)]
+    lib.rei_destroy.restype = None
+    lib.rei_destroy.argtypes = [vp]
+    lib.rei_status_str.restype = cp
+    lib.rei_status_str.argtypes = [ctypes.c_int]
+    lib.rei_last_error.restype = cp
+    lib.rei_last_error.argtypes = [vp]
+    lib.rei_create_error.restype = cp
+    lib.rei_create_error.argtypes = []
+    lib.rei_ic_word.restype = ctypes.c_int
+    lib.rei_ic_word.argtypes = [vp, u32, cp, ctypes.c_size_t]
+    lib.rei_level_size.restype = ctypes.c_int
+    lib.rei_level_size.argtypes = [vp, u32, ctypes.POINTER(u64)]
+    lib.rei_row_bits.restype = ctypes.c_int
+    lib.rei_row_bits.argtypes = [vp, u32, u64, ctypes.POINTER(u64)]
+    lib.rei_row_regex.restype = ctypes.c_int
+    lib.rei_row_regex.argtypes = [vp, u32, u64, cp, ctypes.c_size_t]
+    lib.rei_set_chunk.restype = ctypes.c_int
+    lib.rei_set_chunk.argtypes = [vp, u64]
+    lib.rei_set_max_errors.restype = ctypes.c_int
+    lib.rei_set_max_errors.argtypes = [vp, u32]
+    lib.rei_set_profiling.restype = ctypes.c_int
+    lib.rei_set_profiling.argtypes = [vp, ctypes.c_int]
+    lib.rei_kernel_stats.restype = ctypes.c_int
+    lib.rei_kernel_stats.argtypes = [vp, ctypes.c_int, ctypes.POINTER(u64),
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64)]
+    lib.rei_kernel_name.restype = cp
+    lib.rei_kernel_name.argtypes = [ctypes.c_int]
+    _lib = lib
+    return lib
+
+
+def _strarr(items: Sequence[str]):
+    arr = (ctypes.c_char_p * max(1, len(items)))()
+    for i, s in enumerate(items):
+        arr[i] = s.encode("latin-1")
+    return arr
+
+
+def current_stream_handle() -> Optional[int]:
+    """hipStream_t of torch's current stream (None = null stream)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:  # torch absent or not built with HIP
+        pass
+    return None
+
+
+@dataclass
+class Result:
+    status: str
+    cost: int
+    regex: str
+    first_level: int
+    unique: List[int]          # per level, first_level .. first_level + n_levels - 1
+    candidates: List[int]
+    total_unique: int
+    ic_size: int
+    cs_words: int
+    seconds_stage: float
+    seconds_solve: float
+
+    def unique_at(self, cost: int) -> int:
+        i = cost - self.first_level
+        return self.unique[i] if 0 <= i < len(self.unique) else 0
+
+    def candidates_at(self, cost: int) -> int:
+        i = cost - self.first_level
+        return self.candidates[i] if 0 <= i < len(self.candidates) else 0
+
+
+class Instance:
+    """One staged specification (``rei_create``); ``solve`` runs ``rei_solve``."""
+
+    def __init__(self, alphabet: str, pos: Sequence[str], neg: Sequence[str],
+                 costs=(1, 1, 1, 1, 1), max_cost: int = 30, cache_bytes: int = 1 << 30):
+        lib = load_library()
+        self._lib = lib
+        self._h = None
+        h = ctypes.c_void_p()
+        st = lib.rei_create(alphabet.encode("latin-1"), _strarr(pos), len(pos),
+                            _strarr(neg), len(neg), _Costs(*costs), int(max_cost),
+                            int(cache_bytes), ctypes.byref(h))
+        if st != 0:
+            raise ReiError(st, lib.rei_create_error().decode())
+        self._h = h
+        self.costs = tuple(costs)
+        self.max_cost = int(max_cost)
+
+    def close(self):
+        if self._h:
+            self._lib.rei_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            raise ReiError(st, self._lib.rei_last_error(self._h).decode())
+
+    def solve(self, stream: Optional[int] = -1) -> Result:
+        """Run the search on ``stream`` (-1 = torch's current stream)."""
+        if stream == -1:
+            stream = current_stream_handle()
+        r = _Result()
+        self._check(self._lib.rei_solve(self._h, ctypes.c_void_p(stream or 0), ctypes.byref(r)))
+        n = r.n_levels
+        return Result(STATUS[r.status], r.cost, (r.regex or b"").decode("utf-8"), r.first_level,
+                      [r.unique_per_level[i] for i in range(n)],
+                      [r.candidates_per_level[i] for i in range(n)],
+                      r.total_unique, r.ic_size, r.cs_words, r.seconds_stage, r.seconds_solve)
+
+    # ---- tuning / measurement ----
+    def set_chunk(self, max_candidates: int):
+        self._check(self._lib.rei_set_chunk(self._h, int(max_candidates)))
+
+    def set_max_errors(self, k: int):
+        self._check(self._lib.rei_set_max_errors(self._h, int(k)))
+
+    def set_profiling(self, on: bool):
+        self._check(self._lib.rei_set_profiling(self._h, 1 if on else 0))
+
+    def kernel_stats(self, k: int):
+        n, u = ctypes.c_uint64(), ctypes.c_uint64()
+        ms = ctypes.c_double()
+        self._check(self._lib.rei_kernel_stats(self._h, int(k), ctypes.byref(n), ctypes.byref(ms),
+                                               ctypes.byref(u)))
+        return n.value, ms.value, u.value
+
+    # ---- inspection ----
+    def ic_word(self, i: int) -> str:
+        buf = ctypes.create_string_buffer(4096)
+        self._check(self._lib.rei_ic_word(self._h, int(i), buf, 4096))
+        return buf.value.decode("latin-1")
+
+    def level_size(self, cost: int) -> int:
+        v = ctypes.c_uint64()
+        self._check(self._lib.rei_level_size(self._h, int(cost), ctypes.byref(v)))
+        return v.value
+
+    def row_bits(self, cost: int, i: int, words: int) -> List[int]:
+        buf = (ctypes.c_uint64 * words)()
+        self._check(self._lib.rei_row_bits(self._h, int(cost), int(i), buf))
+        return list(buf)
+
+    def row_regex(self, cost: int, i: int) -> str:
+        buf = ctypes.create_string_buffer(1 << 16)
+        self._check(self._lib.rei_row_regex(self._h, int(cost), int(i), buf, 1 << 16))
+        return buf.value.decode("utf-8")
+
+
+def solve(alphabet, pos, neg, costs=(1, 1, 1, 1, 1), max_cost=30, cache_bytes=1 << 30,
+          max_errors=0, chunk=0, stream=-1) -> Result:
+    inst = Instance(alphabet, pos, neg, costs, max_cost, cache_bytes)
+    try:
+        if max_errors:
+            inst.set_max_errors(max_errors)
+        if chunk:
+            inst.set_chunk(chunk)
+        return inst.solve(stream)
+    finally:
+        inst.close()

@@ -1,0 +1,122 @@
+// Internal declarations of the REI library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rei.h"
+
+namespace rei {
+
+constexpr int kMaxWords = 32;          // 2048 words of ic
+constexpr uint32_t kMaxIc = 64 * kMaxWords;
+
+enum Op : int { OP_CHAR = 0, OP_QUESTION = 1, OP_STAR = 2, OP_CONCAT = 3, OP_UNION = 4 };
+
+// Host-side staging of one specification (infix closure, order, guide table).
+struct Staged {
+  std::string sigma;
+  std::vector<std::string> P, N;       // deduplicated
+  std::vector<std::string> ic;         // shortlex order, ic[0] = empty word
+  uint32_t n = 0;                      // |ic|
+  int W = 1;                           // words per language (power of two)
+  // Guide table in CSR form: for word w, entries gt_off[w] .. gt_off[w+1]-1
+  // are the cuts w = u v, cut position 0..|w|, packed (index(u) << 16) | index(v).
+  std::vector<uint32_t> gt_off, gt_pair;
+  // words of each length: len_off[l] .. len_off[l+1]-1
+  std::vector<uint32_t> len_off;
+  uint32_t max_len = 0;
+  std::vector<uint64_t> pmask, nmask;  // W words each
+  std::vector<int32_t> char_index;     // per alphabet char: its ic index or -1
+};
+
+// Validates and stages; returns REI_OK or an error status with *err set.
+rei_status stage(const char* alphabet, const char* const* pos, size_t n_pos,
+                 const char* const* neg, size_t n_neg, Staged* out, std::string* err);
+
+// ---- slot encoding of the dedup table ------------------------------------
+// EMPTY      all ones
+// cached row bit63 = 0 | fingerprint (24 bits, 62..39) | row (39 bits)
+// new entry  bit63 = 1 | chunk-relative enumeration index (31 bits) | survivor id (32 bits)
+constexpr uint64_t kEmpty = ~0ull;
+constexpr uint64_t kRowBits = 39;
+constexpr uint64_t kRowMask = (1ull << kRowBits) - 1;
+constexpr uint64_t kNewFlag = 1ull << 63;
+constexpr uint64_t kMaxChunk = (1ull << 28);  // chunk-relative indices stay far below 2^31 - 1
+
+// Per-chunk control block in device memory.
+struct Ctrl {
+  uint32_t n_surv;          // survivors appended by the generator
+  uint32_t answer_e;        // chunk-relative index of the first precise survivor (or ~0)
+  uint32_t answer_rank;     // rank of the answer among the chunk's winners
+  uint32_t winners;         // winners in the chunk
+  uint32_t overflow_e;      // chunk-relative index of the winner that does not fit
+  uint32_t pad[3];
+};
+
+// Arguments shared by all generator kernels.
+struct GenArgs {
+  // language cache
+  const uint64_t* rows;       // all rows, W words each
+  // dedup table
+  const uint64_t* slots;
+  uint64_t slot_mask;
+  // survivors
+  uint64_t* skey;             // survivor keys, W words each
+  uint32_t* se;               // survivor chunk-relative index
+  Ctrl* ctrl;
+  // precision
+  const uint64_t* pmask;
+  const uint64_t* nmask;
+  uint32_t max_err;
+  // guide table
+  const uint32_t* gt_off;
+  const uint32_t* gt_pair;
+  const uint32_t* len_off;
+  uint32_t max_len;
+  uint32_t n;                 // |ic|
+  uint32_t n_pairs;           // guide-table entries
+  // block / chunk
+  uint64_t e0, e1;            // chunk range inside the block
+  uint64_t lstart, lcount;    // left operand level: first row, number of rows
+  uint64_t rstart, rcount;    // right operand level
+  const int32_t* char_index;  // base level only
+};
+
+struct ChunkArgs {
+  const uint64_t* rows;
+  uint64_t* rows_w;
+  uint64_t* aux;
+  uint64_t* slots;
+  uint64_t slot_mask;
+  uint64_t* skey;
+  uint32_t* se;
+  uint64_t* spos;             // slot of each survivor after insertion
+  uint32_t* bitmap;           // one bit per chunk-relative index: winner
+  uint32_t* word_prefix;      // exclusive prefix of popcounts
+  uint32_t* block_sums;
+  uint32_t n_bitmap_words;
+  Ctrl* ctrl;
+  uint64_t chunk_e0;          // level enumeration index of chunk-relative 0
+  uint64_t row_base;          // first free row (global)
+  uint64_t room;              // rows that may still be stored
+};
+
+// Kernel launchers (kernels.hip).  Every launcher returns the hipError_t of
+// the launch.
+hipError_t launch_fill(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_rehash(int W, const uint64_t* rows, uint64_t nrows, uint64_t* slots,
+                         uint64_t slot_mask, hipStream_t s);
+hipError_t launch_gen(int W, int op, const GenArgs& a, bool same_level, hipStream_t s);
+hipError_t launch_insert(int W, const ChunkArgs& a, uint32_t max_surv, hipStream_t s);
+hipError_t launch_mark(const ChunkArgs& a, uint32_t max_surv, hipStream_t s);
+hipError_t launch_scan(const ChunkArgs& a, hipStream_t s);
+hipError_t launch_compact(int W, const ChunkArgs& a, uint32_t max_surv, hipStream_t s);
+hipError_t launch_ctrl_reset(Ctrl* c, uint32_t* bitmap, uint32_t n_words, hipStream_t s);
+
+const char* gen_kernel_name(int op);
+
+}  // namespace rei

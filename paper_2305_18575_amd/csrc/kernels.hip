@@ -1,0 +1,651 @@
+// Device kernels of the REI search for CDNA4 (gfx950), wave64.
+//
+// One chunk of candidates (a contiguous range of enumeration indices inside
+// one constructor block of a cost level) goes through:
+//   gen_*     build each candidate's language (characteristic sequence over
+//             ic, W 64-bit words) and probe the dedup table read-only; a
+//             candidate whose language is not yet stored is a survivor and
+//             is appended with its chunk-relative index; precise survivors
+//             lower ctrl->answer_e (Algorithm 2: uniqueness, then precision);
+//   insert    survivors claim table slots; equal languages meet in one slot
+//             and keep the smallest enumeration index (deterministic
+//             atomicMin), so the first occurrence wins;
+//   mark      winners set their bit in a per-chunk bitmap indexed by
+//             enumeration index;
+//   scan      exclusive prefix of the bitmap popcounts = rank of each winner
+//             in enumeration order;
+//   compact   winners before the answer are appended to the level in rank
+//             order ("new languages go to temporary storage, only unique
+//             ones are copied into the cache", Sec. 3, GPU language cache).
+#include <algorithm>
+
+#include "internal.h"
+
+namespace rei {
+
+namespace {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  x ^= x >> 33;
+  x *= 0xff51afd7ed558ccdull;
+  x ^= x >> 33;
+  x *= 0xc4ceb9fe1a85ec53ull;
+  x ^= x >> 33;
+  return x;
+}
+
+template <int W>
+__device__ __forceinline__ uint64_t hash_key(const uint64_t (&k)[W]) {
+  uint64_t h = mix64(k[0] ^ 0x9e3779b97f4a7c15ull);
+#pragma unroll
+  for (int i = 1; i < W; ++i) h = mix64(h ^ k[i]);
+  return h;
+}
+
+__device__ __forceinline__ uint64_t fingerprint(uint64_t h) { return (h >> 40) & 0xFFFFFFull; }
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  lo = __shfl_xor((int)lo, m, kWave);
+  hi = __shfl_xor((int)hi, m, kWave);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// 64x64 bit-matrix transpose across a wave: on entry lane r holds row r, on
+// exit lane c holds column c (bit r of the result = bit c of row r).  Each
+// stage swaps one bit of the row index with the same bit of the column index.
+__device__ __forceinline__ uint64_t transpose64(uint64_t a) {
+  const uint32_t lane = lane_id();
+  const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                             0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int j = 32 >> s;
+    const uint64_t m = masks[s];
+    uint64_t b = shfl_xor64(a, j);
+    a = (lane & j) ? ((a & ~m) | ((b >> j) & m)) : ((a & m) | ((b & m) << j));
+  }
+  return a;
+}
+
+// Probe the table (read-only in the generator kernels: it holds stored rows
+// only) and append survivors.  Must be called by every lane of the wave.
+template <int W>
+__device__ __forceinline__ void filter_emit(const GenArgs& a, bool valid, bool known_dup,
+                                            const uint64_t (&key)[W], uint32_t e_rel) {
+  bool surv = false;
+  if (valid && !known_dup) {
+    const uint64_t h = hash_key<W>(key);
+    const uint64_t fp = fingerprint(h);
+    uint64_t pos = h & a.slot_mask;
+    surv = true;
+    for (;;) {
+      const uint64_t v = a.slots[pos];
+      if (v == kEmpty) break;
+      if (((v >> kRowBits) & 0xFFFFFFull) == fp) {
+        const uint64_t* r = a.rows + (v & kRowMask) * W;
+        bool eq = true;
+#pragma unroll
+        for (int k = 0; k < W; ++k) eq = eq && (r[k] == key[k]);
+        if (eq) {
+          surv = false;
+          break;
+        }
+      }
+      pos = (pos + 1) & a.slot_mask;
+    }
+  }
+  const uint64_t m = __ballot(surv);
+  if (m == 0) return;
+  const uint32_t lane = lane_id();
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  uint32_t base = 0;
+  if ((int)lane == leader) base = atomicAdd(&a.ctrl->n_surv, (uint32_t)__popcll(m));
+  base = __shfl((int)base, leader, kWave);
+  if (surv) {
+    const uint32_t sid = base + (uint32_t)__popcll(m & ((1ull << lane) - 1));
+    uint64_t* dst = a.skey + (uint64_t)sid * W;
+    int bad = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      dst[k] = key[k];
+      bad += __popcll(a.pmask[k] & ~key[k]) + __popcll(a.nmask[k] & key[k]);
+    }
+    a.se[sid] = e_rel;
+    if (bad <= (int)a.max_err) atomicMin(&a.ctrl->answer_e, e_rel);
+  }
+}
+
+// ---- generators -----------------------------------------------------------
+
+template <int W>
+__global__ __launch_bounds__(256) void gen_char(GenArgs a) {
+  const uint64_t e = a.e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = e < a.e1;
+  uint64_t key[W];
+  const int idx = valid ? a.char_index[e] : -1;
+#pragma unroll
+  for (int k = 0; k < W; ++k) key[k] = (idx >= 0 && (idx >> 6) == k) ? (1ull << (idx & 63)) : 0ull;
+  filter_emit<W>(a, valid, false, key, (uint32_t)(e - a.e0));
+}
+
+// r? = eps + r; eps is word 0 of ic (shortlex puts the empty word first).
+template <int W>
+__global__ __launch_bounds__(256) void gen_question(GenArgs a) {
+  const uint64_t e = a.e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = e < a.e1;
+  uint64_t key[W];
+  const uint64_t* src = a.rows + (a.lstart + (valid ? e : 0)) * W;
+#pragma unroll
+  for (int k = 0; k < W; ++k) key[k] = valid ? src[k] : 0ull;
+  const bool dup = (key[0] & 1ull) != 0;  // already contains eps: r? = r
+  key[0] |= 1ull;
+  filter_emit<W>(a, valid, dup, key, (uint32_t)(e - a.e0));
+}
+
+// r* for 64 rows per workgroup, bit-sliced: Xt[w] / Yt[w] hold bit t = row t's
+// membership of word w.  Y(eps) = 1 and, by increasing length,
+// Y(w) = OR over cuts w = u v with u non-empty of X(u) & Y(v) (v is shorter).
+template <int W>
+__global__ __launch_bounds__(256) void gen_star(GenArgs a) {
+  __shared__ uint64_t Xt[64 * W];
+  __shared__ uint64_t Yt[64 * W];
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t base = a.e0 + (uint64_t)blockIdx.x * 64;
+  for (int k = wave; k < W; k += 4) {
+    const uint64_t e = base + lane;
+    const uint64_t v = (e < a.e1) ? a.rows[(a.lstart + e) * W + k] : 0ull;
+    Xt[64 * k + lane] = transpose64(v);
+  }
+  for (uint32_t w = threadIdx.x; w < 64u * W; w += 256) Yt[w] = (w == 0) ? ~0ull : 0ull;
+  __syncthreads();
+  for (uint32_t l = 1; l <= a.max_len; ++l) {
+    const uint32_t lo = a.len_off[l], hi = a.len_off[l + 1];
+    for (uint32_t w = lo + threadIdx.x; w < hi; w += 256) {
+      uint64_t acc = 0;
+      const uint32_t q1 = a.gt_off[w + 1];
+      for (uint32_t q = a.gt_off[w] + 1; q < q1; ++q) {  // cut 0 has u = eps
+        const uint32_t p = a.gt_pair[q];
+        acc |= Xt[p >> 16] & Yt[p & 0xFFFFu];
+      }
+      Yt[w] = acc;
+    }
+    __syncthreads();
+  }
+  if (wave == 0) {
+    uint64_t key[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) key[k] = transpose64(Yt[64 * k + lane]);
+    const uint64_t e = base + lane;
+    filter_emit<W>(a, e < a.e1, false, key, (uint32_t)(e - a.e0));
+  }
+}
+
+// x.y, bit-sliced over 64 right operands.  A workgroup owns YT tiles of 64
+// rows of the right level (transposed into LDS: Yt[tile][w], bit t = row t
+// contains word w) and a group of left rows.  For a left row x, lane l of a
+// wave owns word w = 64k + l of output word k; the cuts (u, v) of w with u in
+// x select which Yt[v] are or-ed:  out_t(w) = OR_{(u,v) cut of w, x(u)=1} y_t(v)
+// (Algorithm 2, the fold over the guide table, done for 64 candidates at once).
+// A wave transpose then gives lane t the W words of candidate (x, y_t).
+constexpr int kConcatYT = 8;
+
+// kShort: every word has at most 32 cuts (length <= 31), so the cuts whose
+// prefix is in x fit one 32-bit mask per output word; otherwise the prefix
+// bit is tested inside the fold.
+template <int W, bool kShort>
+__global__ __launch_bounds__(256) void gen_concat(GenArgs a, uint32_t yt_per_wg, uint32_t xi_per_wg,
+                                                  uint64_t i_lo, uint64_t i_hi, uint32_t gt_lds,
+                                                  uint32_t n_tile_groups) {
+  extern __shared__ uint64_t lds[];
+  uint64_t* Yt = lds;                                        // [yt_per_wg][64W]
+  uint64_t* Xs = Yt + (size_t)yt_per_wg * 64 * W;            // [xi_per_wg][W]
+  uint32_t* G = (uint32_t*)(Xs + (size_t)xi_per_wg * W);     // guide pairs (if gt_lds)
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t nR = a.rcount;
+  const uint64_t nT = (nR + 63) / 64;
+  // flat grid: workgroup -> (group of right tiles, group of left rows)
+  const uint64_t t0 = (uint64_t)(blockIdx.x % n_tile_groups) * yt_per_wg;
+  const uint32_t nt = (uint32_t)min<uint64_t>(yt_per_wg, nT - t0);
+  const uint64_t x0 = i_lo + (uint64_t)(blockIdx.x / n_tile_groups) * xi_per_wg;
+  const uint32_t nx = (uint32_t)min<uint64_t>(xi_per_wg, i_hi + 1 - x0);
+
+  // stage right tiles (transposed), left rows and guide table
+  for (uint32_t job = wave; job < nt * W; job += 4) {
+    const uint32_t tq = job / W, k = job % W;
+    const uint64_t j = (t0 + tq) * 64 + lane;
+    const uint64_t v = (j < nR) ? a.rows[(a.rstart + j) * W + k] : 0ull;
+    Yt[(size_t)tq * 64 * W + 64 * k + lane] = transpose64(v);
+  }
+  for (uint32_t q = threadIdx.x; q < nx * W; q += 256)
+    Xs[q] = a.rows[(a.lstart + x0 + q / W) * W + q % W];
+  if (gt_lds)
+    for (uint32_t q = threadIdx.x; q < a.n_pairs; q += 256) G[q] = a.gt_pair[q];
+  __syncthreads();
+  const uint32_t* gp = gt_lds ? G : a.gt_pair;
+
+  // cut ranges of this lane's words
+  uint32_t off[W], cnt[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    const uint32_t w = 64u * k + lane;
+    off[k] = (w < a.n) ? a.gt_off[w] : 0u;
+    cnt[k] = (w < a.n) ? a.gt_off[w + 1] - off[k] : 0u;
+  }
+
+  for (uint32_t xi = wave; xi < nx; xi += 4) {
+    const uint64_t i = x0 + xi;
+    const uint64_t* xr = Xs + (size_t)xi * W;
+    // bit q of m[k]: x contains the prefix of cut q of word 64k+lane
+    uint32_t m[W];
+    if constexpr (kShort) {
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        uint32_t mm = 0;
+        for (uint32_t q = 0; q < cnt[k]; ++q) {
+          const uint32_t u = gp[off[k] + q] >> 16;
+          mm |= (uint32_t)((xr[u >> 6] >> (u & 63)) & 1ull) << q;
+        }
+        m[k] = mm;
+      }
+    }
+    for (uint32_t tq = 0; tq < nt; ++tq) {
+      const uint64_t* Y = Yt + (size_t)tq * 64 * W;
+      uint64_t key[W];
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        uint64_t acc = 0;
+        if constexpr (kShort) {
+          for (uint32_t mm = m[k]; mm; mm &= mm - 1) {
+            const uint32_t q = __ffs(mm) - 1;
+            acc |= Y[gp[off[k] + q] & 0xFFFFu];
+          }
+        } else {
+          for (uint32_t q = 0; q < cnt[k]; ++q) {
+            const uint32_t p = gp[off[k] + q];
+            const uint32_t u = p >> 16;
+            if ((xr[u >> 6] >> (u & 63)) & 1ull) acc |= Y[p & 0xFFFFu];
+          }
+        }
+        key[k] = transpose64(acc);
+      }
+      const uint64_t j = (t0 + tq) * 64 + lane;
+      const uint64_t e = i * nR + j;
+      const bool valid = (j < nR) && (e >= a.e0) && (e < a.e1);
+      filter_emit<W>(a, valid, false, key, (uint32_t)(e - a.e0));
+    }
+  }
+}
+
+// Pairs (i, j) with i < j of an n-row level, row-major: index of the first
+// pair of row i is i*n - i*(i+1)/2.
+__device__ __forceinline__ void tri_decode(uint64_t e, uint64_t n, uint64_t* pi, uint64_t* pj) {
+  const double b = 2.0 * (double)n - 1.0;
+  double d = b * b - 8.0 * (double)e;
+  if (d < 0) d = 0;
+  int64_t i = (int64_t)((b - sqrt(d)) * 0.5);
+  if (i < 0) i = 0;
+  auto first = [n](int64_t r) -> uint64_t { return (uint64_t)r * n - (uint64_t)r * (uint64_t)(r + 1) / 2; };
+  while (i > 0 && first(i) > e) --i;
+  while ((uint64_t)(i + 1) < n && first(i + 1) <= e) ++i;
+  *pi = (uint64_t)i;
+  *pj = (uint64_t)i + 1 + (e - first(i));
+}
+
+template <int W, bool kSame>
+__global__ __launch_bounds__(256) void gen_union(GenArgs a) {
+  const uint64_t e = a.e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = e < a.e1;
+  uint64_t i = 0, j = 0;
+  if (valid) {
+    if (kSame) {
+      tri_decode(e, a.lcount, &i, &j);
+    } else {
+      i = e / a.rcount;
+      j = e - i * a.rcount;
+    }
+  }
+  const uint64_t* x = a.rows + (a.lstart + i) * W;
+  const uint64_t* y = a.rows + (a.rstart + j) * W;
+  uint64_t key[W];
+  bool eqx = true, eqy = true;
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    const uint64_t xv = valid ? x[k] : 0ull, yv = valid ? y[k] : 0ull;
+    key[k] = xv | yv;
+    eqx = eqx && key[k] == xv;
+    eqy = eqy && key[k] == yv;
+  }
+  // x+y equals x or y (one contains the other): that language is stored
+  filter_emit<W>(a, valid, eqx || eqy, key, (uint32_t)(e - a.e0));
+}
+
+// ---- chunk pipeline ------------------------------------------------------
+
+__global__ void fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void ctrl_reset(Ctrl* c, uint32_t* bitmap, uint32_t n_words) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    c->n_surv = 0;
+    c->answer_e = ~0u;
+    c->answer_rank = ~0u;
+    c->winners = 0;
+    c->overflow_e = ~0u;
+  }
+  for (uint32_t i = t; i < n_words; i += gridDim.x * blockDim.x) bitmap[i] = 0;
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void rehash_rows(const uint64_t* rows, uint64_t nrows, uint64_t* slots,
+                                                   uint64_t mask) {
+  for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows;
+       r += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t key[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) key[k] = rows[r * W + k];
+    const uint64_t h = hash_key<W>(key);
+    const uint64_t mine = (fingerprint(h) << kRowBits) | r;
+    uint64_t pos = h & mask;
+    while (atomicCAS((unsigned long long*)&slots[pos], (unsigned long long)kEmpty,
+                     (unsigned long long)mine) != kEmpty)
+      pos = (pos + 1) & mask;
+  }
+}
+
+template <int W>
+__device__ __forceinline__ bool key_eq(const uint64_t* p, const uint64_t (&key)[W]) {
+  bool eq = true;
+#pragma unroll
+  for (int k = 0; k < W; ++k) eq = eq && p[k] == key[k];
+  return eq;
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void insert_survivors(ChunkArgs a) {
+  const uint32_t ns = a.ctrl->n_surv;
+  for (uint32_t sid = blockIdx.x * blockDim.x + threadIdx.x; sid < ns; sid += gridDim.x * blockDim.x) {
+    uint64_t key[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) key[k] = a.skey[(uint64_t)sid * W + k];
+    const uint64_t h = hash_key<W>(key);
+    const uint64_t fp = fingerprint(h);
+    const uint64_t mine = kNewFlag | ((uint64_t)a.se[sid] << 32) | sid;
+    uint64_t pos = h & a.slot_mask;
+    for (;;) {
+      uint64_t v = a.slots[pos];
+      if (v == kEmpty) {
+        v = atomicCAS((unsigned long long*)&a.slots[pos], (unsigned long long)kEmpty,
+                      (unsigned long long)mine);
+        if (v == kEmpty) break;  // claimed
+      }
+      if (v & kNewFlag) {
+        // another survivor owns the slot; its key never changes
+        if (key_eq<W>(a.skey + (uint64_t)(uint32_t)v * W, key)) {
+          atomicMin((unsigned long long*)&a.slots[pos], (unsigned long long)mine);
+          break;
+        }
+      } else if (((v >> kRowBits) & 0xFFFFFFull) == fp && key_eq<W>(a.rows + (v & kRowMask) * W, key)) {
+        break;  // stored already (the generator filters these; kept for safety)
+      }
+      pos = (pos + 1) & a.slot_mask;
+    }
+    a.spos[sid] = pos;
+  }
+}
+
+__global__ __launch_bounds__(256) void mark_winners(ChunkArgs a) {
+  const uint32_t ns = a.ctrl->n_surv;
+  for (uint32_t sid = blockIdx.x * blockDim.x + threadIdx.x; sid < ns; sid += gridDim.x * blockDim.x) {
+    const uint32_t e = a.se[sid];
+    const uint64_t mine = kNewFlag | ((uint64_t)e << 32) | sid;
+    if (a.slots[a.spos[sid]] == mine) atomicOr(&a.bitmap[e >> 5], 1u << (e & 31));
+  }
+}
+
+constexpr uint32_t kScanBlock = 1024;  // bitmap words per scan block (256 threads x 4)
+
+__global__ __launch_bounds__(256) void scan_reduce(ChunkArgs a) {
+  __shared__ uint32_t red[256];
+  const uint32_t b = blockIdx.x, t = threadIdx.x;
+  uint32_t s = 0;
+  for (uint32_t q = 0; q < 4; ++q) {
+    const uint32_t w = b * kScanBlock + t * 4 + q;
+    if (w < a.n_bitmap_words) s += __popc(a.bitmap[w]);
+  }
+  red[t] = s;
+  __syncthreads();
+  for (uint32_t st = 128; st > 0; st >>= 1) {
+    if (t < st) red[t] += red[t + st];
+    __syncthreads();
+  }
+  if (t == 0) a.block_sums[b] = red[0];
+}
+
+// single workgroup: exclusive scan of the block sums, total -> ctrl->winners
+__global__ __launch_bounds__(1024) void scan_top(ChunkArgs a, uint32_t nb) {
+  __shared__ uint32_t part[1024];
+  const uint32_t t = threadIdx.x;
+  const uint32_t per = (nb + 1023) / 1024;
+  const uint32_t lo = t * per, hi = min(nb, lo + per);
+  uint32_t s = 0;
+  for (uint32_t i = lo; i < hi; ++i) s += a.block_sums[i];
+  part[t] = s;
+  __syncthreads();
+  for (uint32_t st = 1; st < 1024; st <<= 1) {
+    const uint32_t v = (t >= st) ? part[t - st] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - s;  // exclusive
+  for (uint32_t i = lo; i < hi; ++i) {
+    const uint32_t v = a.block_sums[i];
+    a.block_sums[i] = run;
+    run += v;
+  }
+  if (t == 1023) a.ctrl->winners = part[1023];
+}
+
+__global__ __launch_bounds__(256) void scan_down(ChunkArgs a) {
+  __shared__ uint32_t part[256];
+  const uint32_t b = blockIdx.x, t = threadIdx.x;
+  uint32_t c[4], s = 0;
+  for (uint32_t q = 0; q < 4; ++q) {
+    const uint32_t w = b * kScanBlock + t * 4 + q;
+    c[q] = (w < a.n_bitmap_words) ? __popc(a.bitmap[w]) : 0u;
+    s += c[q];
+  }
+  part[t] = s;
+  __syncthreads();
+  for (uint32_t st = 1; st < 256; st <<= 1) {
+    const uint32_t v = (t >= st) ? part[t - st] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = a.block_sums[b] + part[t] - s;
+  for (uint32_t q = 0; q < 4; ++q) {
+    const uint32_t w = b * kScanBlock + t * 4 + q;
+    if (w < a.n_bitmap_words) a.word_prefix[w] = run;
+    run += c[q];
+  }
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void compact_winners(ChunkArgs a) {
+  const uint32_t ns = a.ctrl->n_surv;
+  const uint32_t ans = a.ctrl->answer_e;
+  for (uint32_t sid = blockIdx.x * blockDim.x + threadIdx.x; sid < ns; sid += gridDim.x * blockDim.x) {
+    const uint32_t e = a.se[sid];
+    const uint32_t word = a.bitmap[e >> 5];
+    if (!((word >> (e & 31)) & 1u)) continue;
+    const uint32_t mine = (1u << (e & 31));
+    // only winners reach here: the bit of e is set iff sid owns its slot
+    const uint64_t slot = a.slots[a.spos[sid]];
+    if (slot != (kNewFlag | ((uint64_t)e << 32) | sid)) continue;
+    const uint32_t rank = a.word_prefix[e >> 5] + __popc(word & (mine - 1));
+    if (e == ans) a.ctrl->answer_rank = rank;
+    if (ans != ~0u && e >= ans) continue;  // the answer and later ones are not stored
+    if (rank < a.room) {
+      const uint64_t row = a.row_base + rank;
+      uint64_t key[W];
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        key[k] = a.skey[(uint64_t)sid * W + k];
+        a.rows_w[row * W + k] = key[k];
+      }
+      a.aux[row] = a.chunk_e0 + e;
+      a.slots[a.spos[sid]] = (fingerprint(hash_key<W>(key)) << kRowBits) | row;
+    } else if (rank == a.room) {
+      a.ctrl->overflow_e = e;
+    }
+  }
+}
+
+inline uint32_t grid_for(uint64_t n, uint32_t block, uint32_t cap = 0x7fffffffu) {
+  uint64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (uint32_t)g;
+}
+
+template <int W>
+hipError_t launch_concat_w(const GenArgs& a, hipStream_t s) {
+  const uint64_t nR = a.rcount;
+  const uint64_t i_lo = a.e0 / nR, i_hi = (a.e1 - 1) / nR;
+  const uint64_t rowsx = i_hi - i_lo + 1;
+  const uint64_t nT = (nR + 63) / 64;
+  // right tiles in LDS: at most 32 KB
+  const uint32_t yt_cap = (uint32_t)std::max(1, std::min(kConcatYT, 32768 / (512 * W)));
+  uint32_t yt = (uint32_t)std::min<uint64_t>(yt_cap, nT);
+  uint32_t xi = 16;
+  auto wgs = [&](uint32_t y, uint32_t x) { return ((nT + y - 1) / y) * ((rowsx + x - 1) / x); };
+  while (xi > 4 && wgs(yt, xi) < 2048) xi /= 2;
+  while (yt > 1 && wgs(yt, xi) < 2048) yt /= 2;
+  size_t lds = (size_t)yt * 64 * W * 8 + (size_t)xi * W * 8;
+  const uint32_t gt_lds = (lds + (size_t)a.n_pairs * 4 <= 60 * 1024) ? 1u : 0u;
+  if (gt_lds) lds += (size_t)a.n_pairs * 4;
+  const uint64_t gx = (nT + yt - 1) / yt, gy = (rowsx + xi - 1) / xi;
+  if (gx * gy > 0x7fffffffull) return hipErrorInvalidConfiguration;
+  const dim3 grid((uint32_t)(gx * gy));
+  if (a.max_len < 32)
+    hipLaunchKernelGGL((gen_concat<W, true>), grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi, gt_lds,
+                       (uint32_t)gx);
+  else
+    hipLaunchKernelGGL((gen_concat<W, false>), grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi, gt_lds,
+                       (uint32_t)gx);
+  return hipGetLastError();
+}
+
+template <int W>
+hipError_t launch_gen_w(int op, const GenArgs& a, bool same_level, hipStream_t s) {
+  const uint64_t cnt = a.e1 - a.e0;
+  switch (op) {
+    case OP_CHAR:
+      hipLaunchKernelGGL(gen_char<W>, dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
+      break;
+    case OP_QUESTION:
+      hipLaunchKernelGGL(gen_question<W>, dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
+      break;
+    case OP_STAR:
+      hipLaunchKernelGGL(gen_star<W>, dim3(grid_for(cnt, 64)), dim3(256), 0, s, a);
+      break;
+    case OP_CONCAT:
+      return launch_concat_w<W>(a, s);
+    case OP_UNION:
+      if (same_level)
+        hipLaunchKernelGGL((gen_union<W, true>), dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
+      else
+        hipLaunchKernelGGL((gen_union<W, false>), dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define REI_DISPATCH_W(W, CALL)                          \
+  switch (W) {                                           \
+    case 1: { constexpr int kW = 1; CALL; } break;       \
+    case 2: { constexpr int kW = 2; CALL; } break;       \
+    case 4: { constexpr int kW = 4; CALL; } break;       \
+    case 8: { constexpr int kW = 8; CALL; } break;       \
+    case 16: { constexpr int kW = 16; CALL; } break;     \
+    case 32: { constexpr int kW = 32; CALL; } break;     \
+    default: return hipErrorInvalidValue;                \
+  }
+
+hipError_t launch_fill(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u64, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_ctrl_reset(Ctrl* c, uint32_t* bitmap, uint32_t n_words, hipStream_t s) {
+  hipLaunchKernelGGL(ctrl_reset, dim3(grid_for(n_words, 256, 4096)), dim3(256), 0, s, c, bitmap,
+                     n_words);
+  return hipGetLastError();
+}
+
+hipError_t launch_rehash(int W, const uint64_t* rows, uint64_t nrows, uint64_t* slots,
+                         uint64_t slot_mask, hipStream_t s) {
+  if (nrows == 0) return hipSuccess;
+  REI_DISPATCH_W(W, hipLaunchKernelGGL(rehash_rows<kW>, dim3(grid_for(nrows, 256, 65536)),
+                                       dim3(256), 0, s, rows, nrows, slots, slot_mask));
+  return hipGetLastError();
+}
+
+hipError_t launch_gen(int W, int op, const GenArgs& a, bool same_level, hipStream_t s) {
+  if (a.e1 <= a.e0) return hipSuccess;
+  REI_DISPATCH_W(W, return launch_gen_w<kW>(op, a, same_level, s));
+  return hipGetLastError();
+}
+
+hipError_t launch_insert(int W, const ChunkArgs& a, uint32_t max_surv, hipStream_t s) {
+  REI_DISPATCH_W(W, hipLaunchKernelGGL(insert_survivors<kW>, dim3(grid_for(max_surv, 256, 8192)),
+                                       dim3(256), 0, s, a));
+  return hipGetLastError();
+}
+
+hipError_t launch_mark(const ChunkArgs& a, uint32_t max_surv, hipStream_t s) {
+  hipLaunchKernelGGL(mark_winners, dim3(grid_for(max_surv, 256, 8192)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const ChunkArgs& a, hipStream_t s) {
+  const uint32_t nb = (a.n_bitmap_words + kScanBlock - 1) / kScanBlock;
+  hipLaunchKernelGGL(scan_reduce, dim3(nb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(scan_top, dim3(1), dim3(1024), 0, s, a, nb);
+  hipLaunchKernelGGL(scan_down, dim3(nb), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(int W, const ChunkArgs& a, uint32_t max_surv, hipStream_t s) {
+  REI_DISPATCH_W(W, hipLaunchKernelGGL(compact_winners<kW>, dim3(grid_for(max_surv, 256, 8192)),
+                                       dim3(256), 0, s, a));
+  return hipGetLastError();
+}
+
+const char* gen_kernel_name(int op) {
+  switch (op) {
+    case OP_CHAR: return "gen_char";
+    case OP_QUESTION: return "gen_question";
+    case OP_STAR: return "gen_star";
+    case OP_CONCAT: return "gen_concat";
+    case OP_UNION: return "gen_union";
+  }
+  return "?";
+}
+
+}  // namespace rei

@@ -1,0 +1,67 @@
+"""The C-ABI library without a GPU: it loads, exports what include/rei.h
+declares, and rejects bad specifications on the host before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2305_18575_amd as rei
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "rei.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rei_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = rei.load_library()
+    names = declared_functions()
+    assert names, "no declarations found"
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(rei.EXPORTS) == names
+
+
+def test_status_strings():
+    lib = rei.load_library()
+    for code, name in rei.STATUS.items():
+        expect = "REI_" + name if code >= 0 else "REI_ERR_" + name
+        assert lib.rei_status_str(code).decode() == expect
+
+
+@pytest.mark.parametrize("alphabet,pos,neg,costs,status", [
+    ("01", ["2"], [], (1, 1, 1, 1, 1), "BAD_CHAR"),
+    ("01", ["01"], ["01"], (1, 1, 1, 1, 1), "INCONSISTENT"),
+    ("01", ["0"], ["1"], (1, 0, 1, 1, 1), "INVALID_ARG"),
+    ("", ["0"], ["1"], (1, 1, 1, 1, 1), "INVALID_ARG"),
+    ("0*", ["0"], [], (1, 1, 1, 1, 1), "INVALID_ARG"),
+    ("00", ["0"], [], (1, 1, 1, 1, 1), "INVALID_ARG"),
+])
+def test_create_rejects_bad_specifications(alphabet, pos, neg, costs, status):
+    with pytest.raises(rei.ReiError) as ei:
+        rei.Instance(alphabet, pos, neg, costs=costs)
+    assert ei.value.status_name == status
+
+
+def test_create_rejects_too_large_infix_closure():
+    # 3 strings of length 40 over 3 letters: far more than 2048 distinct infixes
+    import random
+    rng = random.Random(0)
+    strings = ["".join(rng.choice("012") for _ in range(40)) for _ in range(3)]
+    with pytest.raises(rei.ReiError) as ei:
+        rei.Instance("012", strings, [])
+    assert ei.value.status_name == "TOO_LARGE"
+
+
+def test_row_cap_formula_matches_header():
+    # the header documents floor(cache_bytes / (8W + 8)) with W the smallest
+    # power of two with 64W >= |ic|
+    from paper_2305_18575_amd import instances
+    assert instances.row_cap(1 << 20, 63) == (1 << 20) // 16
+    assert instances.row_cap(1 << 20, 65) == (1 << 20) // 24
+    assert instances.row_cap(1 << 20, 200) == (1 << 20) // 40
+    assert instances.row_cap(1 << 20, 2048) == (1 << 20) // 264

@@ -1,0 +1,151 @@
+"""GPU search (through the C ABI) against the CPU oracle, element by element.
+
+Exact agreement is required on everything: status, minimal cost, the printed
+expression (the enumeration order is fixed, so the first precise candidate is
+unique), unique languages and candidates per level, and the stored rows
+themselves.  All arithmetic is bitwise, so there is no tolerance.
+"""
+import pytest
+
+import oracle
+from paper_2305_18575_amd import instances
+
+pytestmark = pytest.mark.gpu
+
+
+def run_both(rei, alphabet, pos, neg, costs=(1, 1, 1, 1, 1), max_cost=30, cache_bytes=1 << 30,
+             max_errors=0, chunk=0, rows=False):
+    print(f"\ncase: sigma={alphabet} |P|={len(pos)} |N|={len(neg)} costs={costs} "
+          f"max_cost={max_cost} cache={cache_bytes} err={max_errors} chunk={chunk}", flush=True)
+    inst = rei.Instance(alphabet, pos, neg, costs, max_cost, cache_bytes)
+    if max_errors:
+        inst.set_max_errors(max_errors)
+    if chunk:
+        inst.set_chunk(chunk)
+    g = inst.solve()
+    n_ic = g.ic_size
+    cap = instances.row_cap(cache_bytes, n_ic) if n_ic else 1 << 40
+    o_inst = oracle.Oracle(alphabet, pos, neg, costs, max_cost, cap, max_errors, threads=8)
+    o = o_inst.solve()
+    assert g.status == o.status, (g, o)
+    assert g.cost == o.cost
+    assert g.regex == o.regex
+    assert g.ic_size == o.ic_size
+    for c in range(0, max_cost + 1):
+        assert g.unique_at(c) == o.unique[c], (c, g.unique, o.unique)
+        assert g.candidates_at(c) == o.candidates[c], (c, g.candidates, o.candidates)
+    if rows:
+        compare_rows(inst, o_inst, g)
+    inst.close()
+    return g, o
+
+
+def words_of(cs_bytes, W):
+    out = [0] * W
+    for i, b in enumerate(cs_bytes):
+        if b:
+            out[i >> 6] |= 1 << (i & 63)
+    return out
+
+
+def compare_rows(inst, o_inst, g, limit=None):
+    """Level c row i on the GPU is level c row i of the oracle (same bits)."""
+    W = g.cs_words
+    for k, c in enumerate(range(g.first_level, g.first_level + len(g.unique))):
+        n = inst.level_size(c)
+        assert n == o_inst.level_size(c), c
+        idx = range(n) if limit is None else range(0, n, max(1, n // limit))
+        for i in idx:
+            got = inst.row_bits(c, i, W)
+            want = words_of(o_inst.row_cs(o_inst.level_row(c, i)), W)
+            assert got == want, (c, i)
+
+
+@pytest.mark.parametrize("block", range(4))
+def test_plain_config_all_seeds(rei, block):
+    """Plain single instances (alphabet {0,1}, 4+4 strings of length 1..5)."""
+    for seed in range(block * 50, block * 50 + 50):
+        inst = instances.plain_instance(seed)
+        run_both(rei, inst.alphabet, inst.pos, inst.neg, inst.costs, inst.max_cost,
+                 rows=(seed % 10 == 0))
+
+
+@pytest.mark.parametrize("costs", [(1, 1, 1, 1, 1), (1, 1, 5, 1, 2)])
+def test_single_config_all_seeds(rei, costs):
+    """Single instances (10+10 strings of length 0..7, up to 255 infixes)."""
+    for seed in range(32):
+        inst = instances.single_instance(seed, costs)
+        run_both(rei, inst.alphabet, inst.pos, inst.neg, costs, inst.max_cost,
+                 rows=(seed % 8 == 0))
+
+
+def test_batched_config_instances(rei):
+    """Uneven small instances: alphabets of 2..4 symbols, 1..8 words per language."""
+    for inst in instances.batched_instances(0, 48):
+        run_both(rei, inst.alphabet, inst.pos, inst.neg, inst.costs, inst.max_cost)
+
+
+def test_large_config_partial(rei):
+    """Ternary instance with hundreds of infixes (16-32 words per language),
+    levels up to cost 8 (the oracle is fast there)."""
+    for seed in (0, 1):
+        inst = instances.large_instance(seed)
+        run_both(rei, inst.alphabet, inst.pos, inst.neg, inst.costs, 8, rows=True)
+
+
+@pytest.mark.parametrize("chunk", [1, 7, 64, 1000])
+def test_chunk_size_does_not_change_results(rei, chunk):
+    inst = instances.single_instance(3, (1, 1, 5, 1, 2))
+    run_both(rei, inst.alphabet, inst.pos, inst.neg, inst.costs, inst.max_cost, chunk=chunk,
+             rows=True)
+
+
+def test_repeated_solves_identical(rei):
+    inst = instances.single_instance(6)
+    h = rei.Instance(inst.alphabet, inst.pos, inst.neg, inst.costs, inst.max_cost)
+    first = h.solve()
+    for _ in range(3):
+        again = h.solve()
+        assert (again.status, again.cost, again.regex, again.unique, again.candidates) == \
+            (first.status, first.cost, first.regex, first.unique, first.candidates)
+
+
+def test_out_of_memory_parity(rei):
+    inst = instances.single_instance(3, (1, 1, 5, 1, 2))
+    for cache in (0, 16, 24 * 40, 1000 * 40, 50000 * 40):
+        run_both(rei, inst.alphabet, inst.pos, inst.neg, inst.costs, inst.max_cost,
+                 cache_bytes=cache)
+
+
+def test_not_found_parity(rei, golden):
+    t = golden["table1_row1"]
+    run_both(rei, t["alphabet"], t["pos"], t["neg"], (1, 1, 1, 1, 1), max_cost=12, rows=True)
+
+
+def test_trivial_specifications(rei):
+    g, _ = run_both(rei, "01", [], ["0", "1"])
+    assert g.regex == "∅"
+    g, _ = run_both(rei, "01", [""], ["0"], costs=(2, 1, 1, 1, 1))
+    assert g.regex == "ε" and g.cost == 2
+    g, _ = run_both(rei, "01", ["1"], ["0"])
+    assert g.regex == "1"
+
+
+@pytest.mark.parametrize("percent", [50, 45, 40, 35, 30, 25, 20, 15, 10])
+def test_allowed_error_table_gpu(rei, golden, percent):
+    """REI with error on the Table 1 row 1 specification: the GPU reproduces
+    the expression and cost the paper prints, and the oracle's counts."""
+    t = golden["table1_row1"]
+    row = next(r for r in t["allowed_error"] if r["percent"] == percent)
+    k = percent * (len(t["pos"]) + len(t["neg"])) // 100
+    g, _ = run_both(rei, t["alphabet"], t["pos"], t["neg"], (1, 1, 1, 1, 1), 30, max_errors=k)
+    assert (g.regex, g.cost) == (row["regex"], row["cost"])
+
+
+def test_allowed_error_5_percent_gpu(rei, golden):
+    """The 5% row (cost 22) against the paper's printed expression."""
+    t = golden["table1_row1"]
+    row = next(r for r in t["allowed_error"] if r["percent"] == 5)
+    k = 5 * (len(t["pos"]) + len(t["neg"])) // 100
+    g = rei.solve(t["alphabet"], t["pos"], t["neg"], max_cost=30, max_errors=k)
+    assert (g.status, g.regex, g.cost) == ("OK", row["regex"], row["cost"])
