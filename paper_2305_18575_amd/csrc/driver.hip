@@ -73,11 +73,19 @@ struct rei_instance {
   uint32_t* d_bsums = nullptr;
   uint64_t bitmap_cap = 0;  // words
   Ctrl* d_ctrl = nullptr;
-  Ctrl* h_ctrl = nullptr;   // pinned
+  DevState* d_state = nullptr;
+  // per-cost counters on the device: stored rows [0, L), unique [L, 2L),
+  // candidates [2L, 3L) with L = max_cost + 2
+  uint64_t* d_levels = nullptr;
+  DevState* h_state = nullptr;    // pinned mirrors
+  uint64_t* h_levels = nullptr;
+
+  // rows known stored at the last synchronisation, candidates enqueued since
+  uint64_t known_rows = 0;
+  uint64_t pending = 0;
 
   // levels, indexed by cost
   std::vector<uint64_t> lstart, lcount;
-  uint64_t total_rows = 0;
 
   // result
   std::vector<uint64_t> uniq, cand;
@@ -181,9 +189,9 @@ rei_status ensure_rows(rei_instance* in, uint64_t need, hipStream_t s) {
     in->err = "hipMalloc of the back-pointer array failed";
     return REI_ERR_DEVICE;
   }
-  if (in->total_rows) {
-    HIP_OK(in, hipMemcpyAsync(nr, in->d_rows, in->total_rows * W * 8, hipMemcpyDeviceToDevice, s));
-    HIP_OK(in, hipMemcpyAsync(na, in->d_aux, in->total_rows * 8, hipMemcpyDeviceToDevice, s));
+  if (in->known_rows) {
+    HIP_OK(in, hipMemcpyAsync(nr, in->d_rows, in->known_rows * W * 8, hipMemcpyDeviceToDevice, s));
+    HIP_OK(in, hipMemcpyAsync(na, in->d_aux, in->known_rows * 8, hipMemcpyDeviceToDevice, s));
   }
   HIP_OK(in, hipStreamSynchronize(s));
   dfree(in->d_rows);
@@ -205,8 +213,8 @@ rei_status ensure_table(rei_instance* in, uint64_t entries, hipStream_t s, bool 
     in->slots_cap = cap;
   }
   LAUNCH(in, s, REI_K_OTHER, cap, launch_fill(in->d_slots, cap, kEmpty, s));
-  LAUNCH(in, s, REI_K_OTHER, in->total_rows,
-         launch_rehash(in->st.W, in->d_rows, in->total_rows, in->d_slots, cap - 1, s));
+  LAUNCH(in, s, REI_K_OTHER, in->known_rows,
+         launch_rehash(in->st.W, in->d_rows, in->known_rows, in->d_slots, cap - 1, s));
   return REI_OK;
 }
 
@@ -275,24 +283,39 @@ bool make_blocks(const rei_instance* in, uint32_t c, std::vector<Block>* out) {
   return true;
 }
 
-enum ChunkOutcome { CH_CONTINUE, CH_ANSWER, CH_OOM };
+// Waits for the stream and reads the device search state.
+rei_status sync_state(rei_instance* in, hipStream_t s) {
+  const uint64_t L = in->max_cost + 2;
+  HIP_OK(in, hipMemcpyAsync(in->h_state, in->d_state, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  HIP_OK(in, hipMemcpyAsync(in->h_levels, in->d_levels, 3 * L * 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(in, hipStreamSynchronize(s));
+  in->known_rows = in->h_state->total_rows;
+  in->pending = 0;
+  return REI_OK;
+}
 
-struct Answer {
-  uint32_t cost = 0;
-  uint64_t e = 0;  // level enumeration index
-};
-
-rei_status run_chunk(rei_instance* in, hipStream_t s, uint32_t c, const Block& b, uint64_t e_base,
-                     uint64_t e0, uint64_t e1, ChunkOutcome* outcome, Answer* ans) {
+// Enqueues one chunk (no host synchronisation unless a buffer may have to
+// grow: then the stream is drained first and the buffer grown for the worst
+// case of this chunk).
+rei_status enqueue_chunk(rei_instance* in, hipStream_t s, uint32_t c, const Block& b, uint64_t e_base,
+                         uint64_t e0, uint64_t e1, bool* stopped) {
   const int W = in->st.W;
   const uint64_t len = e1 - e0;
-  const uint64_t room = in->row_cap > in->total_rows ? in->row_cap - in->total_rows : 0;
+  const uint64_t words = (len + 31) / 32;
   rei_status r;
-  if ((r = ensure_chunk_buffers(in, len)) != REI_OK) return r;
-  if ((r = ensure_rows(in, in->total_rows + std::min(len, room), s)) != REI_OK) return r;
-  if ((r = ensure_table(in, in->total_rows + len, s, false)) != REI_OK) return r;
-  const uint32_t words = (uint32_t)((len + 31) / 32);
-  LAUNCH(in, s, REI_K_OTHER, words, launch_ctrl_reset(in->d_ctrl, in->d_bitmap, words, s));
+  auto worst_rows = [&] { return std::min(in->row_cap, in->known_rows + in->pending + len); };
+  auto worst_entries = [&] { return in->known_rows + in->pending + len; };
+  if (worst_rows() > in->rows_alloc || 2 * worst_entries() > in->slots_cap || len > in->surv_cap ||
+      words > in->bitmap_cap) {
+    if ((r = sync_state(in, s)) != REI_OK) return r;
+    if (in->h_state->stop) {
+      *stopped = true;
+      return REI_OK;
+    }
+    if ((r = ensure_chunk_buffers(in, len)) != REI_OK) return r;
+    if ((r = ensure_rows(in, std::min(in->row_cap, in->known_rows + len), s)) != REI_OK) return r;
+    if ((r = ensure_table(in, in->known_rows + len, s, false)) != REI_OK) return r;
+  }
 
   GenArgs g{};
   g.rows = in->d_rows;
@@ -313,6 +336,7 @@ rei_status run_chunk(rei_instance* in, hipStream_t s, uint32_t c, const Block& b
   g.e0 = e0;
   g.e1 = e1;
   g.char_index = in->d_char_index;
+  g.st = in->d_state;
   if (b.op != OP_CHAR) {
     g.lstart = in->lstart[b.L];
     g.lcount = in->lcount[b.L];
@@ -321,8 +345,7 @@ rei_status run_chunk(rei_instance* in, hipStream_t s, uint32_t c, const Block& b
       g.rcount = in->lcount[b.R];
     }
   }
-  const int kcls = REI_K_GEN_CHAR + b.op;
-  LAUNCH(in, s, kcls, len, launch_gen(W, b.op, g, b.same, s));
+  LAUNCH(in, s, REI_K_GEN_CHAR + b.op, len, launch_gen(W, b.op, g, b.same, s));
 
   ChunkArgs ca{};
   ca.rows = in->d_rows;
@@ -336,49 +359,19 @@ rei_status run_chunk(rei_instance* in, hipStream_t s, uint32_t c, const Block& b
   ca.bitmap = in->d_bitmap;
   ca.word_prefix = in->d_prefix;
   ca.block_sums = in->d_bsums;
-  ca.n_bitmap_words = words;
+  ca.n_bitmap_words = (uint32_t)words;
   ca.ctrl = in->d_ctrl;
+  ca.st = in->d_state;
+  const uint64_t L = in->max_cost + 2;
+  ca.lcount = in->d_levels;
+  ca.uniq = in->d_levels + L;
+  ca.cand = in->d_levels + 2 * L;
+  ca.cost = c;
   ca.chunk_e0 = e_base + e0;
-  ca.row_base = in->total_rows;
-  ca.room = room;
-  const uint32_t max_surv = (uint32_t)len;
-  LAUNCH(in, s, REI_K_INSERT, len, launch_insert(W, ca, max_surv, s));
-  LAUNCH(in, s, REI_K_COMPACT, len, launch_mark(ca, max_surv, s));
-  LAUNCH(in, s, REI_K_COMPACT, words, launch_scan(ca, s));
-  LAUNCH(in, s, REI_K_COMPACT, len, launch_compact(W, ca, max_surv, s));
-  HIP_OK(in, hipMemcpyAsync(in->h_ctrl, in->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-  HIP_OK(in, hipStreamSynchronize(s));
-  const Ctrl h = *in->h_ctrl;
-
-  *outcome = CH_CONTINUE;
-  uint64_t stored;
-  if (h.answer_e != ~0u) {
-    const uint64_t a = h.answer_rank;
-    if (a > room) {
-      stored = room;
-      in->cand[c] += (uint64_t)h.overflow_e + 1;
-      in->uniq[c] += room;
-      *outcome = CH_OOM;
-    } else {
-      stored = a;
-      in->cand[c] += (uint64_t)h.answer_e + 1;
-      in->uniq[c] += a + 1;
-      *outcome = CH_ANSWER;
-      ans->cost = c;
-      ans->e = e_base + e0 + h.answer_e;
-    }
-  } else if (h.winners > room) {
-    stored = room;
-    in->cand[c] += (uint64_t)h.overflow_e + 1;
-    in->uniq[c] += room;
-    *outcome = CH_OOM;
-  } else {
-    stored = h.winners;
-    in->cand[c] += len;
-    in->uniq[c] += h.winners;
-  }
-  in->total_rows += stored;
-  in->lcount[c] += stored;
+  ca.len = len;
+  LAUNCH(in, s, REI_K_INSERT, len, launch_insert(W, ca, s));
+  LAUNCH(in, s, REI_K_COMPACT, len, launch_finalize(W, ca, s));
+  in->pending += len;
   return REI_OK;
 }
 
@@ -507,7 +500,6 @@ rei_status solve_impl(rei_instance* in, hipStream_t s, rei_result* out) {
   in->lcount.assign(in->max_cost + 2, 0);
   in->uniq.assign(in->max_cost + 2, 0);
   in->cand.assign(in->max_cost + 2, 0);
-  in->total_rows = 0;
   in->regex.clear();
 
   if (in->max_cost < c1) {
@@ -535,50 +527,59 @@ rei_status solve_impl(rei_instance* in, hipStream_t s, rei_result* out) {
   }
 
   rei_status r;
+  const uint64_t L = in->max_cost + 2;
+  in->known_rows = 0;
+  in->pending = 0;
+  LAUNCH(in, s, REI_K_OTHER, 1, launch_state_reset(in->d_ctrl, in->d_state, in->row_cap, s));
+  LAUNCH(in, s, REI_K_OTHER, 3 * L, launch_fill(in->d_levels, 3 * L, 0, s));
   if ((r = ensure_table(in, 1024, s, true)) != REI_OK) return r;
   std::vector<Block> blocks;
-  rei_status final_status = REI_NOT_FOUND;
   uint32_t last = in->max_cost;
-  Answer ans;
-  for (uint32_t c = c1; c <= in->max_cost; ++c) {
-    in->lstart[c] = in->total_rows;
+  bool stopped = false;
+  for (uint32_t c = c1; c <= in->max_cost && !stopped; ++c) {
+    in->lstart[c] = in->known_rows;
     if (!make_blocks(in, c, &blocks)) {
       in->err = "candidate count overflows 64 bits";
       return REI_ERR_TOO_LARGE;
     }
     uint64_t e_base = 0;
-    ChunkOutcome oc = CH_CONTINUE;
     for (const Block& b : blocks) {
-      for (uint64_t e0 = 0; e0 < b.count && oc == CH_CONTINUE;) {
+      for (uint64_t e0 = 0; e0 < b.count && !stopped;) {
         const uint64_t e1 = std::min(b.count, e0 + in->chunk_max);
-        if ((r = run_chunk(in, s, c, b, e_base, e0, e1, &oc, &ans)) != REI_OK) return r;
+        if ((r = enqueue_chunk(in, s, c, b, e_base, e0, e1, &stopped)) != REI_OK) return r;
         e0 = e1;
       }
-      if (oc != CH_CONTINUE) break;
+      if (stopped) break;
       e_base += b.count;
     }
-    if (oc == CH_ANSWER) {
-      final_status = REI_OK;
+    // level boundary: the next level's blocks depend on this level's size
+    if ((r = sync_state(in, s)) != REI_OK) return r;
+    in->lcount[c] = in->h_levels[c];
+    if (in->h_state->stop) {
+      stopped = true;
       last = c;
-      break;
-    }
-    if (oc == CH_OOM) {
-      final_status = REI_OUT_OF_MEMORY;
-      last = c;
-      break;
     }
   }
-  if (final_status == REI_OK) {
+  for (uint64_t c = 0; c < L; ++c) {
+    in->lcount[c] = in->h_levels[c];
+    in->uniq[c] = in->h_levels[L + c];
+    in->cand[c] = in->h_levels[2 * L + c];
+  }
+  rei_status final_status = REI_NOT_FOUND;
+  uint32_t cost = 0;
+  if (in->h_state->stop == STOP_OOM) final_status = REI_OUT_OF_MEMORY;
+  if (in->h_state->stop == STOP_ANSWER) {
+    final_status = REI_OK;
+    cost = in->h_state->answer_cost;
     Node nd;
-    if (!decode(in, ans.cost, ans.e, &nd)) {
+    if (!decode(in, cost, in->h_state->answer_e, &nd)) {
       in->err = "answer index does not decode";
       return REI_ERR_DEVICE;
     }
     if ((r = print_node(in, nd, &in->regex)) != REI_OK) return r;
   }
-  HIP_OK(in, hipStreamSynchronize(s));
   if (in->prof && (r = prof_collect(in)) != REI_OK) return r;
-  fill_result(in, final_status, final_status == REI_OK ? ans.cost : 0, last, t0);
+  fill_result(in, final_status, cost, last, t0);
   *out = in->res;
   return REI_OK;
 }
@@ -601,8 +602,12 @@ void free_device(rei_instance* in) {
   dfree(in->d_prefix);
   dfree(in->d_bsums);
   dfree(in->d_ctrl);
-  if (in->h_ctrl) (void)hipHostFree(in->h_ctrl);
-  in->h_ctrl = nullptr;
+  dfree(in->d_state);
+  dfree(in->d_levels);
+  if (in->h_state) (void)hipHostFree(in->h_state);
+  if (in->h_levels) (void)hipHostFree(in->h_levels);
+  in->h_state = nullptr;
+  in->h_levels = nullptr;
   for (auto& r : in->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -630,7 +635,11 @@ rei_status create_device(rei_instance* in) {
   if ((r = upload(in, &in->d_nmask, in->st.nmask)) != REI_OK) return r;
   if ((r = upload(in, &in->d_char_index, in->st.char_index)) != REI_OK) return r;
   HIP_OK(in, hipMalloc(&in->d_ctrl, sizeof(Ctrl)));
-  HIP_OK(in, hipHostMalloc((void**)&in->h_ctrl, sizeof(Ctrl), hipHostMallocDefault));
+  HIP_OK(in, hipMalloc(&in->d_state, sizeof(DevState)));
+  const uint64_t L = in->max_cost + 2;
+  HIP_OK(in, hipMalloc(&in->d_levels, 3 * L * 8));
+  HIP_OK(in, hipHostMalloc((void**)&in->h_state, sizeof(DevState), hipHostMallocDefault));
+  HIP_OK(in, hipHostMalloc((void**)&in->h_levels, 3 * L * 8, hipHostMallocDefault));
   return REI_OK;
 }
 

@@ -47,7 +47,8 @@ constexpr uint64_t kRowMask = (1ull << kRowBits) - 1;
 constexpr uint64_t kNewFlag = 1ull << 63;
 constexpr uint64_t kMaxChunk = (1ull << 28);  // chunk-relative indices stay far below 2^31 - 1
 
-// Per-chunk control block in device memory.
+// Per-chunk control block in device memory.  The generator starts from
+// n_surv = 0, answer_e = ~0; the chunk's last kernel puts them back.
 struct Ctrl {
   uint32_t n_surv;          // survivors appended by the generator
   uint32_t answer_e;        // chunk-relative index of the first precise survivor (or ~0)
@@ -55,6 +56,18 @@ struct Ctrl {
   uint32_t winners;         // winners in the chunk
   uint32_t overflow_e;      // chunk-relative index of the winner that does not fit
   uint32_t pad[3];
+};
+
+// Search state in device memory, advanced by the last kernel of each chunk,
+// so chunks are enqueued without waiting for the host.
+enum StopCode : uint32_t { STOP_NONE = 0, STOP_ANSWER = 1, STOP_OOM = 2 };
+struct DevState {
+  uint64_t total_rows;      // rows stored (all levels)
+  uint64_t row_cap;         // rows that fit the cache budget
+  uint32_t stop;            // StopCode; kernels of later chunks return at once
+  uint32_t answer_cost;
+  uint64_t answer_e;        // level enumeration index of the answer
+  uint64_t pad[4];
 };
 
 // Arguments shared by all generator kernels.
@@ -84,6 +97,7 @@ struct GenArgs {
   uint64_t lstart, lcount;    // left operand level: first row, number of rows
   uint64_t rstart, rcount;    // right operand level
   const int32_t* char_index;  // base level only
+  const DevState* st;
 };
 
 struct ChunkArgs {
@@ -100,9 +114,13 @@ struct ChunkArgs {
   uint32_t* block_sums;
   uint32_t n_bitmap_words;
   Ctrl* ctrl;
+  DevState* st;
+  uint64_t* uniq;             // per cost level: new languages
+  uint64_t* cand;             // per cost level: candidates
+  uint64_t* lcount;           // per cost level: stored rows
+  uint32_t cost;              // level being built
   uint64_t chunk_e0;          // level enumeration index of chunk-relative 0
-  uint64_t row_base;          // first free row (global)
-  uint64_t room;              // rows that may still be stored
+  uint64_t len;               // candidates in the chunk
 };
 
 // Kernel launchers (kernels.hip).  Every launcher returns the hipError_t of
@@ -111,11 +129,12 @@ hipError_t launch_fill(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_rehash(int W, const uint64_t* rows, uint64_t nrows, uint64_t* slots,
                          uint64_t slot_mask, hipStream_t s);
 hipError_t launch_gen(int W, int op, const GenArgs& a, bool same_level, hipStream_t s);
-hipError_t launch_insert(int W, const ChunkArgs& a, uint32_t max_surv, hipStream_t s);
-hipError_t launch_mark(const ChunkArgs& a, uint32_t max_surv, hipStream_t s);
-hipError_t launch_scan(const ChunkArgs& a, hipStream_t s);
-hipError_t launch_compact(int W, const ChunkArgs& a, uint32_t max_surv, hipStream_t s);
-hipError_t launch_ctrl_reset(Ctrl* c, uint32_t* bitmap, uint32_t n_words, hipStream_t s);
+hipError_t launch_insert(int W, const ChunkArgs& a, hipStream_t s);
+// Winners, their ranks, the stored rows and the accounting of the chunk:
+// one workgroup when the chunk is small (LDS bitmap), else a grid pipeline.
+hipError_t launch_finalize(int W, const ChunkArgs& a, hipStream_t s);
+hipError_t launch_state_reset(Ctrl* c, DevState* st, uint64_t row_cap, hipStream_t s);
+constexpr uint64_t kSmallChunk = 1ull << 14;   // candidates finalized by one workgroup
 
 const char* gen_kernel_name(int op);
 

@@ -124,6 +124,7 @@ __device__ __forceinline__ void filter_emit(const GenArgs& a, bool valid, bool k
 
 template <int W>
 __global__ __launch_bounds__(256) void gen_char(GenArgs a) {
+  if (a.st->stop) return;
   const uint64_t e = a.e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = e < a.e1;
   uint64_t key[W];
@@ -136,6 +137,7 @@ __global__ __launch_bounds__(256) void gen_char(GenArgs a) {
 // r? = eps + r; eps is word 0 of ic (shortlex puts the empty word first).
 template <int W>
 __global__ __launch_bounds__(256) void gen_question(GenArgs a) {
+  if (a.st->stop) return;
   const uint64_t e = a.e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = e < a.e1;
   uint64_t key[W];
@@ -154,6 +156,7 @@ template <int W>
 __global__ __launch_bounds__(256) void gen_star(GenArgs a) {
   __shared__ uint64_t Xt[64 * W];
   __shared__ uint64_t Yt[64 * W];
+  if (a.st->stop) return;
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t base = a.e0 + (uint64_t)blockIdx.x * 64;
   for (int k = wave; k < W; k += 4) {
@@ -202,6 +205,7 @@ __global__ __launch_bounds__(256) void gen_concat(GenArgs a, uint32_t yt_per_wg,
                                                   uint64_t i_lo, uint64_t i_hi, uint32_t gt_lds,
                                                   uint32_t n_tile_groups) {
   extern __shared__ uint64_t lds[];
+  if (a.st->stop) return;
   uint64_t* Yt = lds;                                        // [yt_per_wg][64W]
   uint64_t* Xs = Yt + (size_t)yt_per_wg * 64 * W;            // [xi_per_wg][W]
   uint32_t* G = (uint32_t*)(Xs + (size_t)xi_per_wg * W);     // guide pairs (if gt_lds)
@@ -298,6 +302,7 @@ __device__ __forceinline__ void tri_decode(uint64_t e, uint64_t n, uint64_t* pi,
 
 template <int W, bool kSame>
 __global__ __launch_bounds__(256) void gen_union(GenArgs a) {
+  if (a.st->stop) return;
   const uint64_t e = a.e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = e < a.e1;
   uint64_t i = 0, j = 0;
@@ -332,16 +337,27 @@ __global__ void fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
     p[i] = v;
 }
 
-__global__ void ctrl_reset(Ctrl* c, uint32_t* bitmap, uint32_t n_words) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 0) {
-    c->n_surv = 0;
-    c->answer_e = ~0u;
-    c->answer_rank = ~0u;
-    c->winners = 0;
-    c->overflow_e = ~0u;
-  }
-  for (uint32_t i = t; i < n_words; i += gridDim.x * blockDim.x) bitmap[i] = 0;
+__global__ void fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__device__ __forceinline__ void ctrl_clear(Ctrl* c) {
+  c->n_surv = 0;
+  c->answer_e = ~0u;
+  c->answer_rank = ~0u;
+  c->winners = 0;
+  c->overflow_e = ~0u;
+}
+
+__global__ void state_reset(Ctrl* c, DevState* st, uint64_t row_cap) {
+  ctrl_clear(c);
+  st->total_rows = 0;
+  st->row_cap = row_cap;
+  st->stop = STOP_NONE;
+  st->answer_cost = 0;
+  st->answer_e = 0;
 }
 
 template <int W>
@@ -369,8 +385,13 @@ __device__ __forceinline__ bool key_eq(const uint64_t* p, const uint64_t (&key)[
   return eq;
 }
 
+__device__ __forceinline__ uint64_t new_ref(uint32_t e, uint32_t sid) {
+  return kNewFlag | ((uint64_t)e << 32) | sid;
+}
+
 template <int W>
 __global__ __launch_bounds__(256) void insert_survivors(ChunkArgs a) {
+  if (a.st->stop) return;
   const uint32_t ns = a.ctrl->n_surv;
   for (uint32_t sid = blockIdx.x * blockDim.x + threadIdx.x; sid < ns; sid += gridDim.x * blockDim.x) {
     uint64_t key[W];
@@ -378,7 +399,7 @@ __global__ __launch_bounds__(256) void insert_survivors(ChunkArgs a) {
     for (int k = 0; k < W; ++k) key[k] = a.skey[(uint64_t)sid * W + k];
     const uint64_t h = hash_key<W>(key);
     const uint64_t fp = fingerprint(h);
-    const uint64_t mine = kNewFlag | ((uint64_t)a.se[sid] << 32) | sid;
+    const uint64_t mine = new_ref(a.se[sid], sid);
     uint64_t pos = h & a.slot_mask;
     for (;;) {
       uint64_t v = a.slots[pos];
@@ -402,12 +423,120 @@ __global__ __launch_bounds__(256) void insert_survivors(ChunkArgs a) {
   }
 }
 
+// Outcome of a chunk, in enumeration order: the answer (first precise
+// candidate) if its winners before it fit the row cap, else out of memory at
+// the first winner that does not fit; otherwise all winners are stored.
+__device__ void account_chunk(const ChunkArgs& a, uint32_t ans, uint32_t answer_rank, uint32_t winners,
+                              uint32_t overflow_e) {
+  DevState* st = a.st;
+  const uint64_t room = st->row_cap > st->total_rows ? st->row_cap - st->total_rows : 0;
+  const uint32_t c = a.cost;
+  uint64_t stored;
+  if (ans != ~0u) {
+    if ((uint64_t)answer_rank > room) {
+      stored = room;
+      a.cand[c] += (uint64_t)overflow_e + 1;
+      a.uniq[c] += room;
+      st->stop = STOP_OOM;
+    } else {
+      stored = answer_rank;
+      a.cand[c] += (uint64_t)ans + 1;
+      a.uniq[c] += (uint64_t)answer_rank + 1;
+      st->stop = STOP_ANSWER;
+      st->answer_cost = c;
+      st->answer_e = a.chunk_e0 + ans;
+    }
+  } else if ((uint64_t)winners > room) {
+    stored = room;
+    a.cand[c] += (uint64_t)overflow_e + 1;
+    a.uniq[c] += room;
+    st->stop = STOP_OOM;
+  } else {
+    stored = winners;
+    a.cand[c] += a.len;
+    a.uniq[c] += winners;
+  }
+  st->total_rows += stored;
+  a.lcount[c] += stored;
+  ctrl_clear(a.ctrl);
+}
+
+template <int W>
+__device__ __forceinline__ void store_winner(const ChunkArgs& a, uint32_t sid, uint32_t e, uint64_t row) {
+  uint64_t key[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    key[k] = a.skey[(uint64_t)sid * W + k];
+    a.rows_w[row * W + k] = key[k];
+  }
+  a.aux[row] = a.chunk_e0 + e;
+  a.slots[a.spos[sid]] = (fingerprint(hash_key<W>(key)) << kRowBits) | row;
+}
+
+constexpr uint32_t kSmallWords = (uint32_t)(kSmallChunk / 32);
+
+// Whole finalization of a small chunk in one workgroup: winner bitmap in LDS,
+// its prefix scan, ordered append, accounting.
+template <int W>
+__global__ __launch_bounds__(1024) void finalize_small(ChunkArgs a) {
+  __shared__ uint32_t bm[kSmallWords];
+  __shared__ uint32_t pre[kSmallWords];
+  __shared__ uint32_t sc[1024];
+  __shared__ uint32_t s_rank, s_over;
+  if (a.st->stop) return;
+  const uint32_t t = threadIdx.x;
+  const uint32_t ns = a.ctrl->n_surv, ans = a.ctrl->answer_e;
+  const uint32_t words = (uint32_t)((a.len + 31) / 32);
+  for (uint32_t i = t; i < words; i += 1024) bm[i] = 0;
+  if (t == 0) {
+    s_rank = ~0u;
+    s_over = ~0u;
+  }
+  __syncthreads();
+  for (uint32_t sid = t; sid < ns; sid += 1024) {
+    const uint32_t e = a.se[sid];
+    if (a.slots[a.spos[sid]] == new_ref(e, sid)) atomicOr(&bm[e >> 5], 1u << (e & 31));
+  }
+  __syncthreads();
+  const uint32_t v = (t < words) ? (uint32_t)__popc(bm[t]) : 0u;
+  sc[t] = v;
+  __syncthreads();
+  for (uint32_t off = 1; off < 1024; off <<= 1) {
+    const uint32_t x = (t >= off) ? sc[t - off] : 0u;
+    __syncthreads();
+    sc[t] += x;
+    __syncthreads();
+  }
+  if (t < words) pre[t] = sc[t] - v;
+  const uint32_t total = sc[1023];
+  __syncthreads();
+  const uint64_t row_base = a.st->total_rows;
+  const uint64_t room = a.st->row_cap > row_base ? a.st->row_cap - row_base : 0;
+  for (uint32_t sid = t; sid < ns; sid += 1024) {
+    const uint32_t e = a.se[sid];
+    const uint32_t word = bm[e >> 5];
+    const uint32_t bit = 1u << (e & 31);
+    if (!(word & bit)) continue;  // e is unique per survivor: the bit marks this one
+    const uint32_t rank = pre[e >> 5] + (uint32_t)__popc(word & (bit - 1));
+    if (e == ans) s_rank = rank;
+    if (ans != ~0u && e >= ans) continue;  // the answer and later ones are not stored
+    if (rank < room)
+      store_winner<W>(a, sid, e, row_base + rank);
+    else if (rank == room)
+      s_over = e;
+  }
+  __syncthreads();
+  if (t == 0) account_chunk(a, ans, s_rank, total, s_over);
+}
+
+// ---- grid path for large chunks ----
+
 __global__ __launch_bounds__(256) void mark_winners(ChunkArgs a) {
+  if (a.st->stop) return;
   const uint32_t ns = a.ctrl->n_surv;
   for (uint32_t sid = blockIdx.x * blockDim.x + threadIdx.x; sid < ns; sid += gridDim.x * blockDim.x) {
     const uint32_t e = a.se[sid];
-    const uint64_t mine = kNewFlag | ((uint64_t)e << 32) | sid;
-    if (a.slots[a.spos[sid]] == mine) atomicOr(&a.bitmap[e >> 5], 1u << (e & 31));
+    if (a.slots[a.spos[sid]] == new_ref(e, sid)) atomicOr(&a.bitmap[e >> 5], 1u << (e & 31));
   }
 }
 
@@ -415,6 +544,7 @@ constexpr uint32_t kScanBlock = 1024;  // bitmap words per scan block (256 threa
 
 __global__ __launch_bounds__(256) void scan_reduce(ChunkArgs a) {
   __shared__ uint32_t red[256];
+  if (a.st->stop) return;
   const uint32_t b = blockIdx.x, t = threadIdx.x;
   uint32_t s = 0;
   for (uint32_t q = 0; q < 4; ++q) {
@@ -433,9 +563,10 @@ __global__ __launch_bounds__(256) void scan_reduce(ChunkArgs a) {
 // single workgroup: exclusive scan of the block sums, total -> ctrl->winners
 __global__ __launch_bounds__(1024) void scan_top(ChunkArgs a, uint32_t nb) {
   __shared__ uint32_t part[1024];
+  if (a.st->stop) return;
   const uint32_t t = threadIdx.x;
   const uint32_t per = (nb + 1023) / 1024;
-  const uint32_t lo = t * per, hi = min(nb, lo + per);
+  const uint32_t lo = min(nb, t * per), hi = min(nb, lo + per);
   uint32_t s = 0;
   for (uint32_t i = lo; i < hi; ++i) s += a.block_sums[i];
   part[t] = s;
@@ -457,6 +588,7 @@ __global__ __launch_bounds__(1024) void scan_top(ChunkArgs a, uint32_t nb) {
 
 __global__ __launch_bounds__(256) void scan_down(ChunkArgs a) {
   __shared__ uint32_t part[256];
+  if (a.st->stop) return;
   const uint32_t b = blockIdx.x, t = threadIdx.x;
   uint32_t c[4], s = 0;
   for (uint32_t q = 0; q < 4; ++q) {
@@ -482,33 +614,29 @@ __global__ __launch_bounds__(256) void scan_down(ChunkArgs a) {
 
 template <int W>
 __global__ __launch_bounds__(256) void compact_winners(ChunkArgs a) {
+  if (a.st->stop) return;
   const uint32_t ns = a.ctrl->n_surv;
   const uint32_t ans = a.ctrl->answer_e;
+  const uint64_t row_base = a.st->total_rows;
+  const uint64_t room = a.st->row_cap > row_base ? a.st->row_cap - row_base : 0;
   for (uint32_t sid = blockIdx.x * blockDim.x + threadIdx.x; sid < ns; sid += gridDim.x * blockDim.x) {
     const uint32_t e = a.se[sid];
     const uint32_t word = a.bitmap[e >> 5];
-    if (!((word >> (e & 31)) & 1u)) continue;
-    const uint32_t mine = (1u << (e & 31));
-    // only winners reach here: the bit of e is set iff sid owns its slot
-    const uint64_t slot = a.slots[a.spos[sid]];
-    if (slot != (kNewFlag | ((uint64_t)e << 32) | sid)) continue;
-    const uint32_t rank = a.word_prefix[e >> 5] + __popc(word & (mine - 1));
+    const uint32_t bit = 1u << (e & 31);
+    if (!(word & bit)) continue;
+    const uint32_t rank = a.word_prefix[e >> 5] + (uint32_t)__popc(word & (bit - 1));
     if (e == ans) a.ctrl->answer_rank = rank;
-    if (ans != ~0u && e >= ans) continue;  // the answer and later ones are not stored
-    if (rank < a.room) {
-      const uint64_t row = a.row_base + rank;
-      uint64_t key[W];
-#pragma unroll
-      for (int k = 0; k < W; ++k) {
-        key[k] = a.skey[(uint64_t)sid * W + k];
-        a.rows_w[row * W + k] = key[k];
-      }
-      a.aux[row] = a.chunk_e0 + e;
-      a.slots[a.spos[sid]] = (fingerprint(hash_key<W>(key)) << kRowBits) | row;
-    } else if (rank == a.room) {
+    if (ans != ~0u && e >= ans) continue;
+    if (rank < room)
+      store_winner<W>(a, sid, e, row_base + rank);
+    else if (rank == room)
       a.ctrl->overflow_e = e;
-    }
   }
+}
+
+__global__ void account_large(ChunkArgs a) {
+  if (a.st->stop) return;
+  account_chunk(a, a.ctrl->answer_e, a.ctrl->answer_rank, a.ctrl->winners, a.ctrl->overflow_e);
 }
 
 inline uint32_t grid_for(uint64_t n, uint32_t block, uint32_t cap = 0x7fffffffu) {
@@ -592,9 +720,8 @@ hipError_t launch_fill(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_ctrl_reset(Ctrl* c, uint32_t* bitmap, uint32_t n_words, hipStream_t s) {
-  hipLaunchKernelGGL(ctrl_reset, dim3(grid_for(n_words, 256, 4096)), dim3(256), 0, s, c, bitmap,
-                     n_words);
+hipError_t launch_state_reset(Ctrl* c, DevState* st, uint64_t row_cap, hipStream_t s) {
+  hipLaunchKernelGGL(state_reset, dim3(1), dim3(1), 0, s, c, st, row_cap);
   return hipGetLastError();
 }
 
@@ -612,28 +739,27 @@ hipError_t launch_gen(int W, int op, const GenArgs& a, bool same_level, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_insert(int W, const ChunkArgs& a, uint32_t max_surv, hipStream_t s) {
-  REI_DISPATCH_W(W, hipLaunchKernelGGL(insert_survivors<kW>, dim3(grid_for(max_surv, 256, 8192)),
+hipError_t launch_insert(int W, const ChunkArgs& a, hipStream_t s) {
+  REI_DISPATCH_W(W, hipLaunchKernelGGL(insert_survivors<kW>, dim3(grid_for(a.len, 256, 8192)),
                                        dim3(256), 0, s, a));
   return hipGetLastError();
 }
 
-hipError_t launch_mark(const ChunkArgs& a, uint32_t max_surv, hipStream_t s) {
-  hipLaunchKernelGGL(mark_winners, dim3(grid_for(max_surv, 256, 8192)), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_scan(const ChunkArgs& a, hipStream_t s) {
+hipError_t launch_finalize(int W, const ChunkArgs& a, hipStream_t s) {
+  if (a.len <= kSmallChunk) {
+    REI_DISPATCH_W(W, hipLaunchKernelGGL(finalize_small<kW>, dim3(1), dim3(1024), 0, s, a));
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(fill_u32, dim3(grid_for(a.n_bitmap_words, 256, 4096)), dim3(256), 0, s, a.bitmap,
+                     (uint64_t)a.n_bitmap_words, 0u);
+  const uint32_t g = grid_for(a.len, 256, 8192);
+  hipLaunchKernelGGL(mark_winners, dim3(g), dim3(256), 0, s, a);
   const uint32_t nb = (a.n_bitmap_words + kScanBlock - 1) / kScanBlock;
   hipLaunchKernelGGL(scan_reduce, dim3(nb), dim3(256), 0, s, a);
   hipLaunchKernelGGL(scan_top, dim3(1), dim3(1024), 0, s, a, nb);
   hipLaunchKernelGGL(scan_down, dim3(nb), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_compact(int W, const ChunkArgs& a, uint32_t max_surv, hipStream_t s) {
-  REI_DISPATCH_W(W, hipLaunchKernelGGL(compact_winners<kW>, dim3(grid_for(max_surv, 256, 8192)),
-                                       dim3(256), 0, s, a));
+  REI_DISPATCH_W(W, hipLaunchKernelGGL(compact_winners<kW>, dim3(g), dim3(256), 0, s, a));
+  hipLaunchKernelGGL(account_large, dim3(1), dim3(1), 0, s, a);
   return hipGetLastError();
 }
 

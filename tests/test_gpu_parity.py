@@ -149,3 +149,18 @@ def test_allowed_error_5_percent_gpu(rei, golden):
     k = 5 * (len(t["pos"]) + len(t["neg"])) // 100
     g = rei.solve(t["alphabet"], t["pos"], t["neg"], max_cost=30, max_errors=k)
     assert (g.status, g.regex, g.cost) == ("OK", row["regex"], row["cost"])
+
+
+def test_table1_row1_exact_answer_gpu(rei, golden):
+    """Table 1 row 1 without error: minimal cost 28 (printed in the paper).
+    The expression printed depends on the tie-break among equal-cost
+    representatives; the language it denotes on ic must be the one of the
+    paper's expression."""
+    t = golden["table1_row1"]
+    row = next(r for r in t["allowed_error"] if r["percent"] == 0)
+    g = rei.solve(t["alphabet"], t["pos"], t["neg"], max_cost=30, cache_bytes=8 << 30)
+    assert (g.status, g.cost) == ("OK", row["cost"])
+    o = oracle.Oracle(t["alphabet"], t["pos"], t["neg"])
+    assert o.cs_of_regex(g.regex) == o.cs_of_regex(row["regex"])
+    import brute
+    assert brute.regex_cost(g.regex) == 28
