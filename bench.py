@@ -2,10 +2,13 @@
 
 A step solves one batch of synthetic single instances (alphabet {0,1}, target
 expression of cost 10..14, 10 positive and 10 negative strings of length
-0..7, seeds 0..31, under the cost functions (1,1,1,1,1) and (1,1,5,1,2)),
-each through rei_solve on the current stream.  Instances are staged
-(rei_create: host staging + upload) before the timed region, so their
-tables are resident in HBM when timing starts.
+0..7, seeds 0..31, under the cost functions (1,1,1,1,1) and (1,1,5,1,2))
+with one rei_solve_batch call on the current stream (one workgroup per
+instance runs its whole search; instances that outgrow their preallocated
+rows finish on the per-chunk path).  Instances are staged (rei_create: host
+staging + upload) before the timed region, so their tables are resident in
+HBM when timing starts.  The same instances solved one after the other with
+rei_solve are timed as well (sequential_value).
 
 value = sum over the batch of unique languages enumerated / wall time of the
 batch.  The JSON line also carries the time-to-minimal-regex distribution,
@@ -62,6 +65,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-errors", type=int, default=0)
+    ap.add_argument("--sequential", action="store_true",
+                    help="time rei_solve per instance as the step instead of rei_solve_batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the search is "
@@ -82,26 +87,37 @@ def main():
         handles.append(h)
     stream = torch.cuda.current_stream().cuda_stream
 
-    def step():
-        res = []
-        for h in handles:
-            res.append(h.solve(stream))
-        return res
+    def step_sequential():
+        return [h.solve(stream) for h in handles]
+
+    def step_batch():
+        return rei.solve_batch(handles, stream)
+
+    step = step_sequential if args.sequential else step_batch
+
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = [fn() for _ in range(k)]
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t
 
     for _ in range(args.warmup):
         step()
     for h in handles:
         h.set_profiling(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = []
-    for _ in range(args.steps):
-        results.append(step())
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    results, elapsed = timed(step, args.steps)
+    for h in handles:
+        h.set_profiling(False)
+    other = step_batch if args.sequential else step_sequential
+    other()
+    other_results, other_elapsed = timed(other, args.steps)
+    key = lambda r: (r.status, r.cost, r.regex, tuple(r.unique), tuple(r.candidates))
+    same = all(key(a) == key(b) for ra, rb in zip(results, other_results) for a, b in zip(ra, rb))
 
     uniq = sum(r.total_unique for batch in results for r in batch)
     value = uniq / elapsed
+    other_value = sum(r.total_unique for batch in other_results for r in batch) / other_elapsed
     solve_ms = sorted(r.seconds_solve * 1e3 for batch in results for r in batch)
 
     def pct(p):
@@ -117,7 +133,7 @@ def main():
             ms += b
             units += c
         classes[name] = {"launches": n, "ms": ms, "units": units}
-    gen = {k: v for k, v in classes.items() if k.startswith("gen_")}
+    gen = {k: v for k, v in classes.items() if k.startswith("gen_") or k == "solve_batch"}
     dom = max(gen, key=lambda k: gen[k]["ms"])
     d = classes[dom]
     avg_ms = d["ms"] / max(1, d["launches"])
@@ -158,7 +174,12 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": desc, "instances_per_step": len(insts)},
+        "config": {"workload": desc, "instances_per_step": len(insts),
+                   "mode": "rei_solve per instance" if args.sequential else "rei_solve_batch"},
+        ("batched_value" if args.sequential else "sequential_value"): round(other_value, 3),
+        "batched_over_sequential": round((other_value / value) if args.sequential else (value / other_value), 3),
+        "identical_results": same,
+        "instances_per_sec": round(len(insts) * args.steps / elapsed, 3),
         "time_to_minimal_regex_ms": {"mean": round(sum(solve_ms) / len(solve_ms), 4),
                                      "p50": round(pct(0.5), 4), "p99": round(pct(0.99), 4)},
         "roofline": roofline,

@@ -107,6 +107,52 @@ typedef struct {
  * identical results. */
 rei_status rei_solve(rei_instance *inst, void *hip_stream, rei_result *out);
 
+/* Solve n instances together: instances with at most 8 words per language
+ * and max_cost <= 63 run in one launch per word width, one workgroup per
+ * instance executing the whole level loop on the device (no host round trip
+ * per level); the others, and any instance that outgrows its preallocated
+ * rows, run rei_solve's path afterwards.  Every result equals what rei_solve
+ * returns for that instance.
+ *   insts        n distinct instances (each used by this call only).
+ *   arena_bytes  device bytes preallocated per batched instance for rows,
+ *                back-pointers and table (0 = 16 MiB); capped by the
+ *                instance's cache budget.
+ *   out          n results; out[i] belongs to insts[i] (owned by it, as for
+ *                rei_solve).  seconds_solve is the wall time of the call.
+ * Returns REI_OK when every instance was searched (each out[i].status tells
+ * its outcome), or the first error. */
+rei_status rei_solve_batch(rei_instance *const *insts, size_t n, void *hip_stream, uint64_t arena_bytes,
+                           rei_result *out);
+
+/* ---- serving: continuous batching ------------------------------------------
+ * A server solves submitted instances asynchronously.  Requests are admitted
+ * in arrival order while the device bytes they need fit hbm_budget; admitted
+ * requests that can be batched (as in rei_solve_batch) are launched together
+ * on a free stream from a pool of n_streams, so requests arriving while others
+ * run are started at once and their work overlaps on the device; the others
+ * (and batched ones that outgrow their preallocated rows) run rei_solve's path
+ * on one of n_workers worker threads, each with its own stream.  Each result
+ * equals rei_solve's for that instance.  The budget counts the device bytes
+ * of requests in flight (an estimate made at submit: the batched arena, or
+ * the cache budget plus its table for the per-chunk path); a finished
+ * instance keeps its buffers until rei_destroy, so that nothing on the
+ * serving path frees device memory (a free waits for the whole device).
+ * A submitted instance must not be used by the caller until its ticket
+ * reports done.  Calls may come from any host thread. */
+typedef struct rei_server rei_server;
+rei_status rei_server_create(uint64_t hbm_budget, uint32_t max_batch, uint32_t n_streams,
+                             uint32_t n_workers, rei_server **out);
+rei_status rei_server_submit(rei_server *srv, rei_instance *inst, uint64_t *ticket);
+/* *done = 1 when the ticket's search has ended: then *out (if not NULL) gets
+ * its result, *latency_s (if not NULL) the time from submit to completion,
+ * the ticket is retired and the return value is the search's status (REI_OK
+ * also for REI_NOT_FOUND / REI_OUT_OF_MEMORY outcomes, see out->status).
+ * With wait != 0 the call blocks until done. */
+rei_status rei_server_poll(rei_server *srv, uint64_t ticket, int wait, int *done, rei_result *out,
+                           double *latency_s);
+/* Finishes every submitted request, then frees the server. */
+void rei_server_destroy(rei_server *srv);
+
 /* Free the instance and its device memory.  NULL is ignored. */
 void rei_destroy(rei_instance *inst);
 
@@ -146,10 +192,12 @@ typedef enum {
   REI_K_INSERT,
   REI_K_COMPACT,
   REI_K_OTHER,
+  REI_K_BATCH,          /* the batched solver (rei_solve_batch), per word width */
   REI_K_COUNT
 } rei_kernel_class;
 
-/* Record a HIP event pair around every kernel launch of the next solves. */
+/* Record a HIP event pair around every kernel launch of the next solves
+ * (for rei_solve_batch: around each batched launch, counted on insts[0]). */
 rei_status rei_set_profiling(rei_instance *inst, int enable);
 /* Launch count, total device milliseconds and work units (candidates for the
  * generator classes, survivors for REI_K_INSERT) of one kernel class,

@@ -23,10 +23,11 @@ STATUS = {0: "OK", 1: "NOT_FOUND", 2: "OUT_OF_MEMORY", -1: "INVALID_ARG",
           -6: "HOST_ALLOC"}
 
 KERNEL_CLASSES = ["gen_char", "gen_question", "gen_star", "gen_concat", "gen_union",
-                  "insert_survivors", "compact_winners", "other"]
+                  "insert_survivors", "compact_winners", "other", "solve_batch"]
 
 # exported symbols, as declared in include/rei.h
-EXPORTS = ["rei_create", "rei_solve", "rei_destroy", "rei_status_str", "rei_last_error",
+EXPORTS = ["rei_create", "rei_solve", "rei_solve_batch", "rei_server_create", "rei_server_submit",
+           "rei_server_poll", "rei_server_destroy", "rei_destroy", "rei_status_str", "rei_last_error",
            "rei_create_error", "rei_ic_word", "rei_level_size", "rei_row_bits",
            "rei_row_regex", "rei_set_chunk", "rei_set_max_errors", "rei_set_profiling",
            "rei_kernel_stats", "rei_kernel_name"]
@@ -81,6 +82,18 @@ def load_library():
                                u32, u64, ctypes.POINTER(vp)]
     lib.rei_solve.restype = ctypes.c_int
     lib.rei_solve.argtypes = [vp, vp, ctypes.POINTER(_Result)]
+    lib.rei_solve_batch.restype = ctypes.c_int
+    lib.rei_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, vp, u64,
+                                    ctypes.POINTER(_Result)]
+    lib.rei_server_create.restype = ctypes.c_int
+    lib.rei_server_create.argtypes = [u64, u32, u32, u32, ctypes.POINTER(vp)]
+    lib.rei_server_submit.restype = ctypes.c_int
+    lib.rei_server_submit.argtypes = [vp, vp, ctypes.POINTER(u64)]
+    lib.rei_server_poll.restype = ctypes.c_int
+    lib.rei_server_poll.argtypes = [vp, u64, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(_Result), ctypes.POINTER(ctypes.c_double)]
+    lib.rei_server_destroy.restype = None
+    lib.rei_server_destroy.argtypes = [vp]
     lib.rei_destroy.restype = None
     lib.rei_destroy.argtypes = [vp]
     lib.rei_status_str.restype = cp
@@ -182,6 +195,13 @@ class Instance:
         except Exception:
             pass
 
+    def _result(self, r) -> "Result":
+        n = r.n_levels
+        return Result(STATUS[r.status], r.cost, (r.regex or b"").decode("utf-8"), r.first_level,
+                      [r.unique_per_level[i] for i in range(n)],
+                      [r.candidates_per_level[i] for i in range(n)],
+                      r.total_unique, r.ic_size, r.cs_words, r.seconds_stage, r.seconds_solve)
+
     def _check(self, st):
         if st != 0:
             raise ReiError(st, self._lib.rei_last_error(self._h).decode())
@@ -192,11 +212,7 @@ class Instance:
             stream = current_stream_handle()
         r = _Result()
         self._check(self._lib.rei_solve(self._h, ctypes.c_void_p(stream or 0), ctypes.byref(r)))
-        n = r.n_levels
-        return Result(STATUS[r.status], r.cost, (r.regex or b"").decode("utf-8"), r.first_level,
-                      [r.unique_per_level[i] for i in range(n)],
-                      [r.candidates_per_level[i] for i in range(n)],
-                      r.total_unique, r.ic_size, r.cs_words, r.seconds_stage, r.seconds_solve)
+        return self._result(r)
 
     # ---- tuning / measurement ----
     def set_chunk(self, max_candidates: int):
@@ -235,6 +251,77 @@ class Instance:
         buf = ctypes.create_string_buffer(1 << 16)
         self._check(self._lib.rei_row_regex(self._h, int(cost), int(i), buf, 1 << 16))
         return buf.value.decode("utf-8")
+
+
+def solve_batch(instances: Sequence["Instance"], stream: Optional[int] = -1,
+                arena_bytes: int = 0) -> List[Result]:
+    """``rei_solve_batch`` over staged instances (results in the same order)."""
+    if not instances:
+        return []
+    lib = load_library()
+    if stream == -1:
+        stream = current_stream_handle()
+    n = len(instances)
+    hs = (ctypes.c_void_p * n)(*[i._h for i in instances])
+    rs = (_Result * n)()
+    st = lib.rei_solve_batch(hs, n, ctypes.c_void_p(stream or 0), int(arena_bytes), rs)
+    if st != 0:
+        msg = "; ".join(sorted({lib.rei_last_error(i._h).decode() for i in instances} - {""}))
+        raise ReiError(st, msg)
+    return [inst._result(rs[k]) for k, inst in enumerate(instances)]
+
+
+class Server:
+    """Continuous-batching server (``rei_server_*``): submit staged instances,
+    poll or wait for their results."""
+
+    def __init__(self, hbm_budget: int, max_batch: int = 64, n_streams: int = 4, n_workers: int = 2):
+        lib = load_library()
+        self._lib = lib
+        h = ctypes.c_void_p()
+        st = lib.rei_server_create(int(hbm_budget), int(max_batch), int(n_streams), int(n_workers),
+                                   ctypes.byref(h))
+        if st != 0:
+            raise ReiError(st, "rei_server_create")
+        self._h = h
+        self._inst = {}
+
+    def submit(self, inst: "Instance") -> int:
+        t = ctypes.c_uint64()
+        st = self._lib.rei_server_submit(self._h, inst._h, ctypes.byref(t))
+        if st != 0:
+            raise ReiError(st, "rei_server_submit")
+        self._inst[t.value] = inst
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = False):
+        """(done, Result or None, latency seconds or None)."""
+        done = ctypes.c_int()
+        r = _Result()
+        lat = ctypes.c_double()
+        st = self._lib.rei_server_poll(self._h, int(ticket), 1 if wait else 0, ctypes.byref(done),
+                                       ctypes.byref(r), ctypes.byref(lat))
+        if not done.value:
+            return False, None, None
+        inst = self._inst.pop(ticket)
+        if st != 0:
+            raise ReiError(st, inst._lib.rei_last_error(inst._h).decode())
+        return True, inst._result(r), lat.value
+
+    def wait(self, ticket: int):
+        _, res, lat = self.poll(ticket, wait=True)
+        return res, lat
+
+    def close(self):
+        if self._h:
+            self._lib.rei_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def solve(alphabet, pos, neg, costs=(1, 1, 1, 1, 1), max_cost=30, cache_bytes=1 << 30,

@@ -1,0 +1,413 @@
+// Batched solver: one workgroup runs the complete search of one instance
+// (Algorithm 1's cost loop, Algorithm 2's constructors, uniqueness, ordered
+// append, precision) with barriers as the only synchronisation, so many small
+// instances progress side by side in one launch and no host round trip is
+// needed per level or chunk.  Results are bit-identical to the per-chunk grid
+// path: the same enumeration order, the same deterministic winner rule
+// (smallest enumeration index), the same ordered append.
+#include "device_common.h"
+
+namespace rei {
+namespace {
+
+constexpr uint32_t kWords = kBatchChunk / 32;  // winner bitmap words per chunk
+constexpr int kMaxBlocks = 2 + 2 * (int)kBatchMaxCost;
+
+struct BlockD {
+  uint32_t op, L, R, same;
+  uint64_t count;
+};
+
+// Barrier between phases whose global-memory effects later phases read: the
+// agent-scope fences make plain loads after the barrier see stores and
+// atomics from before it (the vector L1 is not kept coherent with atomics).
+__device__ __forceinline__ void phase_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Concatenation of 64 candidates that share one operand ("uniform") while the
+// other operand varies over the 64 bit positions of the transposed tile T.
+// kLeft = false: tile = right rows, out_t(w) = OR over cuts (u, v) of w with
+//                uniform(u) of T[v];
+// kLeft = true:  tile = left rows,  out_t(w) = OR over cuts (u, v) with
+//                uniform(v) of T[u].
+// Lane t receives the W words of candidate t.
+template <int W, bool kLeft>
+__device__ __forceinline__ void concat_tile(const uint64_t* T, const uint64_t* uni, const BatchDesc& d,
+                                            uint64_t (&key)[W]) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    const uint32_t w = 64u * k + lane;
+    uint64_t acc = 0;
+    if (w < d.n) {
+      const uint32_t q1 = d.gt_off[w + 1];
+      for (uint32_t q = d.gt_off[w]; q < q1; ++q) {
+        const uint32_t p = d.gt_pair[q];
+        const uint32_t ui = kLeft ? (p & 0xFFFFu) : (p >> 16);
+        const uint32_t si = kLeft ? (p >> 16) : (p & 0xFFFFu);
+        if ((uni[ui >> 6] >> (ui & 63)) & 1ull) acc |= T[si];
+      }
+    }
+    key[k] = transpose64(acc);
+  }
+}
+
+template <int W>
+__device__ __forceinline__ uint32_t insert_one(const BatchDesc& d, uint32_t sid) {
+  uint64_t key[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) key[k] = d.skey[(uint64_t)sid * W + k];
+  const uint64_t h = hash_key<W>(key);
+  const uint64_t fp = fingerprint(h);
+  const uint64_t mine = new_ref(d.se[sid], sid);
+  uint64_t pos = h & d.slot_mask;
+  for (;;) {
+    uint64_t v = d.slots[pos];
+    if (v == kEmpty) {
+      v = atomicCAS((unsigned long long*)&d.slots[pos], (unsigned long long)kEmpty, (unsigned long long)mine);
+      if (v == kEmpty) break;
+    }
+    if (v & kNewFlag) {
+      if (key_eq<W>(d.skey + (uint64_t)(uint32_t)v * W, key)) {
+        atomicMin((unsigned long long*)&d.slots[pos], (unsigned long long)mine);
+        break;
+      }
+    } else if (((v >> kRowBits) & 0xFFFFFFull) == fp && key_eq<W>(d.rows + (v & kRowMask) * W, key)) {
+      break;
+    }
+    pos = (pos + 1) & d.slot_mask;
+  }
+  return (uint32_t)pos;
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void solve_batch(const BatchDesc* descs, uint32_t n_inst) {
+  __shared__ uint64_t s_lstart[kBatchMaxCost + 2], s_lcount[kBatchMaxCost + 2];
+  __shared__ BlockD s_blk[kMaxBlocks];
+  __shared__ uint32_t s_nblk;
+  __shared__ uint32_t s_nsurv, s_ans, s_rank, s_over, s_stop;
+  __shared__ uint64_t s_total;
+  __shared__ uint32_t s_bm[kWords], s_pre[kWords];
+  __shared__ uint32_t s_sc[256];
+  __shared__ uint64_t s_tile[4][64 * W];
+  __shared__ uint64_t s_uni[4][W];
+
+  if (blockIdx.x >= n_inst) return;
+  const BatchDesc d = descs[blockIdx.x];
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const Probe probe{d.rows, d.slots, d.slot_mask, d.pmask, d.nmask, d.max_err};
+  const Sink sink{d.skey, d.se, &s_nsurv, &s_ans};
+
+  // start: empty table, zero counters
+  for (uint64_t i = tid; i <= d.slot_mask; i += 256) d.slots[i] = kEmpty;
+  for (uint32_t c = tid; c < d.max_cost + 2; c += 256) {
+    d.lcount[c] = 0;
+    d.uniq[c] = 0;
+    d.cand[c] = 0;
+  }
+  for (uint32_t c = tid; c < kBatchMaxCost + 2; c += 256) {
+    s_lstart[c] = 0;
+    s_lcount[c] = 0;
+  }
+  if (tid == 0) {
+    s_total = 0;
+    s_stop = STOP_NONE;
+  }
+  phase_barrier();
+
+  uint32_t ans_cost = 0;
+  uint64_t ans_e = 0;
+  for (uint32_t c = d.c1; c <= d.max_cost && s_stop == STOP_NONE; ++c) {
+    if (tid == 0) {
+      s_lstart[c] = s_total;
+      // constructor blocks of level c, in enumeration order
+      uint32_t nb = 0;
+      auto lc = [&](int64_t k) -> uint64_t { return (k >= (int64_t)d.c1 && k < (int64_t)c) ? s_lcount[k] : 0ull; };
+      if (c == d.c1) {
+        s_blk[nb++] = {OP_CHAR, 0, 0, 0, (uint64_t)d.nsigma};
+      } else {
+        const int64_t cc = c;
+        if (lc(cc - d.c2)) s_blk[nb++] = {OP_QUESTION, (uint32_t)(cc - d.c2), 0, 0, lc(cc - d.c2)};
+        if (lc(cc - d.c3)) s_blk[nb++] = {OP_STAR, (uint32_t)(cc - d.c3), 0, 0, lc(cc - d.c3)};
+        for (int64_t L = d.c1; cc - (int64_t)d.c4 - L >= (int64_t)d.c1; ++L) {
+          const int64_t R = cc - d.c4 - L;
+          const uint64_t n = lc(L) * lc(R);
+          if (n) s_blk[nb++] = {OP_CONCAT, (uint32_t)L, (uint32_t)R, 0, n};
+        }
+        for (int64_t L = d.c1; L <= cc - (int64_t)d.c5 - L; ++L) {
+          const int64_t R = cc - d.c5 - L;
+          const uint64_t a = lc(L), b = lc(R);
+          const uint64_t n = (L < R) ? a * b : (a ? a * (a - 1) / 2 : 0);
+          if (n) s_blk[nb++] = {OP_UNION, (uint32_t)L, (uint32_t)R, L == R ? 1u : 0u, n};
+        }
+      }
+      s_nblk = nb;
+    }
+    __syncthreads();
+    uint64_t e_base = 0;
+    for (uint32_t bi = 0; bi < s_nblk && s_stop == STOP_NONE; ++bi) {
+      const BlockD blk = s_blk[bi];
+      const uint64_t lst = s_lstart[blk.L], lct = s_lcount[blk.L];
+      const uint64_t rst = s_lstart[blk.R], rct = s_lcount[blk.R];
+      for (uint64_t e0 = 0; e0 < blk.count && s_stop == STOP_NONE; e0 += kBatchChunk) {
+        const uint64_t e1 = min(blk.count, e0 + (uint64_t)kBatchChunk);
+        const uint32_t len = (uint32_t)(e1 - e0);
+        if (tid == 0) {
+          s_nsurv = 0;
+          s_ans = ~0u;
+          s_rank = ~0u;
+          s_over = ~0u;
+        }
+        __syncthreads();
+
+        // ---- generate and probe
+        if (blk.op == OP_CHAR || blk.op == OP_QUESTION || blk.op == OP_UNION) {
+          for (uint64_t base = e0 + 64 * wave; base < e1; base += 256) {
+            const uint64_t e = base + lane;
+            const bool valid = e < e1;
+            uint64_t key[W];
+            bool dup = false;
+            if (blk.op == OP_CHAR) {
+              const int idx = valid ? d.char_index[e] : -1;
+#pragma unroll
+              for (int k = 0; k < W; ++k) key[k] = (idx >= 0 && (idx >> 6) == k) ? (1ull << (idx & 63)) : 0ull;
+            } else if (blk.op == OP_QUESTION) {
+              const uint64_t* src = d.rows + (lst + (valid ? e : 0)) * W;
+#pragma unroll
+              for (int k = 0; k < W; ++k) key[k] = valid ? src[k] : 0ull;
+              dup = (key[0] & 1ull) != 0;
+              key[0] |= 1ull;
+            } else {
+              uint64_t i = 0, j = 0;
+              if (valid) {
+                if (blk.same) {
+                  tri_decode(e, lct, &i, &j);
+                } else {
+                  i = e / rct;
+                  j = e - i * rct;
+                }
+              }
+              const uint64_t* x = d.rows + (lst + i) * W;
+              const uint64_t* y = d.rows + (rst + j) * W;
+              bool eqx = true, eqy = true;
+#pragma unroll
+              for (int k = 0; k < W; ++k) {
+                const uint64_t xv = valid ? x[k] : 0ull, yv = valid ? y[k] : 0ull;
+                key[k] = xv | yv;
+                eqx = eqx && key[k] == xv;
+                eqy = eqy && key[k] == yv;
+              }
+              dup = eqx || eqy;
+            }
+            filter_emit<W>(probe, sink, valid, dup, key, (uint32_t)(e - e0));
+          }
+        } else if (blk.op == OP_STAR) {
+          uint64_t* Xt = s_tile[0];
+          uint64_t* Yt = s_tile[1];
+          for (uint64_t g0 = e0; g0 < e1; g0 += 64) {
+            for (int k = wave; k < W; k += 4) {
+              const uint64_t e = g0 + lane;
+              const uint64_t v = (e < e1) ? d.rows[(lst + e) * W + k] : 0ull;
+              Xt[64 * k + lane] = transpose64(v);
+            }
+            for (uint32_t w = tid; w < 64u * W; w += 256) Yt[w] = (w == 0) ? ~0ull : 0ull;
+            __syncthreads();
+            for (uint32_t l = 1; l <= d.max_len; ++l) {
+              const uint32_t lo = d.len_off[l], hi = d.len_off[l + 1];
+              for (uint32_t w = lo + tid; w < hi; w += 256) {
+                uint64_t acc = 0;
+                const uint32_t q1 = d.gt_off[w + 1];
+                for (uint32_t q = d.gt_off[w] + 1; q < q1; ++q) {  // cut 0 has u = eps
+                  const uint32_t p = d.gt_pair[q];
+                  acc |= Xt[p >> 16] & Yt[p & 0xFFFFu];
+                }
+                Yt[w] = acc;
+              }
+              __syncthreads();
+            }
+            if (wave == 0) {
+              uint64_t key[W];
+#pragma unroll
+              for (int k = 0; k < W; ++k) key[k] = transpose64(Yt[64 * k + lane]);
+              const uint64_t e = g0 + lane;
+              filter_emit<W>(probe, sink, e < e1, false, key, (uint32_t)(e - e0));
+            }
+            __syncthreads();
+          }
+        } else {  // OP_CONCAT
+          uint64_t* T = s_tile[wave];
+          uint64_t* U = s_uni[wave];
+          const uint64_t nL = lct, nR = rct;
+          const uint64_t i_lo = e0 / nR, i_hi = (e1 - 1) / nR;
+          if (nR >= 64 || nR >= nL) {
+            // right operands across the lanes
+            const uint64_t nT = (nR + 63) / 64;
+            const uint64_t items = (i_hi - i_lo + 1) * nT;
+            for (uint64_t it = wave; it < items; it += 4) {
+              const uint64_t i = i_lo + it / nT, jt = it % nT;
+              const uint64_t ef = i * nR + 64 * jt, el = i * nR + min(64 * jt + 64, nR);
+              if (el <= e0 || ef >= e1) continue;
+              const uint64_t jr = 64 * jt + lane;
+#pragma unroll
+              for (int k = 0; k < W; ++k)
+                T[64 * k + lane] = transpose64(jr < nR ? d.rows[(rst + jr) * W + k] : 0ull);
+              if (lane < (uint32_t)W) U[lane] = d.rows[(lst + i) * W + lane];
+              wave_sync();
+              uint64_t key[W];
+              concat_tile<W, false>(T, U, d, key);
+              const uint64_t e = i * nR + jr;
+              filter_emit<W>(probe, sink, jr < nR && e >= e0 && e < e1, false, key, (uint32_t)(e - e0));
+              wave_sync();
+            }
+          } else {
+            // left operands across the lanes (the right level is small)
+            const uint64_t it_lo = i_lo / 64, it_hi = i_hi / 64;
+            const uint64_t items = (it_hi - it_lo + 1) * nR;
+            for (uint64_t it = wave; it < items; it += 4) {
+              const uint64_t xt = it_lo + it / nR, j = it % nR;
+              const uint64_t ef = (64 * xt) * nR + j, el = (64 * xt + 63) * nR + j;
+              if (el < e0 || ef >= e1) continue;
+              const uint64_t ir = 64 * xt + lane;
+#pragma unroll
+              for (int k = 0; k < W; ++k)
+                T[64 * k + lane] = transpose64(ir < nL ? d.rows[(lst + ir) * W + k] : 0ull);
+              if (lane < (uint32_t)W) U[lane] = d.rows[(rst + j) * W + lane];
+              wave_sync();
+              uint64_t key[W];
+              concat_tile<W, true>(T, U, d, key);
+              const uint64_t e = ir * nR + j;
+              filter_emit<W>(probe, sink, ir < nL && e >= e0 && e < e1, false, key, (uint32_t)(e - e0));
+              wave_sync();
+            }
+          }
+        }
+        phase_barrier();
+
+        // ---- insert survivors
+        const uint32_t ns = s_nsurv;
+        for (uint32_t sid = tid; sid < ns; sid += 256) d.spos[sid] = insert_one<W>(d, sid);
+        phase_barrier();
+
+        // ---- winners, ranks, ordered append, accounting
+        const uint32_t words = (len + 31) / 32;
+        for (uint32_t i = tid; i < words; i += 256) s_bm[i] = 0;
+        __syncthreads();
+        for (uint32_t sid = tid; sid < ns; sid += 256) {
+          const uint32_t e = d.se[sid];
+          if (d.slots[d.spos[sid]] == new_ref(e, sid)) atomicOr(&s_bm[e >> 5], 1u << (e & 31));
+        }
+        __syncthreads();
+        const uint32_t v = (tid < words) ? (uint32_t)__popc(s_bm[tid]) : 0u;
+        s_sc[tid] = v;
+        __syncthreads();
+        for (uint32_t off = 1; off < 256; off <<= 1) {
+          const uint32_t x = (tid >= off) ? s_sc[tid - off] : 0u;
+          __syncthreads();
+          s_sc[tid] += x;
+          __syncthreads();
+        }
+        if (tid < words) s_pre[tid] = s_sc[tid] - v;
+        const uint32_t winners = s_sc[255];
+        __syncthreads();
+        const uint64_t total = s_total;
+        const uint64_t room = d.row_cap > total ? d.row_cap - total : 0;
+        const uint64_t alloc_room = d.rows_alloc > total ? d.rows_alloc - total : 0;
+        const uint32_t ans = s_ans;
+        for (uint32_t sid = tid; sid < ns; sid += 256) {
+          const uint32_t e = d.se[sid];
+          const uint32_t word = s_bm[e >> 5];
+          const uint32_t bit = 1u << (e & 31);
+          if (!(word & bit)) continue;
+          const uint32_t rank = s_pre[e >> 5] + (uint32_t)__popc(word & (bit - 1));
+          if (e == ans) s_rank = rank;
+          if (ans != ~0u && e >= ans) continue;
+          if (rank < room && rank < alloc_room) {
+            const uint64_t row = total + rank;
+            uint64_t key[W];
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+              key[k] = d.skey[(uint64_t)sid * W + k];
+              d.rows[row * W + k] = key[k];
+            }
+            d.aux[row] = e_base + e0 + e;
+            d.slots[d.spos[sid]] = (fingerprint(hash_key<W>(key)) << kRowBits) | row;
+          } else if (rank == room) {
+            s_over = e;
+          }
+        }
+        __syncthreads();
+        if (tid == 0) {
+          uint64_t stored, du, dc;
+          uint32_t stop = STOP_NONE;
+          if (ans != ~0u) {
+            if ((uint64_t)s_rank > room) {
+              stored = room;
+              dc = (uint64_t)s_over + 1;
+              du = room;
+              stop = STOP_OOM;
+            } else {
+              stored = s_rank;
+              dc = (uint64_t)ans + 1;
+              du = (uint64_t)s_rank + 1;
+              stop = STOP_ANSWER;
+              ans_cost = c;
+              ans_e = e_base + e0 + ans;
+            }
+          } else if ((uint64_t)winners > room) {
+            stored = room;
+            dc = (uint64_t)s_over + 1;
+            du = room;
+            stop = STOP_OOM;
+          } else {
+            stored = winners;
+            dc = len;
+            du = winners;
+          }
+          if (stored > alloc_room) {
+            stop = STOP_CAPACITY;
+          } else {
+            s_total = total + stored;
+            s_lcount[c] += stored;
+            d.lcount[c] += stored;
+            d.uniq[c] += du;
+            d.cand[c] += dc;
+          }
+          s_stop = stop;
+          d.st->answer_cost = ans_cost;
+          d.st->answer_e = ans_e;
+        }
+        phase_barrier();
+      }
+      e_base += blk.count;
+    }
+  }
+  if (tid == 0) {
+    d.st->total_rows = s_total;
+    d.st->row_cap = d.row_cap;
+    d.st->stop = s_stop;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_solve_batch(int W, const BatchDesc* d_descs, uint32_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  switch (W) {
+    case 1: hipLaunchKernelGGL(solve_batch<1>, dim3(n), dim3(256), 0, s, d_descs, n); break;
+    case 2: hipLaunchKernelGGL(solve_batch<2>, dim3(n), dim3(256), 0, s, d_descs, n); break;
+    case 4: hipLaunchKernelGGL(solve_batch<4>, dim3(n), dim3(256), 0, s, d_descs, n); break;
+    case 8: hipLaunchKernelGGL(solve_batch<8>, dim3(n), dim3(256), 0, s, d_descs, n); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rei

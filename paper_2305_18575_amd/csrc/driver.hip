@@ -2,7 +2,14 @@
 // constructor blocks of each level, chunking, device memory, reconstruction
 // of the answer from the per-row back-pointers, and the C ABI.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <list>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <cstring>
 #include <new>
 #include <string>
@@ -17,6 +24,7 @@ namespace {
 thread_local std::string g_create_error;
 
 constexpr uint64_t kDefaultChunk = 1ull << 24;
+constexpr uint64_t kDefaultArena = 16ull << 20;  // bytes per batched instance
 
 struct Block {
   int op;
@@ -491,50 +499,95 @@ void fill_result(rei_instance* in, rei_status st, uint32_t cost, uint32_t last_l
   r.seconds_solve = now_s() - t0;
 }
 
-rei_status solve_impl(rei_instance* in, hipStream_t s, rei_result* out) {
-  const double t0 = now_s();
-  HIP_OK(in, hipSetDevice(in->device));
-  const rei_costs& k = in->costs;
-  const uint32_t c1 = k.c_char;
+// Resets the host-side result state; answers the trivial specifications
+// (Algorithm 1: P = {} gives the empty language, P = {eps} gives eps, both at
+// the character cost) and max_cost below the character cost.  Returns true
+// when the result is complete without a search.
+bool begin_solve(rei_instance* in, double t0) {
+  const uint32_t c1 = in->costs.c_char;
   in->lstart.assign(in->max_cost + 2, 0);
   in->lcount.assign(in->max_cost + 2, 0);
   in->uniq.assign(in->max_cost + 2, 0);
   in->cand.assign(in->max_cost + 2, 0);
   in->regex.clear();
-
+  in->known_rows = 0;
+  in->pending = 0;
   if (in->max_cost < c1) {
     fill_result(in, REI_NOT_FOUND, 0, 0, t0);
-    *out = in->res;
-    return REI_OK;
+    return true;
   }
-  // trivial specifications (Algorithm 1): the empty language, then eps
   if (in->st.P.size() <= in->max_err) {
     in->regex = "\xE2\x88\x85";
     fill_result(in, REI_OK, c1, 0, t0);
-    *out = in->res;
-    return REI_OK;
+    return true;
   }
-  {
-    uint64_t bad = 0;
-    for (auto& w : in->st.P) bad += w.empty() ? 0 : 1;
-    for (auto& w : in->st.N) bad += w.empty() ? 1 : 0;
-    if (bad <= in->max_err) {
-      in->regex = "\xCE\xB5";
-      fill_result(in, REI_OK, c1, 0, t0);
-      *out = in->res;
-      return REI_OK;
+  uint64_t bad = 0;
+  for (auto& w : in->st.P) bad += w.empty() ? 0 : 1;
+  for (auto& w : in->st.N) bad += w.empty() ? 1 : 0;
+  if (bad <= in->max_err) {
+    in->regex = "\xCE\xB5";
+    fill_result(in, REI_OK, c1, 0, t0);
+    return true;
+  }
+  return false;
+}
+
+// Builds the result from the device state mirrored by sync_state: level
+// sizes and counters, the stop code, and the answer's expression.
+rei_status finish_solve(rei_instance* in, double t0) {
+  const uint64_t L = in->max_cost + 2;
+  const uint32_t c1 = in->costs.c_char;
+  uint64_t start = 0;
+  uint32_t last_used = c1;
+  for (uint64_t c = 0; c < L; ++c) {
+    in->lcount[c] = in->h_levels[c];
+    in->uniq[c] = in->h_levels[L + c];
+    in->cand[c] = in->h_levels[2 * L + c];
+    if (c >= c1) {
+      in->lstart[c] = start;
+      start += in->lcount[c];
+      if (in->cand[c]) last_used = (uint32_t)c;
     }
   }
-
+  rei_status final_status = REI_NOT_FOUND;
+  uint32_t cost = 0, last = in->max_cost;
   rei_status r;
+  if (in->h_state->stop == STOP_OOM) {
+    final_status = REI_OUT_OF_MEMORY;
+    last = last_used;
+  }
+  if (in->h_state->stop == STOP_ANSWER) {
+    final_status = REI_OK;
+    cost = in->h_state->answer_cost;
+    last = cost;
+    Node nd;
+    if (!decode(in, cost, in->h_state->answer_e, &nd)) {
+      in->err = "answer index does not decode";
+      return REI_ERR_DEVICE;
+    }
+    if ((r = print_node(in, nd, &in->regex)) != REI_OK) return r;
+  }
+  if (in->prof && (r = prof_collect(in)) != REI_OK) return r;
+  fill_result(in, final_status, cost, last, t0);
+  return REI_OK;
+}
+
+// The per-chunk search on the grid: chunks are enqueued without waiting,
+// with one wait per cost level.
+rei_status search_levels(rei_instance* in, hipStream_t s) {
+  const uint32_t c1 = in->costs.c_char;
   const uint64_t L = in->max_cost + 2;
+  rei_status r;
+  // a fresh search: nothing stored yet (also when a batched attempt ran out
+  // of its preallocated rows and left some behind)
   in->known_rows = 0;
   in->pending = 0;
+  std::fill(in->lstart.begin(), in->lstart.end(), 0);
+  std::fill(in->lcount.begin(), in->lcount.end(), 0);
   LAUNCH(in, s, REI_K_OTHER, 1, launch_state_reset(in->d_ctrl, in->d_state, in->row_cap, s));
   LAUNCH(in, s, REI_K_OTHER, 3 * L, launch_fill(in->d_levels, 3 * L, 0, s));
   if ((r = ensure_table(in, 1024, s, true)) != REI_OK) return r;
   std::vector<Block> blocks;
-  uint32_t last = in->max_cost;
   bool stopped = false;
   for (uint32_t c = c1; c <= in->max_cost && !stopped; ++c) {
     in->lstart[c] = in->known_rows;
@@ -555,32 +608,162 @@ rei_status solve_impl(rei_instance* in, hipStream_t s, rei_result* out) {
     // level boundary: the next level's blocks depend on this level's size
     if ((r = sync_state(in, s)) != REI_OK) return r;
     in->lcount[c] = in->h_levels[c];
-    if (in->h_state->stop) {
-      stopped = true;
-      last = c;
-    }
+    if (in->h_state->stop) stopped = true;
   }
-  for (uint64_t c = 0; c < L; ++c) {
-    in->lcount[c] = in->h_levels[c];
-    in->uniq[c] = in->h_levels[L + c];
-    in->cand[c] = in->h_levels[2 * L + c];
+  return REI_OK;
+}
+
+rei_status solve_impl(rei_instance* in, hipStream_t s, rei_result* out) {
+  const double t0 = now_s();
+  HIP_OK(in, hipSetDevice(in->device));
+  rei_status r;
+  if (!begin_solve(in, t0)) {
+    if ((r = search_levels(in, s)) != REI_OK) return r;
+    if ((r = finish_solve(in, t0)) != REI_OK) return r;
   }
-  rei_status final_status = REI_NOT_FOUND;
-  uint32_t cost = 0;
-  if (in->h_state->stop == STOP_OOM) final_status = REI_OUT_OF_MEMORY;
-  if (in->h_state->stop == STOP_ANSWER) {
-    final_status = REI_OK;
-    cost = in->h_state->answer_cost;
-    Node nd;
-    if (!decode(in, cost, in->h_state->answer_e, &nd)) {
-      in->err = "answer index does not decode";
-      return REI_ERR_DEVICE;
-    }
-    if ((r = print_node(in, nd, &in->regex)) != REI_OK) return r;
-  }
-  if (in->prof && (r = prof_collect(in)) != REI_OK) return r;
-  fill_result(in, final_status, cost, last, t0);
   *out = in->res;
+  return REI_OK;
+}
+
+// Rows the batched solver preallocates for one instance (its cache budget,
+// capped by a per-instance arena size).
+uint64_t batch_rows(const rei_instance* in, uint64_t arena_bytes) {
+  const uint64_t per_row = 8ull * in->st.W + 8 + 32;  // row, back-pointer, table share
+  return std::max<uint64_t>(1024, std::min<uint64_t>(in->row_cap, arena_bytes / per_row));
+}
+
+bool batchable(const rei_instance* in) {
+  return in->st.W <= kBatchMaxW && in->max_cost <= kBatchMaxCost;
+}
+
+// ---- batched solving -------------------------------------------------------
+
+struct BatchRun {
+  hipStream_t s = nullptr;
+  double t0 = 0;
+  std::vector<rei_instance*> grid;                    // per-chunk path afterwards
+  std::vector<rei_instance*> members[kBatchMaxW + 1];  // batched, by word width
+  std::vector<rei_instance*> finished;                // results complete
+  std::vector<BatchDesc*> dbufs;
+  rei_instance* pin = nullptr;  // holds the batched launches' timings
+  size_t rec_first = 0;
+  std::vector<int> rec_w;
+};
+
+BatchDesc make_desc(const rei_instance* in) {
+  const uint64_t L = in->max_cost + 2;
+  BatchDesc d{};
+  d.gt_off = in->d_gt_off;
+  d.gt_pair = in->d_gt_pair;
+  d.len_off = in->d_len_off;
+  d.pmask = in->d_pmask;
+  d.nmask = in->d_nmask;
+  d.char_index = in->d_char_index;
+  d.n = in->st.n;
+  d.n_pairs = (uint32_t)in->st.gt_pair.size();
+  d.max_len = in->st.max_len;
+  d.nsigma = (uint32_t)in->st.sigma.size();
+  d.c1 = in->costs.c_char;
+  d.c2 = in->costs.c_question;
+  d.c3 = in->costs.c_star;
+  d.c4 = in->costs.c_concat;
+  d.c5 = in->costs.c_union;
+  d.max_cost = in->max_cost;
+  d.max_err = in->max_err;
+  d.rows = in->d_rows;
+  d.aux = in->d_aux;
+  d.rows_alloc = in->rows_alloc;
+  d.row_cap = in->row_cap;
+  d.slots = in->d_slots;
+  d.slot_mask = in->slots_cap - 1;
+  d.skey = in->d_skey;
+  d.se = in->d_se;
+  d.spos = in->d_spos;
+  d.st = in->d_state;
+  d.lcount = in->d_levels;
+  d.uniq = in->d_levels + L;
+  d.cand = in->d_levels + 2 * L;
+  return d;
+}
+
+// Device bytes a batched instance uses (rows, back-pointers, table, survivors).
+uint64_t batch_reserve(const rei_instance* in, uint64_t arena_bytes) {
+  const uint64_t R = batch_rows(in, arena_bytes);
+  const uint64_t W = in->st.W;
+  return R * (8 * W + 8) + pow2_at_least(4 * (R + kBatchChunk)) * 8 + kBatchChunk * (8 * W + 12);
+}
+
+// Trivial instances are finished at once, others that cannot be batched go to
+// run->grid; the rest are staged and launched (one launch per word width) on
+// run->s.  Nothing waits for the device.
+rei_status batch_launch(rei_instance* const* insts, size_t n, hipStream_t s, uint64_t arena_bytes,
+                        BatchRun* run) {
+  run->s = s;
+  run->t0 = now_s();
+  std::vector<BatchDesc> groups[kBatchMaxW + 1];
+  rei_status r;
+  for (size_t i = 0; i < n; ++i) {
+    rei_instance* in = insts[i];
+    in->err.clear();
+    HIP_OK(in, hipSetDevice(in->device));
+    if (begin_solve(in, run->t0)) {
+      run->finished.push_back(in);
+      continue;
+    }
+    if (!batchable(in)) {
+      run->grid.push_back(in);
+      continue;
+    }
+    const uint64_t R = batch_rows(in, arena_bytes);
+    if ((r = ensure_chunk_buffers(in, kBatchChunk)) != REI_OK) return r;
+    if ((r = ensure_rows(in, R, s)) != REI_OK) return r;
+    if ((r = ensure_table(in, in->rows_alloc + kBatchChunk, s, false)) != REI_OK) return r;
+    groups[in->st.W].push_back(make_desc(in));
+    run->members[in->st.W].push_back(in);
+  }
+  run->pin = n ? insts[0] : nullptr;
+  run->rec_first = run->pin ? run->pin->recs.size() : 0;
+  for (int W = 1; W <= kBatchMaxW; W *= 2) {
+    if (groups[W].empty()) continue;
+    rei_instance* in0 = run->members[W][0];
+    BatchDesc* dd = nullptr;
+    HIP_OK(in0, hipMalloc(&dd, groups[W].size() * sizeof(BatchDesc)));
+    run->dbufs.push_back(dd);
+    HIP_OK(in0, hipMemcpyAsync(dd, groups[W].data(), groups[W].size() * sizeof(BatchDesc),
+                               hipMemcpyHostToDevice, s));
+    hipEvent_t ev = nullptr;
+    if ((r = prof_begin(run->pin, s, &ev)) != REI_OK) return r;
+    HIP_OK(in0, launch_solve_batch(W, dd, (uint32_t)groups[W].size(), s));
+    if ((r = prof_end(run->pin, s, REI_K_BATCH, ev, 0)) != REI_OK) return r;
+    if (run->pin->prof) run->rec_w.push_back(W);
+  }
+  return REI_OK;
+}
+
+// After run->s has finished the launches: results of the batched instances;
+// those that outgrew their preallocated rows are appended to run->grid.
+rei_status batch_collect(BatchRun* run) {
+  rei_status r;
+  for (auto* p : run->dbufs) (void)hipFree(p);
+  run->dbufs.clear();
+  uint64_t group_cand[kBatchMaxW + 1] = {0};
+  std::vector<rei_instance*> done;
+  for (int W = 1; W <= kBatchMaxW; W *= 2)
+    for (rei_instance* in : run->members[W]) {
+      if ((r = sync_state(in, run->s)) != REI_OK) return r;
+      const uint64_t L = in->max_cost + 2;
+      for (uint64_t c = 0; c < L; ++c) group_cand[W] += in->h_levels[2 * L + c];
+      if (in->h_state->stop == STOP_CAPACITY)
+        run->grid.push_back(in);
+      else
+        done.push_back(in);
+    }
+  for (size_t q = 0; q < run->rec_w.size(); ++q) run->pin->recs[run->rec_first + q].units = group_cand[run->rec_w[q]];
+  for (rei_instance* in : done) {
+    if ((r = finish_solve(in, run->t0)) != REI_OK) return r;
+    run->finished.push_back(in);
+  }
+  if (run->pin && run->pin->prof && (r = prof_collect(run->pin)) != REI_OK) return r;
   return REI_OK;
 }
 
@@ -706,6 +889,41 @@ rei_status rei_solve(rei_instance* inst, void* hip_stream, rei_result* out) {
   }
 }
 
+rei_status rei_solve_batch(rei_instance* const* insts, size_t n, void* hip_stream, uint64_t arena_bytes,
+                           rei_result* out) {
+  if (n && (!insts || !out)) return REI_ERR_INVALID_ARG;
+  for (size_t i = 0; i < n; ++i)
+    if (!insts[i]) return REI_ERR_INVALID_ARG;
+  if (arena_bytes == 0) arena_bytes = kDefaultArena;
+  hipStream_t s = (hipStream_t)hip_stream;
+  BatchRun run;
+  rei_status r;
+  try {
+    if ((r = batch_launch(insts, n, s, arena_bytes, &run)) != REI_OK) {
+      for (auto* p : run.dbufs) (void)hipFree(p);
+      return r;
+    }
+    hipError_t se = hipStreamSynchronize(s);
+    if (se != hipSuccess) {
+      for (size_t i = 0; i < n; ++i) insts[i]->err = std::string("batched launch: ") + hipGetErrorString(se);
+      for (auto* p : run.dbufs) (void)hipFree(p);
+      return REI_ERR_DEVICE;
+    }
+    if ((r = batch_collect(&run)) != REI_OK) return r;
+    for (rei_instance* in : run.grid) {
+      if ((r = search_levels(in, s)) != REI_OK) return r;
+      if ((r = finish_solve(in, run.t0)) != REI_OK) return r;
+    }
+    for (size_t i = 0; i < n; ++i) {
+      insts[i]->res.seconds_solve = now_s() - run.t0;
+      out[i] = insts[i]->res;
+    }
+  } catch (const std::bad_alloc&) {
+    return REI_ERR_HOST_ALLOC;
+  }
+  return REI_OK;
+}
+
 void rei_destroy(rei_instance* inst) {
   if (!inst) return;
   free_device(inst);
@@ -808,8 +1026,277 @@ const char* rei_kernel_name(rei_kernel_class k) {
     case REI_K_INSERT: return "insert_survivors";
     case REI_K_COMPACT: return "compact_winners";
     case REI_K_OTHER: return "other";
+    case REI_K_BATCH: return "solve_batch";
     default: return "?";
   }
+}
+
+}  // extern "C"
+
+// ---- serving: continuous batching -----------------------------------------
+//
+// Requests (staged instances) queue on submit.  A scheduler thread admits
+// them in arrival order while their device bytes fit the budget, launches
+// each admitted group as one batched solve on a free stream (so groups that
+// arrive while others run overlap on the device), collects finished groups by
+// event, and hands instances that cannot be batched, or that outgrew their
+// preallocated rows, to worker threads that run the per-chunk path on their
+// own streams.  Every result equals rei_solve's for that instance.
+
+struct rei_server {
+  uint64_t budget = 0;
+  uint64_t in_use = 0;
+  uint32_t max_batch = 64;
+  uint64_t arena = kDefaultArena;
+  int device = 0;
+  struct Req {
+    rei_instance* in = nullptr;
+    uint64_t reserve = 0;
+    double t_submit = 0, t_done = 0;
+    bool done = false;
+    rei_status status = REI_OK;
+    rei_result res{};
+  };
+  std::mutex mu;
+  std::condition_variable cv_sched, cv_done, cv_grid;
+  std::unordered_map<uint64_t, Req> reqs;
+  std::deque<uint64_t> queue;       // waiting for admission
+  std::deque<uint64_t> grid_queue;  // admitted, per-chunk path
+  uint64_t next_ticket = 1;
+  bool stopping = false;
+  struct Flight {
+    BatchRun run;
+    std::vector<uint64_t> tickets;
+    int stream = -1;
+    hipEvent_t ev = nullptr;
+  };
+  std::list<Flight> flights;
+  std::vector<hipStream_t> streams;
+  std::vector<bool> stream_busy;
+  std::thread sched;
+  std::vector<std::thread> workers;
+  int busy_workers = 0;
+};
+
+namespace {
+
+void server_finish(rei_server* sv, uint64_t t, rei_status st) {
+  // caller holds sv->mu
+  auto& q = sv->reqs[t];
+  q.status = st;
+  q.res = q.in->res;
+  q.t_done = now_s();
+  q.res.seconds_solve = q.t_done - q.t_submit;
+  q.done = true;
+  sv->in_use -= q.reserve;
+  sv->cv_done.notify_all();
+  sv->cv_sched.notify_all();
+}
+
+void server_worker(rei_server* sv, hipStream_t s) {
+  (void)hipSetDevice(sv->device);
+  std::unique_lock<std::mutex> lk(sv->mu);
+  for (;;) {
+    sv->cv_grid.wait(lk, [&] { return sv->stopping || !sv->grid_queue.empty(); });
+    if (sv->grid_queue.empty()) {
+      if (sv->stopping) return;
+      continue;
+    }
+    const uint64_t t = sv->grid_queue.front();
+    sv->grid_queue.pop_front();
+    rei_instance* in = sv->reqs[t].in;
+    const double t0 = sv->reqs[t].t_submit;
+    sv->busy_workers++;
+    lk.unlock();
+    rei_status r;
+    try {
+      r = search_levels(in, s);
+      if (r == REI_OK) r = finish_solve(in, t0);
+    } catch (const std::bad_alloc&) {
+      r = REI_ERR_HOST_ALLOC;
+    }
+    lk.lock();
+    sv->busy_workers--;
+    server_finish(sv, t, r);
+  }
+}
+
+uint64_t request_reserve(const rei_server* sv, const rei_instance* in) {
+  uint64_t b = batchable(in) ? batch_reserve(in, sv->arena)
+                             : in->cache_bytes + pow2_at_least(4 * (in->row_cap + 1)) * 8;
+  return std::min(b, sv->budget);
+}
+
+void server_sched(rei_server* sv) {
+  (void)hipSetDevice(sv->device);
+  std::unique_lock<std::mutex> lk(sv->mu);
+  for (;;) {
+    // finished groups
+    for (auto it = sv->flights.begin(); it != sv->flights.end();) {
+      if (hipEventQuery(it->ev) != hipSuccess) {
+        ++it;
+        continue;
+      }
+      rei_server::Flight f = std::move(*it);
+      it = sv->flights.erase(it);
+      lk.unlock();
+      rei_status r = batch_collect(&f.run);
+      lk.lock();
+      (void)hipEventDestroy(f.ev);
+      sv->stream_busy[f.stream] = false;
+      std::unordered_map<rei_instance*, uint64_t> by_inst;
+      for (uint64_t t : f.tickets) by_inst[sv->reqs[t].in] = t;
+      if (r != REI_OK) {
+        for (uint64_t t : f.tickets) server_finish(sv, t, r);
+        continue;
+      }
+      for (rei_instance* in : f.run.finished) server_finish(sv, by_inst[in], REI_OK);
+      for (rei_instance* in : f.run.grid) {
+        sv->grid_queue.push_back(by_inst[in]);
+        sv->cv_grid.notify_one();
+      }
+    }
+    // admission in arrival order, while the bytes fit and a stream is free
+    int free_stream = -1;
+    for (size_t k = 0; k < sv->streams.size(); ++k)
+      if (!sv->stream_busy[k]) free_stream = (int)k;
+    std::vector<uint64_t> take;
+    while (!sv->queue.empty()) {
+      const uint64_t t = sv->queue.front();
+      auto& q = sv->reqs[t];
+      if (sv->in_use + q.reserve > sv->budget) break;
+      if (batchable(q.in)) {
+        if (free_stream < 0 || take.size() >= sv->max_batch) break;
+        take.push_back(t);
+      } else {
+        sv->grid_queue.push_back(t);
+        sv->cv_grid.notify_one();
+      }
+      sv->in_use += q.reserve;
+      sv->queue.pop_front();
+    }
+    if (!take.empty()) {
+      sv->flights.emplace_back();
+      rei_server::Flight& f = sv->flights.back();
+      f.tickets = take;
+      f.stream = free_stream;
+      sv->stream_busy[free_stream] = true;
+      std::vector<rei_instance*> ins;
+      for (uint64_t t : take) ins.push_back(sv->reqs[t].in);
+      hipStream_t s = sv->streams[free_stream];
+      lk.unlock();
+      rei_status r = batch_launch(ins.data(), ins.size(), s, sv->arena, &f.run);
+      hipError_t e = hipEventCreateWithFlags(&f.ev, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventRecord(f.ev, s);
+      lk.lock();
+      if (r != REI_OK || e != hipSuccess) {
+        (void)hipStreamSynchronize(s);
+        for (auto* p : f.run.dbufs) (void)hipFree(p);
+        f.run.dbufs.clear();
+        if (f.ev) (void)hipEventDestroy(f.ev);
+        sv->stream_busy[free_stream] = false;
+        for (uint64_t t : take) server_finish(sv, t, r != REI_OK ? r : REI_ERR_DEVICE);
+        sv->flights.pop_back();
+      }
+      continue;  // look again at once: more may be admissible
+    }
+    if (sv->stopping && sv->queue.empty() && sv->flights.empty()) return;
+    // wait for an arrival, a freed budget, or poll running groups
+    sv->cv_sched.wait_for(lk, std::chrono::microseconds(sv->flights.empty() ? 2000 : 20));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+rei_status rei_server_create(uint64_t hbm_budget, uint32_t max_batch, uint32_t n_streams,
+                             uint32_t n_workers, rei_server** out) {
+  if (!out || hbm_budget == 0) return REI_ERR_INVALID_ARG;
+  *out = nullptr;
+  rei_server* sv = new (std::nothrow) rei_server();
+  if (!sv) return REI_ERR_HOST_ALLOC;
+  sv->budget = hbm_budget;
+  sv->max_batch = max_batch ? max_batch : 64;
+  if (hipGetDevice(&sv->device) != hipSuccess) {
+    delete sv;
+    return REI_ERR_DEVICE;
+  }
+  const uint32_t ns = n_streams ? n_streams : 4;
+  for (uint32_t k = 0; k < ns; ++k) {
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      for (auto q : sv->streams) (void)hipStreamDestroy(q);
+      delete sv;
+      return REI_ERR_DEVICE;
+    }
+    sv->streams.push_back(s);
+    sv->stream_busy.push_back(false);
+  }
+  const uint32_t nw = n_workers ? n_workers : 2;
+  for (uint32_t k = 0; k < nw; ++k) {
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) break;
+    sv->streams.push_back(s);  // owned here, destroyed with the others
+    sv->stream_busy.push_back(true);  // never used for batches
+    sv->workers.emplace_back(server_worker, sv, s);
+  }
+  sv->sched = std::thread(server_sched, sv);
+  *out = sv;
+  return REI_OK;
+}
+
+rei_status rei_server_submit(rei_server* sv, rei_instance* inst, uint64_t* ticket) {
+  if (!sv || !inst || !ticket) return REI_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> g(sv->mu);
+  if (sv->stopping) return REI_ERR_INVALID_ARG;
+  const uint64_t t = sv->next_ticket++;
+  rei_server::Req q;
+  q.in = inst;
+  q.t_submit = now_s();
+  q.reserve = request_reserve(sv, inst);
+  sv->reqs[t] = q;
+  sv->queue.push_back(t);
+  sv->cv_sched.notify_all();
+  *ticket = t;
+  return REI_OK;
+}
+
+rei_status rei_server_poll(rei_server* sv, uint64_t ticket, int wait, int* done, rei_result* out,
+                           double* latency_s) {
+  if (!sv || !done) return REI_ERR_INVALID_ARG;
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->reqs.find(ticket);
+  if (it == sv->reqs.end()) return REI_ERR_INVALID_ARG;
+  if (wait) sv->cv_done.wait(lk, [&] { return it->second.done; });
+  *done = it->second.done ? 1 : 0;
+  if (!*done) return REI_OK;
+  if (out) *out = it->second.res;
+  if (latency_s) *latency_s = it->second.t_done - it->second.t_submit;
+  const rei_status st = it->second.status;
+  sv->reqs.erase(it);
+  return st;
+}
+
+void rei_server_destroy(rei_server* sv) {
+  if (!sv) return;
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    sv->stopping = true;
+    sv->cv_sched.notify_all();
+    sv->cv_grid.notify_all();
+  }
+  if (sv->sched.joinable()) sv->sched.join();
+  {
+    // the scheduler has drained the queue; let the workers finish theirs
+    std::unique_lock<std::mutex> lk(sv->mu);
+    sv->cv_done.wait(lk, [&] { return sv->grid_queue.empty() && sv->busy_workers == 0; });
+    sv->cv_grid.notify_all();
+  }
+  for (auto& w : sv->workers)
+    if (w.joinable()) w.join();
+  for (auto s : sv->streams) (void)hipStreamDestroy(s);
+  delete sv;
 }
 
 }  // extern "C"

@@ -60,7 +60,9 @@ struct Ctrl {
 
 // Search state in device memory, advanced by the last kernel of each chunk,
 // so chunks are enqueued without waiting for the host.
-enum StopCode : uint32_t { STOP_NONE = 0, STOP_ANSWER = 1, STOP_OOM = 2 };
+enum StopCode : uint32_t { STOP_NONE = 0, STOP_ANSWER = 1, STOP_OOM = 2, STOP_CAPACITY = 3 };
+// STOP_CAPACITY: the batched solver ran out of its preallocated rows; the
+// instance is solved again on the per-chunk path.
 struct DevState {
   uint64_t total_rows;      // rows stored (all levels)
   uint64_t row_cap;         // rows that fit the cache budget
@@ -137,5 +139,39 @@ hipError_t launch_state_reset(Ctrl* c, DevState* st, uint64_t row_cap, hipStream
 constexpr uint64_t kSmallChunk = 1ull << 14;   // candidates finalized by one workgroup
 
 const char* gen_kernel_name(int op);
+
+// ---- batched solver: one workgroup runs the whole search of one instance --
+constexpr uint32_t kBatchChunk = 8192;   // candidates per chunk
+constexpr uint32_t kBatchMaxCost = 63;   // largest max_cost handled in a batch
+constexpr int kBatchMaxW = 8;            // largest words per language
+
+struct BatchDesc {
+  // staged tables
+  const uint32_t* gt_off;
+  const uint32_t* gt_pair;
+  const uint32_t* len_off;
+  const uint64_t* pmask;
+  const uint64_t* nmask;
+  const int32_t* char_index;
+  uint32_t n, n_pairs, max_len, nsigma;
+  uint32_t c1, c2, c3, c4, c5, max_cost, max_err, pad;
+  // buffers of the instance
+  uint64_t* rows;
+  uint64_t* aux;
+  uint64_t rows_alloc;        // rows the buffers hold
+  uint64_t row_cap;           // rows the cache budget allows
+  uint64_t* slots;
+  uint64_t slot_mask;         // table holds rows_alloc + kBatchChunk entries at load <= 1/2
+  uint64_t* skey;             // kBatchChunk survivors
+  uint32_t* se;
+  uint64_t* spos;
+  DevState* st;
+  uint64_t* lcount;           // per cost: rows, unique, candidates (max_cost + 2 each)
+  uint64_t* uniq;
+  uint64_t* cand;
+};
+
+// Launches one workgroup per descriptor (all with the same W).
+hipError_t launch_solve_batch(int W, const BatchDesc* d_descs, uint32_t n, hipStream_t s);
 
 }  // namespace rei

@@ -19,105 +19,19 @@
 //             ones are copied into the cache", Sec. 3, GPU language cache).
 #include <algorithm>
 
-#include "internal.h"
+#include "device_common.h"
 
 namespace rei {
 
 namespace {
 
-constexpr int kWave = 64;
-
-__device__ __forceinline__ uint64_t mix64(uint64_t x) {
-  x ^= x >> 33;
-  x *= 0xff51afd7ed558ccdull;
-  x ^= x >> 33;
-  x *= 0xc4ceb9fe1a85ec53ull;
-  x ^= x >> 33;
-  return x;
-}
-
-template <int W>
-__device__ __forceinline__ uint64_t hash_key(const uint64_t (&k)[W]) {
-  uint64_t h = mix64(k[0] ^ 0x9e3779b97f4a7c15ull);
-#pragma unroll
-  for (int i = 1; i < W; ++i) h = mix64(h ^ k[i]);
-  return h;
-}
-
-__device__ __forceinline__ uint64_t fingerprint(uint64_t h) { return (h >> 40) & 0xFFFFFFull; }
-
-__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
-
-__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
-  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
-  lo = __shfl_xor((int)lo, m, kWave);
-  hi = __shfl_xor((int)hi, m, kWave);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// 64x64 bit-matrix transpose across a wave: on entry lane r holds row r, on
-// exit lane c holds column c (bit r of the result = bit c of row r).  Each
-// stage swaps one bit of the row index with the same bit of the column index.
-__device__ __forceinline__ uint64_t transpose64(uint64_t a) {
-  const uint32_t lane = lane_id();
-  const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
-                             0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    const int j = 32 >> s;
-    const uint64_t m = masks[s];
-    uint64_t b = shfl_xor64(a, j);
-    a = (lane & j) ? ((a & ~m) | ((b >> j) & m)) : ((a & m) | ((b & m) << j));
-  }
-  return a;
-}
-
-// Probe the table (read-only in the generator kernels: it holds stored rows
-// only) and append survivors.  Must be called by every lane of the wave.
+// Probe the table and append survivors (see filter_emit in device_common.h).
 template <int W>
 __device__ __forceinline__ void filter_emit(const GenArgs& a, bool valid, bool known_dup,
                                             const uint64_t (&key)[W], uint32_t e_rel) {
-  bool surv = false;
-  if (valid && !known_dup) {
-    const uint64_t h = hash_key<W>(key);
-    const uint64_t fp = fingerprint(h);
-    uint64_t pos = h & a.slot_mask;
-    surv = true;
-    for (;;) {
-      const uint64_t v = a.slots[pos];
-      if (v == kEmpty) break;
-      if (((v >> kRowBits) & 0xFFFFFFull) == fp) {
-        const uint64_t* r = a.rows + (v & kRowMask) * W;
-        bool eq = true;
-#pragma unroll
-        for (int k = 0; k < W; ++k) eq = eq && (r[k] == key[k]);
-        if (eq) {
-          surv = false;
-          break;
-        }
-      }
-      pos = (pos + 1) & a.slot_mask;
-    }
-  }
-  const uint64_t m = __ballot(surv);
-  if (m == 0) return;
-  const uint32_t lane = lane_id();
-  const int leader = __ffsll((unsigned long long)m) - 1;
-  uint32_t base = 0;
-  if ((int)lane == leader) base = atomicAdd(&a.ctrl->n_surv, (uint32_t)__popcll(m));
-  base = __shfl((int)base, leader, kWave);
-  if (surv) {
-    const uint32_t sid = base + (uint32_t)__popcll(m & ((1ull << lane) - 1));
-    uint64_t* dst = a.skey + (uint64_t)sid * W;
-    int bad = 0;
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-      dst[k] = key[k];
-      bad += __popcll(a.pmask[k] & ~key[k]) + __popcll(a.nmask[k] & key[k]);
-    }
-    a.se[sid] = e_rel;
-    if (bad <= (int)a.max_err) atomicMin(&a.ctrl->answer_e, e_rel);
-  }
+  const Probe p{a.rows, a.slots, a.slot_mask, a.pmask, a.nmask, a.max_err};
+  const Sink k{a.skey, a.se, &a.ctrl->n_surv, &a.ctrl->answer_e};
+  filter_emit<W>(p, k, valid, known_dup, key, e_rel);
 }
 
 // ---- generators -----------------------------------------------------------
@@ -285,21 +199,6 @@ __global__ __launch_bounds__(256) void gen_concat(GenArgs a, uint32_t yt_per_wg,
   }
 }
 
-// Pairs (i, j) with i < j of an n-row level, row-major: index of the first
-// pair of row i is i*n - i*(i+1)/2.
-__device__ __forceinline__ void tri_decode(uint64_t e, uint64_t n, uint64_t* pi, uint64_t* pj) {
-  const double b = 2.0 * (double)n - 1.0;
-  double d = b * b - 8.0 * (double)e;
-  if (d < 0) d = 0;
-  int64_t i = (int64_t)((b - sqrt(d)) * 0.5);
-  if (i < 0) i = 0;
-  auto first = [n](int64_t r) -> uint64_t { return (uint64_t)r * n - (uint64_t)r * (uint64_t)(r + 1) / 2; };
-  while (i > 0 && first(i) > e) --i;
-  while ((uint64_t)(i + 1) < n && first(i + 1) <= e) ++i;
-  *pi = (uint64_t)i;
-  *pj = (uint64_t)i + 1 + (e - first(i));
-}
-
 template <int W, bool kSame>
 __global__ __launch_bounds__(256) void gen_union(GenArgs a) {
   if (a.st->stop) return;
@@ -375,18 +274,6 @@ __global__ __launch_bounds__(256) void rehash_rows(const uint64_t* rows, uint64_
                      (unsigned long long)mine) != kEmpty)
       pos = (pos + 1) & mask;
   }
-}
-
-template <int W>
-__device__ __forceinline__ bool key_eq(const uint64_t* p, const uint64_t (&key)[W]) {
-  bool eq = true;
-#pragma unroll
-  for (int k = 0; k < W; ++k) eq = eq && p[k] == key[k];
-  return eq;
-}
-
-__device__ __forceinline__ uint64_t new_ref(uint32_t e, uint32_t sid) {
-  return kNewFlag | ((uint64_t)e << 32) | sid;
 }
 
 template <int W>

@@ -12,9 +12,10 @@ Recipe (the paper's own instance files are not available; these stand in):
   Uniformity comes from a counting table over costs.
 * Positive examples are drawn uniformly without replacement from the target's
   language restricted to the length window; negative examples from the
-  complement in the same window.  Membership is decided by Python's ``re``
-  module on a translation of the target, which is independent of both
-  implementations under test.
+  complement in the same window.  Membership is decided by a Thompson
+  automaton of the target, determinised on the fly while walking all strings
+  of the window (a textbook construction, independent of both
+  implementations under test, with no backtracking).
 * If either side is too small, or the instance breaks a size bound, the
   target is redrawn from the same random stream.
 
@@ -99,6 +100,82 @@ def ast_to_text(ast) -> str:
     return '(' + ast_to_text(ast[1]) + '+' + ast_to_text(ast[2]) + ')'
 
 
+class _Nfa:
+    """Thompson automaton of an AST: epsilon moves and character moves."""
+
+    def __init__(self, ast):
+        self.eps: List[List[int]] = []
+        self.move: List[dict] = []
+        self.start, self.accept = self._build(ast)
+
+    def _state(self) -> int:
+        self.eps.append([])
+        self.move.append({})
+        return len(self.eps) - 1
+
+    def _build(self, ast):
+        t = ast[0]
+        if t == 'c':
+            a, b = self._state(), self._state()
+            self.move[a][ast[1]] = b
+            return a, b
+        if t in '?*':
+            rs, ra = self._build(ast[1])
+            a, b = self._state(), self._state()
+            self.eps[a] += [rs, b]
+            self.eps[ra].append(b)
+            if t == '*':
+                self.eps[ra].append(rs)
+            return a, b
+        ls, la = self._build(ast[1])
+        rs, ra = self._build(ast[2])
+        if t == '.':
+            self.eps[la].append(rs)
+            return ls, ra
+        a, b = self._state(), self._state()
+        self.eps[a] += [ls, rs]
+        self.eps[la].append(b)
+        self.eps[ra].append(b)
+        return a, b
+
+    def closure(self, states) -> frozenset:
+        out, stack = set(states), list(states)
+        while stack:
+            q = stack.pop()
+            for r in self.eps[q]:
+                if r not in out:
+                    out.add(r)
+                    stack.append(r)
+        return frozenset(out)
+
+
+def language_members(ast, sigma: str, lo: int, hi: int) -> List[str]:
+    """Strings of length lo..hi (length-major, alphabet order) in the
+    target's language."""
+    nfa = _Nfa(ast)
+    trans = {}
+
+    def step(S, a):
+        k = (S, a)
+        if k not in trans:
+            trans[k] = nfa.closure({nfa.move[q][a] for q in S if a in nfa.move[q]})
+        return trans[k]
+
+    level = {"": nfa.closure({nfa.start})}
+    out = []
+    for n in range(0, hi + 1):
+        if n >= lo:
+            out.extend(w for w in level if nfa.accept in level[w])
+        if n == hi:
+            break
+        nxt = {}
+        for w, S in level.items():
+            for a in sigma:
+                nxt[w + a] = step(S, a)
+        level = nxt
+    return out
+
+
 def words(sigma: str, lo: int, hi: int) -> List[str]:
     """All strings over ``sigma`` with length in [lo, hi], length-major order."""
     out = []
@@ -137,9 +214,9 @@ def _draw_spec(rng, sigma, cost_lo, cost_hi, npos, nneg, len_lo, len_hi,
     while True:
         cost = int(rng.integers(cost_lo, cost_hi + 1))
         ast = random_ast(rng, sigma, cost)
-        pat = re.compile(ast_to_pyre(ast))
-        inl = [w for w in universe if pat.fullmatch(w)]
-        outl = [w for w in universe if not pat.fullmatch(w)]
+        members = set(language_members(ast, sigma, len_lo, len_hi))
+        inl = [w for w in universe if w in members]
+        outl = [w for w in universe if w not in members]
         if len(inl) < npos or len(outl) < nneg:
             continue
         pi = rng.choice(len(inl), size=npos, replace=False)

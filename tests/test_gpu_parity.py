@@ -164,3 +164,90 @@ def test_table1_row1_exact_answer_gpu(rei, golden):
     assert o.cs_of_regex(g.regex) == o.cs_of_regex(row["regex"])
     import brute
     assert brute.regex_cost(g.regex) == 28
+
+
+# ---- batched mode: many instances per call, one workgroup per instance ----
+
+def check_against_oracle(res, spec, cache_bytes=1 << 30, max_errors=0):
+    alphabet, pos, neg, costs, max_cost = spec
+    cap = instances.row_cap(cache_bytes, res.ic_size) if res.ic_size else 1 << 40
+    o = oracle.solve(alphabet, pos, neg, costs, max_cost, cap, max_errors, threads=8)
+    assert (res.status, res.cost, res.regex) == (o.status, o.cost, o.regex), (res, o)
+    for c in range(0, max_cost + 1):
+        assert res.unique_at(c) == o.unique[c], (c, res.unique, o.unique)
+        assert res.candidates_at(c) == o.candidates[c], (c, res.candidates, o.candidates)
+
+
+def batch_specs():
+    specs = []
+    for seed in range(0, 200, 5):
+        i = instances.plain_instance(seed)
+        specs.append((i.alphabet, i.pos, i.neg, i.costs, i.max_cost))
+    for costs in ((1, 1, 1, 1, 1), (1, 1, 5, 1, 2)):
+        for seed in range(32):
+            i = instances.single_instance(seed, costs)
+            specs.append((i.alphabet, i.pos, i.neg, costs, i.max_cost))
+    for i in instances.batched_instances(0, 48):
+        specs.append((i.alphabet, i.pos, i.neg, i.costs, i.max_cost))
+    # one instance with 16 words per language: solved on the per-chunk path
+    i = instances.large_instance(0)
+    specs.append((i.alphabet, i.pos, i.neg, i.costs, 8))
+    return specs
+
+
+@pytest.mark.parametrize("arena", [0, 1 << 16])
+def test_batch_equals_oracle(rei, arena):
+    """All results of one batched call equal the oracle's; arena 64 KiB
+    forces most instances to outgrow their rows and take the per-chunk path."""
+    specs = batch_specs()
+    print(f"\nbatch of {len(specs)} instances, arena {arena}", flush=True)
+    hs = [rei.Instance(a, p, n, c, m) for (a, p, n, c, m) in specs]
+    res = rei.solve_batch(hs, arena_bytes=arena)
+    for r, spec in zip(res, specs):
+        check_against_oracle(r, spec)
+    # rows of a few batched instances equal the oracle's rows
+    for k in (0, 45, 80):
+        a, p, n, c, m = specs[k]
+        o_inst = oracle.Oracle(a, p, n, c, m, 1 << 40, 0, threads=8)
+        o_inst.solve()
+        compare_rows(hs[k], o_inst, res[k])
+    for h in hs:
+        h.close()
+
+
+def test_batch_out_of_memory_and_errors(rei, golden):
+    t = golden["table1_row1"]
+    specs, hs, caps, errs = [], [], [], []
+    inst = instances.single_instance(3, (1, 1, 5, 1, 2))
+    for cache in (0, 16, 24 * 40, 1000 * 40, 50000 * 40):
+        specs.append((inst.alphabet, inst.pos, inst.neg, inst.costs, inst.max_cost))
+        caps.append(cache)
+        errs.append(0)
+    for percent in (50, 40, 25, 15, 10):
+        k = percent * 22 // 100
+        specs.append((t["alphabet"], t["pos"], t["neg"], (1, 1, 1, 1, 1), 30))
+        caps.append(1 << 30)
+        errs.append(k)
+    for (a, p, n, c, m), cache, k in zip(specs, caps, errs):
+        h = rei.Instance(a, p, n, c, m, cache)
+        if k:
+            h.set_max_errors(k)
+        hs.append(h)
+    res = rei.solve_batch(hs)
+    for r, spec, cache, k in zip(res, specs, caps, errs):
+        check_against_oracle(r, spec, cache, k)
+    for h in hs:
+        h.close()
+
+
+def test_batch_repeat_and_single_agree(rei):
+    specs = batch_specs()[40:104]
+    hs = [rei.Instance(a, p, n, c, m) for (a, p, n, c, m) in specs]
+    first = rei.solve_batch(hs)
+    second = rei.solve_batch(hs)
+    for h, a, b in zip(hs, first, second):
+        s = h.solve()
+        key = lambda r: (r.status, r.cost, r.regex, r.unique, r.candidates)
+        assert key(a) == key(b) == key(s)
+    for h in hs:
+        h.close()
