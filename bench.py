@@ -65,6 +65,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-errors", type=int, default=0)
+    ap.add_argument("--serving-requests", type=int, default=200,
+                    help="requests per serving run (0 = skip the serving measurement)")
     ap.add_argument("--sequential", action="store_true",
                     help="time rei_solve per instance as the step instead of rei_solve_batch")
     args = ap.parse_args()
@@ -144,6 +146,36 @@ def main():
                 "avg_launch_us": round(avg_ms * 1e3, 3), "launches": d["launches"],
                 "candidates_per_launch": round(d["units"] / max(1, d["launches"]), 1)}
 
+    serving_out = None
+    if args.serving_requests:
+        from paper_2305_18575_amd import serving as S
+        specs = S.request_mix(2024, args.serving_requests)
+        hs = S.stage(rei, specs)
+        for h in hs:  # first solve allocates each instance's buffers
+            h.solve(stream)
+        base_arr = S.poisson_arrivals(2024, len(hs), 1.0)
+        seq_res, _, _ = S.run_sequential(rei, hs, base_arr * 0.0, stream)
+        # capacity of the sequential solver: requests per second of pure service
+        t = time.perf_counter()
+        for h in hs:
+            h.solve(stream)
+        capacity = len(hs) / (time.perf_counter() - t)
+        runs = []
+        for mult in (1.0, 2.0):
+            qps = capacity * mult
+            arr = base_arr / qps
+            res, lat, ips = S.run_served(rei, hs, arr, budget=128 << 30)
+            sres, slat, sips = S.run_sequential(rei, hs, arr, stream)
+            runs.append({"qps": round(qps, 2), "served": {"instances_per_sec": round(ips, 2),
+                                                          **{k: round(v, 3) for k, v in S.percentiles(lat).items()}},
+                         "sequential": {"instances_per_sec": round(sips, 2),
+                                        **{k: round(v, 3) for k, v in S.percentiles(slat).items()}},
+                         "identical_results": all(S.same(a, b) for a, b in zip(res, seq_res))})
+        serving_out = {"requests": len(hs), "mix": "60% plain / 30% large (max cost 10) / 10% single",
+                       "sequential_capacity_per_sec": round(capacity, 2), "runs": runs}
+        for h in hs:
+            h.close()
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -183,6 +215,7 @@ def main():
         "time_to_minimal_regex_ms": {"mean": round(sum(solve_ms) / len(solve_ms), 4),
                                      "p50": round(pct(0.5), 4), "p99": round(pct(0.99), 4)},
         "roofline": roofline,
+        "serving": serving_out,
         "cpu_baseline": cpu,
         "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3), "units": v["units"]}
                     for k, v in classes.items()},

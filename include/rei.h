@@ -197,7 +197,8 @@ typedef enum {
 } rei_kernel_class;
 
 /* Record a HIP event pair around every kernel launch of the next solves
- * (for rei_solve_batch: around each batched launch, counted on insts[0]). */
+ * (for rei_solve_batch: around each batched launch, counted on insts[0]).
+ * Turning profiling on clears the statistics; turning it off keeps them. */
 rei_status rei_set_profiling(rei_instance *inst, int enable);
 /* Launch count, total device milliseconds and work units (candidates for the
  * generator classes, survivors for REI_K_INSERT) of one kernel class,

@@ -60,35 +60,7 @@ __device__ __forceinline__ void concat_tile(const uint64_t* T, const uint64_t* u
   }
 }
 
-template <int W>
-__device__ __forceinline__ uint32_t insert_one(const BatchDesc& d, uint32_t sid) {
-  uint64_t key[W];
-#pragma unroll
-  for (int k = 0; k < W; ++k) key[k] = d.skey[(uint64_t)sid * W + k];
-  const uint64_t h = hash_key<W>(key);
-  const uint64_t fp = fingerprint(h);
-  const uint64_t mine = new_ref(d.se[sid], sid);
-  uint64_t pos = h & d.slot_mask;
-  for (;;) {
-    uint64_t v = d.slots[pos];
-    if (v == kEmpty) {
-      v = atomicCAS((unsigned long long*)&d.slots[pos], (unsigned long long)kEmpty, (unsigned long long)mine);
-      if (v == kEmpty) break;
-    }
-    if (v & kNewFlag) {
-      if (key_eq<W>(d.skey + (uint64_t)(uint32_t)v * W, key)) {
-        atomicMin((unsigned long long*)&d.slots[pos], (unsigned long long)mine);
-        break;
-      }
-    } else if (((v >> kRowBits) & 0xFFFFFFull) == fp && key_eq<W>(d.rows + (v & kRowMask) * W, key)) {
-      break;
-    }
-    pos = (pos + 1) & d.slot_mask;
-  }
-  return (uint32_t)pos;
-}
-
-template <int W>
+template <int W, bool kInl>
 __global__ __launch_bounds__(256) void solve_batch(const BatchDesc* descs, uint32_t n_inst) {
   __shared__ uint64_t s_lstart[kBatchMaxCost + 2], s_lcount[kBatchMaxCost + 2];
   __shared__ BlockD s_blk[kMaxBlocks];
@@ -107,7 +79,10 @@ __global__ __launch_bounds__(256) void solve_batch(const BatchDesc* descs, uint3
   const Sink sink{d.skey, d.se, &s_nsurv, &s_ans};
 
   // start: empty table, zero counters
-  for (uint64_t i = tid; i <= d.slot_mask; i += 256) d.slots[i] = kEmpty;
+  for (uint64_t i = tid; i <= d.slot_mask; i += 256) {
+    d.slots[i] = kEmpty;
+    if (kInl) d.sref[i] = kEmpty;
+  }
   for (uint32_t c = tid; c < d.max_cost + 2; c += 256) {
     d.lcount[c] = 0;
     d.uniq[c] = 0;
@@ -207,7 +182,7 @@ __global__ __launch_bounds__(256) void solve_batch(const BatchDesc* descs, uint3
               }
               dup = eqx || eqy;
             }
-            filter_emit<W>(probe, sink, valid, dup, key, (uint32_t)(e - e0));
+            filter_emit<W, kInl>(probe, sink, valid, dup, key, (uint32_t)(e - e0));
           }
         } else if (blk.op == OP_STAR) {
           uint64_t* Xt = s_tile[0];
@@ -238,7 +213,7 @@ __global__ __launch_bounds__(256) void solve_batch(const BatchDesc* descs, uint3
 #pragma unroll
               for (int k = 0; k < W; ++k) key[k] = transpose64(Yt[64 * k + lane]);
               const uint64_t e = g0 + lane;
-              filter_emit<W>(probe, sink, e < e1, false, key, (uint32_t)(e - e0));
+              filter_emit<W, kInl>(probe, sink, e < e1, false, key, (uint32_t)(e - e0));
             }
             __syncthreads();
           }
@@ -264,7 +239,7 @@ __global__ __launch_bounds__(256) void solve_batch(const BatchDesc* descs, uint3
               uint64_t key[W];
               concat_tile<W, false>(T, U, d, key);
               const uint64_t e = i * nR + jr;
-              filter_emit<W>(probe, sink, jr < nR && e >= e0 && e < e1, false, key, (uint32_t)(e - e0));
+              filter_emit<W, kInl>(probe, sink, jr < nR && e >= e0 && e < e1, false, key, (uint32_t)(e - e0));
               wave_sync();
             }
           } else {
@@ -284,7 +259,7 @@ __global__ __launch_bounds__(256) void solve_batch(const BatchDesc* descs, uint3
               uint64_t key[W];
               concat_tile<W, true>(T, U, d, key);
               const uint64_t e = ir * nR + j;
-              filter_emit<W>(probe, sink, ir < nL && e >= e0 && e < e1, false, key, (uint32_t)(e - e0));
+              filter_emit<W, kInl>(probe, sink, ir < nL && e >= e0 && e < e1, false, key, (uint32_t)(e - e0));
               wave_sync();
             }
           }
@@ -293,7 +268,13 @@ __global__ __launch_bounds__(256) void solve_batch(const BatchDesc* descs, uint3
 
         // ---- insert survivors
         const uint32_t ns = s_nsurv;
-        for (uint32_t sid = tid; sid < ns; sid += 256) d.spos[sid] = insert_one<W>(d, sid);
+        for (uint32_t sid = tid; sid < ns; sid += 256) {
+          uint64_t key[W];
+#pragma unroll
+          for (int k = 0; k < W; ++k) key[k] = d.skey[(uint64_t)sid * W + k];
+          d.spos[sid] = table_insert<W, kInl>(d.slots, d.sref, d.slot_mask, d.rows, d.skey, key, hash_key<W>(key),
+                                              new_ref(d.se[sid], sid));
+        }
         phase_barrier();
 
         // ---- winners, ranks, ordered append, accounting
@@ -302,7 +283,8 @@ __global__ __launch_bounds__(256) void solve_batch(const BatchDesc* descs, uint3
         __syncthreads();
         for (uint32_t sid = tid; sid < ns; sid += 256) {
           const uint32_t e = d.se[sid];
-          if (d.slots[d.spos[sid]] == new_ref(e, sid)) atomicOr(&s_bm[e >> 5], 1u << (e & 31));
+          if (table_is_winner<kInl>(d.slots, d.sref, d.spos[sid], new_ref(e, sid)))
+            atomicOr(&s_bm[e >> 5], 1u << (e & 31));
         }
         __syncthreads();
         const uint32_t v = (tid < words) ? (uint32_t)__popc(s_bm[tid]) : 0u;
@@ -338,7 +320,7 @@ __global__ __launch_bounds__(256) void solve_batch(const BatchDesc* descs, uint3
               d.rows[row * W + k] = key[k];
             }
             d.aux[row] = e_base + e0 + e;
-            d.slots[d.spos[sid]] = (fingerprint(hash_key<W>(key)) << kRowBits) | row;
+            table_publish<W, kInl>(d.slots, d.sref, d.spos[sid], key, row);
           } else if (rank == room) {
             s_over = e;
           }
@@ -398,13 +380,18 @@ __global__ __launch_bounds__(256) void solve_batch(const BatchDesc* descs, uint3
 
 }  // namespace
 
-hipError_t launch_solve_batch(int W, const BatchDesc* d_descs, uint32_t n, hipStream_t s) {
+hipError_t launch_solve_batch(int W, bool inl, const BatchDesc* d_descs, uint32_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   switch (W) {
-    case 1: hipLaunchKernelGGL(solve_batch<1>, dim3(n), dim3(256), 0, s, d_descs, n); break;
-    case 2: hipLaunchKernelGGL(solve_batch<2>, dim3(n), dim3(256), 0, s, d_descs, n); break;
-    case 4: hipLaunchKernelGGL(solve_batch<4>, dim3(n), dim3(256), 0, s, d_descs, n); break;
-    case 8: hipLaunchKernelGGL(solve_batch<8>, dim3(n), dim3(256), 0, s, d_descs, n); break;
+    case 1:
+      if (inl)
+        hipLaunchKernelGGL((solve_batch<1, true>), dim3(n), dim3(256), 0, s, d_descs, n);
+      else
+        hipLaunchKernelGGL((solve_batch<1, false>), dim3(n), dim3(256), 0, s, d_descs, n);
+      break;
+    case 2: hipLaunchKernelGGL((solve_batch<2, false>), dim3(n), dim3(256), 0, s, d_descs, n); break;
+    case 4: hipLaunchKernelGGL((solve_batch<4, false>), dim3(n), dim3(256), 0, s, d_descs, n); break;
+    case 8: hipLaunchKernelGGL((solve_batch<8, false>), dim3(n), dim3(256), 0, s, d_descs, n); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -55,8 +55,125 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t a) {
   return a;
 }
 
-// Where a generator probes: the cache rows and the dedup table (read-only
-// while generators run: it holds stored rows only), and the precision masks.
+// ---- dedup table -----------------------------------------------------------
+// Fingerprint form (any W): a slot holds EMPTY, a stored row
+// (0 | fingerprint | row) or a survivor of the running chunk (1 | e | sid);
+// equal keys are confirmed against the row or the survivor's key.
+// Inline form (kInl: one word per language and |ic| <= 63, so no language is
+// all ones): a slot holds the key itself; sref[pos] holds the smallest
+// survivor reference of the running chunk for that key (EMPTY otherwise).
+// A probe is then a single read.
+
+template <int W>
+__device__ __forceinline__ bool key_eq(const uint64_t* p, const uint64_t (&key)[W]) {
+  bool eq = true;
+#pragma unroll
+  for (int k = 0; k < W; ++k) eq = eq && p[k] == key[k];
+  return eq;
+}
+
+__device__ __forceinline__ uint64_t new_ref(uint32_t e, uint32_t sid) {
+  return kNewFlag | ((uint64_t)e << 32) | sid;
+}
+
+// Is the key stored?  The table holds stored rows only while generators run.
+template <int W, bool kInl>
+__device__ __forceinline__ bool table_find(const uint64_t* slots, uint64_t mask, const uint64_t* rows,
+                                           const uint64_t (&key)[W], uint64_t h) {
+  uint64_t pos = h & mask;
+  if constexpr (kInl) {
+    for (;;) {
+      const uint64_t v = slots[pos];
+      if (v == kEmpty) return false;
+      if (v == key[0]) return true;
+      pos = (pos + 1) & mask;
+    }
+  } else {
+    const uint64_t fp = fingerprint(h);
+    for (;;) {
+      const uint64_t v = slots[pos];
+      if (v == kEmpty) return false;
+      if (((v >> kRowBits) & 0xFFFFFFull) == fp && key_eq<W>(rows + (v & kRowMask) * W, key)) return true;
+      pos = (pos + 1) & mask;
+    }
+  }
+}
+
+// Inserts a survivor (reference `mine` = 1 | e | sid); equal keys meet in one
+// slot and keep the smallest reference.  Returns the slot.
+template <int W, bool kInl>
+__device__ __forceinline__ uint64_t table_insert(uint64_t* slots, uint64_t* sref, uint64_t mask,
+                                                 const uint64_t* rows, const uint64_t* skey,
+                                                 const uint64_t (&key)[W], uint64_t h, uint64_t mine) {
+  uint64_t pos = h & mask;
+  if constexpr (kInl) {
+    for (;;) {
+      uint64_t v = slots[pos];
+      if (v == kEmpty) {
+        v = atomicCAS((unsigned long long*)&slots[pos], (unsigned long long)kEmpty,
+                      (unsigned long long)key[0]);
+        if (v == kEmpty) v = key[0];  // claimed
+      }
+      if (v == key[0]) {
+        atomicMin((unsigned long long*)&sref[pos], (unsigned long long)mine);
+        return pos;
+      }
+      pos = (pos + 1) & mask;
+    }
+  } else {
+    const uint64_t fp = fingerprint(h);
+    for (;;) {
+      uint64_t v = slots[pos];
+      if (v == kEmpty) {
+        v = atomicCAS((unsigned long long*)&slots[pos], (unsigned long long)kEmpty,
+                      (unsigned long long)mine);
+        if (v == kEmpty) return pos;  // claimed
+      }
+      if (v & kNewFlag) {
+        // another survivor owns the slot; its key never changes
+        if (key_eq<W>(skey + (uint64_t)(uint32_t)v * W, key)) {
+          atomicMin((unsigned long long*)&slots[pos], (unsigned long long)mine);
+          return pos;
+        }
+      } else if (((v >> kRowBits) & 0xFFFFFFull) == fp && key_eq<W>(rows + (v & kRowMask) * W, key)) {
+        return pos;  // stored already (the generators filter these; kept for safety)
+      }
+      pos = (pos + 1) & mask;
+    }
+  }
+}
+
+// After all inserts of the chunk: does `mine` own its key's slot?
+template <bool kInl>
+__device__ __forceinline__ bool table_is_winner(const uint64_t* slots, const uint64_t* sref, uint64_t pos,
+                                                uint64_t mine) {
+  return kInl ? sref[pos] == mine : slots[pos] == mine;
+}
+
+// The winner's key is now stored as `row`.
+template <int W, bool kInl>
+__device__ __forceinline__ void table_publish(uint64_t* slots, uint64_t* sref, uint64_t pos,
+                                              const uint64_t (&key)[W], uint64_t row) {
+  if constexpr (kInl)
+    sref[pos] = kEmpty;  // the key is in the slot already
+  else
+    slots[pos] = (fingerprint(hash_key<W>(key)) << kRowBits) | row;
+}
+
+// Stores a row's key during a rebuild (all keys distinct).
+template <int W, bool kInl>
+__device__ __forceinline__ void table_rebuild_one(uint64_t* slots, uint64_t mask, const uint64_t (&key)[W],
+                                                  uint64_t row) {
+  const uint64_t h = hash_key<W>(key);
+  const uint64_t v = kInl ? key[0] : ((fingerprint(h) << kRowBits) | row);
+  uint64_t pos = h & mask;
+  while (atomicCAS((unsigned long long*)&slots[pos], (unsigned long long)kEmpty, (unsigned long long)v) !=
+         kEmpty)
+    pos = (pos + 1) & mask;
+}
+
+// Where a generator probes: the cache rows and the dedup table, and the
+// precision masks.
 struct Probe {
   const uint64_t* rows;
   const uint64_t* slots;
@@ -79,31 +196,11 @@ struct Sink {
 // if it is not stored yet; survivors that satisfy the specification (at most
 // max_err misclassified examples) lower answer_e.  Must be called by every
 // lane of the wave.
-template <int W>
+template <int W, bool kInl>
 __device__ __forceinline__ void filter_emit(const Probe& a, const Sink& o, bool valid, bool known_dup,
                                             const uint64_t (&key)[W], uint32_t e_rel) {
   bool surv = false;
-  if (valid && !known_dup) {
-    const uint64_t h = hash_key<W>(key);
-    const uint64_t fp = fingerprint(h);
-    uint64_t pos = h & a.slot_mask;
-    surv = true;
-    for (;;) {
-      const uint64_t v = a.slots[pos];
-      if (v == kEmpty) break;
-      if (((v >> kRowBits) & 0xFFFFFFull) == fp) {
-        const uint64_t* r = a.rows + (v & kRowMask) * W;
-        bool eq = true;
-#pragma unroll
-        for (int k = 0; k < W; ++k) eq = eq && (r[k] == key[k]);
-        if (eq) {
-          surv = false;
-          break;
-        }
-      }
-      pos = (pos + 1) & a.slot_mask;
-    }
-  }
+  if (valid && !known_dup) surv = !table_find<W, kInl>(a.slots, a.slot_mask, a.rows, key, hash_key<W>(key));
   const uint64_t m = __ballot(surv);
   if (m == 0) return;
   const uint32_t lane = lane_id();
@@ -138,18 +235,6 @@ __device__ __forceinline__ void tri_decode(uint64_t e, uint64_t n, uint64_t* pi,
   while ((uint64_t)(i + 1) < n && first(i + 1) <= e) ++i;
   *pi = (uint64_t)i;
   *pj = (uint64_t)i + 1 + (e - first(i));
-}
-
-template <int W>
-__device__ __forceinline__ bool key_eq(const uint64_t* p, const uint64_t (&key)[W]) {
-  bool eq = true;
-#pragma unroll
-  for (int k = 0; k < W; ++k) eq = eq && p[k] == key[k];
-  return eq;
-}
-
-__device__ __forceinline__ uint64_t new_ref(uint32_t e, uint32_t sid) {
-  return kNewFlag | ((uint64_t)e << 32) | sid;
 }
 
 }  // namespace

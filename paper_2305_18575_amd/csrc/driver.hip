@@ -70,7 +70,9 @@ struct rei_instance {
   uint64_t rows_alloc = 0;
   // dedup table
   uint64_t* d_slots = nullptr;
+  uint64_t* d_sref = nullptr;  // inline-key table only
   uint64_t slots_cap = 0;
+  bool inl = false;            // one word per language and |ic| <= 63: keys live in the slots
   // chunk buffers
   uint64_t* d_skey = nullptr;
   uint32_t* d_se = nullptr;
@@ -217,12 +219,16 @@ rei_status ensure_table(rei_instance* in, uint64_t entries, hipStream_t s, bool 
   if (force && in->slots_cap >= cap) cap = in->slots_cap;
   if (cap != in->slots_cap) {
     dfree(in->d_slots);
+    dfree(in->d_sref);
+    in->slots_cap = 0;
     HIP_OK(in, hipMalloc(&in->d_slots, cap * 8));
+    if (in->inl) HIP_OK(in, hipMalloc(&in->d_sref, cap * 8));
     in->slots_cap = cap;
   }
   LAUNCH(in, s, REI_K_OTHER, cap, launch_fill(in->d_slots, cap, kEmpty, s));
+  if (in->inl) LAUNCH(in, s, REI_K_OTHER, cap, launch_fill(in->d_sref, cap, kEmpty, s));
   LAUNCH(in, s, REI_K_OTHER, in->known_rows,
-         launch_rehash(in->st.W, in->d_rows, in->known_rows, in->d_slots, cap - 1, s));
+         launch_rehash(in->st.W, in->inl, in->d_rows, in->known_rows, in->d_slots, cap - 1, s));
   return REI_OK;
 }
 
@@ -345,6 +351,7 @@ rei_status enqueue_chunk(rei_instance* in, hipStream_t s, uint32_t c, const Bloc
   g.e1 = e1;
   g.char_index = in->d_char_index;
   g.st = in->d_state;
+  g.inl = in->inl ? 1u : 0u;
   if (b.op != OP_CHAR) {
     g.lstart = in->lstart[b.L];
     g.lcount = in->lcount[b.L];
@@ -360,6 +367,8 @@ rei_status enqueue_chunk(rei_instance* in, hipStream_t s, uint32_t c, const Bloc
   ca.rows_w = in->d_rows;
   ca.aux = in->d_aux;
   ca.slots = in->d_slots;
+  ca.sref = in->d_sref;
+  ca.inl = in->inl ? 1u : 0u;
   ca.slot_mask = in->slots_cap - 1;
   ca.skey = in->d_skey;
   ca.se = in->d_se;
@@ -642,7 +651,8 @@ struct BatchRun {
   hipStream_t s = nullptr;
   double t0 = 0;
   std::vector<rei_instance*> grid;                    // per-chunk path afterwards
-  std::vector<rei_instance*> members[kBatchMaxW + 1];  // batched, by word width
+  // batched, by group: index 0 = one word with keys inline, else W
+  std::vector<rei_instance*> members[kBatchMaxW + 1];
   std::vector<rei_instance*> finished;                // results complete
   std::vector<BatchDesc*> dbufs;
   rei_instance* pin = nullptr;  // holds the batched launches' timings
@@ -675,6 +685,8 @@ BatchDesc make_desc(const rei_instance* in) {
   d.rows_alloc = in->rows_alloc;
   d.row_cap = in->row_cap;
   d.slots = in->d_slots;
+  d.sref = in->d_sref;
+  d.inl = in->inl ? 1u : 0u;
   d.slot_mask = in->slots_cap - 1;
   d.skey = in->d_skey;
   d.se = in->d_se;
@@ -718,24 +730,25 @@ rei_status batch_launch(rei_instance* const* insts, size_t n, hipStream_t s, uin
     if ((r = ensure_chunk_buffers(in, kBatchChunk)) != REI_OK) return r;
     if ((r = ensure_rows(in, R, s)) != REI_OK) return r;
     if ((r = ensure_table(in, in->rows_alloc + kBatchChunk, s, false)) != REI_OK) return r;
-    groups[in->st.W].push_back(make_desc(in));
-    run->members[in->st.W].push_back(in);
+    const int g = in->inl ? 0 : in->st.W;
+    groups[g].push_back(make_desc(in));
+    run->members[g].push_back(in);
   }
   run->pin = n ? insts[0] : nullptr;
   run->rec_first = run->pin ? run->pin->recs.size() : 0;
-  for (int W = 1; W <= kBatchMaxW; W *= 2) {
-    if (groups[W].empty()) continue;
-    rei_instance* in0 = run->members[W][0];
+  for (int g = 0; g <= kBatchMaxW; g = g ? 2 * g : 1) {
+    if (groups[g].empty()) continue;
+    rei_instance* in0 = run->members[g][0];
     BatchDesc* dd = nullptr;
-    HIP_OK(in0, hipMalloc(&dd, groups[W].size() * sizeof(BatchDesc)));
+    HIP_OK(in0, hipMalloc(&dd, groups[g].size() * sizeof(BatchDesc)));
     run->dbufs.push_back(dd);
-    HIP_OK(in0, hipMemcpyAsync(dd, groups[W].data(), groups[W].size() * sizeof(BatchDesc),
+    HIP_OK(in0, hipMemcpyAsync(dd, groups[g].data(), groups[g].size() * sizeof(BatchDesc),
                                hipMemcpyHostToDevice, s));
     hipEvent_t ev = nullptr;
     if ((r = prof_begin(run->pin, s, &ev)) != REI_OK) return r;
-    HIP_OK(in0, launch_solve_batch(W, dd, (uint32_t)groups[W].size(), s));
+    HIP_OK(in0, launch_solve_batch(g ? g : 1, g == 0, dd, (uint32_t)groups[g].size(), s));
     if ((r = prof_end(run->pin, s, REI_K_BATCH, ev, 0)) != REI_OK) return r;
-    if (run->pin->prof) run->rec_w.push_back(W);
+    if (run->pin->prof) run->rec_w.push_back(g);
   }
   return REI_OK;
 }
@@ -748,11 +761,11 @@ rei_status batch_collect(BatchRun* run) {
   run->dbufs.clear();
   uint64_t group_cand[kBatchMaxW + 1] = {0};
   std::vector<rei_instance*> done;
-  for (int W = 1; W <= kBatchMaxW; W *= 2)
-    for (rei_instance* in : run->members[W]) {
+  for (int g = 0; g <= kBatchMaxW; g = g ? 2 * g : 1)
+    for (rei_instance* in : run->members[g]) {
       if ((r = sync_state(in, run->s)) != REI_OK) return r;
       const uint64_t L = in->max_cost + 2;
-      for (uint64_t c = 0; c < L; ++c) group_cand[W] += in->h_levels[2 * L + c];
+      for (uint64_t c = 0; c < L; ++c) group_cand[g] += in->h_levels[2 * L + c];
       if (in->h_state->stop == STOP_CAPACITY)
         run->grid.push_back(in);
       else
@@ -778,6 +791,7 @@ void free_device(rei_instance* in) {
   dfree(in->d_rows);
   dfree(in->d_aux);
   dfree(in->d_slots);
+  dfree(in->d_sref);
   dfree(in->d_skey);
   dfree(in->d_se);
   dfree(in->d_spos);
@@ -867,6 +881,7 @@ rei_status rei_create(const char* alphabet, const char* const* pos, size_t n_pos
   in->max_cost = max_cost;
   in->cache_bytes = cache_bytes;
   in->row_cap = cache_bytes / (8ull * in->st.W + 8);
+  in->inl = in->st.W == 1 && in->st.n <= 63;
   if ((st = create_device(in)) != REI_OK) {
     g_create_error = in->err;
     free_device(in);
@@ -998,12 +1013,13 @@ rei_status rei_set_max_errors(rei_instance* inst, uint32_t max_errors) {
 
 rei_status rei_set_profiling(rei_instance* inst, int enable) {
   if (!inst) return REI_ERR_INVALID_ARG;
+  if (enable && !inst->prof)
+    for (int k = 0; k < REI_K_COUNT; ++k) {
+      inst->st_launch[k] = 0;
+      inst->st_ms[k] = 0;
+      inst->st_units[k] = 0;
+    }
   inst->prof = enable != 0;
-  for (int k = 0; k < REI_K_COUNT; ++k) {
-    inst->st_launch[k] = 0;
-    inst->st_ms[k] = 0;
-    inst->st_units[k] = 0;
-  }
   return REI_OK;
 }
 

@@ -100,6 +100,7 @@ struct GenArgs {
   uint64_t rstart, rcount;    // right operand level
   const int32_t* char_index;  // base level only
   const DevState* st;
+  uint32_t inl;               // inline-key table (one word per language, |ic| <= 63)
 };
 
 struct ChunkArgs {
@@ -107,7 +108,9 @@ struct ChunkArgs {
   uint64_t* rows_w;
   uint64_t* aux;
   uint64_t* slots;
+  uint64_t* sref;             // inline-key table: smallest survivor per slot
   uint64_t slot_mask;
+  uint32_t inl;
   uint64_t* skey;
   uint32_t* se;
   uint64_t* spos;             // slot of each survivor after insertion
@@ -128,7 +131,7 @@ struct ChunkArgs {
 // Kernel launchers (kernels.hip).  Every launcher returns the hipError_t of
 // the launch.
 hipError_t launch_fill(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
-hipError_t launch_rehash(int W, const uint64_t* rows, uint64_t nrows, uint64_t* slots,
+hipError_t launch_rehash(int W, bool inl, const uint64_t* rows, uint64_t nrows, uint64_t* slots,
                          uint64_t slot_mask, hipStream_t s);
 hipError_t launch_gen(int W, int op, const GenArgs& a, bool same_level, hipStream_t s);
 hipError_t launch_insert(int W, const ChunkArgs& a, hipStream_t s);
@@ -161,7 +164,9 @@ struct BatchDesc {
   uint64_t rows_alloc;        // rows the buffers hold
   uint64_t row_cap;           // rows the cache budget allows
   uint64_t* slots;
+  uint64_t* sref;
   uint64_t slot_mask;         // table holds rows_alloc + kBatchChunk entries at load <= 1/2
+  uint32_t inl, pad2;
   uint64_t* skey;             // kBatchChunk survivors
   uint32_t* se;
   uint64_t* spos;
@@ -172,6 +177,6 @@ struct BatchDesc {
 };
 
 // Launches one workgroup per descriptor (all with the same W).
-hipError_t launch_solve_batch(int W, const BatchDesc* d_descs, uint32_t n, hipStream_t s);
+hipError_t launch_solve_batch(int W, bool inl, const BatchDesc* d_descs, uint32_t n, hipStream_t s);
 
 }  // namespace rei

@@ -26,17 +26,17 @@ namespace rei {
 namespace {
 
 // Probe the table and append survivors (see filter_emit in device_common.h).
-template <int W>
+template <int W, bool kInl>
 __device__ __forceinline__ void filter_emit(const GenArgs& a, bool valid, bool known_dup,
                                             const uint64_t (&key)[W], uint32_t e_rel) {
   const Probe p{a.rows, a.slots, a.slot_mask, a.pmask, a.nmask, a.max_err};
   const Sink k{a.skey, a.se, &a.ctrl->n_surv, &a.ctrl->answer_e};
-  filter_emit<W>(p, k, valid, known_dup, key, e_rel);
+  filter_emit<W, kInl>(p, k, valid, known_dup, key, e_rel);
 }
 
 // ---- generators -----------------------------------------------------------
 
-template <int W>
+template <int W, bool kInl>
 __global__ __launch_bounds__(256) void gen_char(GenArgs a) {
   if (a.st->stop) return;
   const uint64_t e = a.e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -45,11 +45,11 @@ __global__ __launch_bounds__(256) void gen_char(GenArgs a) {
   const int idx = valid ? a.char_index[e] : -1;
 #pragma unroll
   for (int k = 0; k < W; ++k) key[k] = (idx >= 0 && (idx >> 6) == k) ? (1ull << (idx & 63)) : 0ull;
-  filter_emit<W>(a, valid, false, key, (uint32_t)(e - a.e0));
+  filter_emit<W, kInl>(a, valid, false, key, (uint32_t)(e - a.e0));
 }
 
 // r? = eps + r; eps is word 0 of ic (shortlex puts the empty word first).
-template <int W>
+template <int W, bool kInl>
 __global__ __launch_bounds__(256) void gen_question(GenArgs a) {
   if (a.st->stop) return;
   const uint64_t e = a.e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -60,13 +60,13 @@ __global__ __launch_bounds__(256) void gen_question(GenArgs a) {
   for (int k = 0; k < W; ++k) key[k] = valid ? src[k] : 0ull;
   const bool dup = (key[0] & 1ull) != 0;  // already contains eps: r? = r
   key[0] |= 1ull;
-  filter_emit<W>(a, valid, dup, key, (uint32_t)(e - a.e0));
+  filter_emit<W, kInl>(a, valid, dup, key, (uint32_t)(e - a.e0));
 }
 
 // r* for 64 rows per workgroup, bit-sliced: Xt[w] / Yt[w] hold bit t = row t's
 // membership of word w.  Y(eps) = 1 and, by increasing length,
 // Y(w) = OR over cuts w = u v with u non-empty of X(u) & Y(v) (v is shorter).
-template <int W>
+template <int W, bool kInl>
 __global__ __launch_bounds__(256) void gen_star(GenArgs a) {
   __shared__ uint64_t Xt[64 * W];
   __shared__ uint64_t Yt[64 * W];
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void gen_star(GenArgs a) {
 #pragma unroll
     for (int k = 0; k < W; ++k) key[k] = transpose64(Yt[64 * k + lane]);
     const uint64_t e = base + lane;
-    filter_emit<W>(a, e < a.e1, false, key, (uint32_t)(e - a.e0));
+    filter_emit<W, kInl>(a, e < a.e1, false, key, (uint32_t)(e - a.e0));
   }
 }
 
@@ -114,10 +114,13 @@ constexpr int kConcatYT = 8;
 // kShort: every word has at most 32 cuts (length <= 31), so the cuts whose
 // prefix is in x fit one 32-bit mask per output word; otherwise the prefix
 // bit is tested inside the fold.
-template <int W, bool kShort>
+// kGtLds: the guide table is staged in LDS.  The choice is made at compile
+// time so that every access has a fixed address space: reading LDS through a
+// generic pointer (chosen at run time between LDS and global memory) gave
+// wrong prefix bits now and then on gfx950.
+template <int W, bool kShort, bool kInl, bool kGtLds>
 __global__ __launch_bounds__(256) void gen_concat(GenArgs a, uint32_t yt_per_wg, uint32_t xi_per_wg,
-                                                  uint64_t i_lo, uint64_t i_hi, uint32_t gt_lds,
-                                                  uint32_t n_tile_groups) {
+                                                  uint64_t i_lo, uint64_t i_hi, uint32_t n_tile_groups) {
   extern __shared__ uint64_t lds[];
   if (a.st->stop) return;
   uint64_t* Yt = lds;                                        // [yt_per_wg][64W]
@@ -141,10 +144,14 @@ __global__ __launch_bounds__(256) void gen_concat(GenArgs a, uint32_t yt_per_wg,
   }
   for (uint32_t q = threadIdx.x; q < nx * W; q += 256)
     Xs[q] = a.rows[(a.lstart + x0 + q / W) * W + q % W];
-  if (gt_lds)
+  if constexpr (kGtLds)
     for (uint32_t q = threadIdx.x; q < a.n_pairs; q += 256) G[q] = a.gt_pair[q];
   __syncthreads();
-  const uint32_t* gp = gt_lds ? G : a.gt_pair;
+  const uint32_t* gp;
+  if constexpr (kGtLds)
+    gp = G;
+  else
+    gp = a.gt_pair;
 
   // cut ranges of this lane's words
   uint32_t off[W], cnt[W];
@@ -194,12 +201,12 @@ __global__ __launch_bounds__(256) void gen_concat(GenArgs a, uint32_t yt_per_wg,
       const uint64_t j = (t0 + tq) * 64 + lane;
       const uint64_t e = i * nR + j;
       const bool valid = (j < nR) && (e >= a.e0) && (e < a.e1);
-      filter_emit<W>(a, valid, false, key, (uint32_t)(e - a.e0));
+      filter_emit<W, kInl>(a, valid, false, key, (uint32_t)(e - a.e0));
     }
   }
 }
 
-template <int W, bool kSame>
+template <int W, bool kSame, bool kInl>
 __global__ __launch_bounds__(256) void gen_union(GenArgs a) {
   if (a.st->stop) return;
   const uint64_t e = a.e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -225,7 +232,7 @@ __global__ __launch_bounds__(256) void gen_union(GenArgs a) {
     eqy = eqy && key[k] == yv;
   }
   // x+y equals x or y (one contains the other): that language is stored
-  filter_emit<W>(a, valid, eqx || eqy, key, (uint32_t)(e - a.e0));
+  filter_emit<W, kInl>(a, valid, eqx || eqy, key, (uint32_t)(e - a.e0));
 }
 
 // ---- chunk pipeline ------------------------------------------------------
@@ -259,7 +266,7 @@ __global__ void state_reset(Ctrl* c, DevState* st, uint64_t row_cap) {
   st->answer_e = 0;
 }
 
-template <int W>
+template <int W, bool kInl>
 __global__ __launch_bounds__(256) void rehash_rows(const uint64_t* rows, uint64_t nrows, uint64_t* slots,
                                                    uint64_t mask) {
   for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows;
@@ -267,16 +274,11 @@ __global__ __launch_bounds__(256) void rehash_rows(const uint64_t* rows, uint64_
     uint64_t key[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) key[k] = rows[r * W + k];
-    const uint64_t h = hash_key<W>(key);
-    const uint64_t mine = (fingerprint(h) << kRowBits) | r;
-    uint64_t pos = h & mask;
-    while (atomicCAS((unsigned long long*)&slots[pos], (unsigned long long)kEmpty,
-                     (unsigned long long)mine) != kEmpty)
-      pos = (pos + 1) & mask;
+    table_rebuild_one<W, kInl>(slots, mask, key, r);
   }
 }
 
-template <int W>
+template <int W, bool kInl>
 __global__ __launch_bounds__(256) void insert_survivors(ChunkArgs a) {
   if (a.st->stop) return;
   const uint32_t ns = a.ctrl->n_surv;
@@ -284,29 +286,8 @@ __global__ __launch_bounds__(256) void insert_survivors(ChunkArgs a) {
     uint64_t key[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) key[k] = a.skey[(uint64_t)sid * W + k];
-    const uint64_t h = hash_key<W>(key);
-    const uint64_t fp = fingerprint(h);
-    const uint64_t mine = new_ref(a.se[sid], sid);
-    uint64_t pos = h & a.slot_mask;
-    for (;;) {
-      uint64_t v = a.slots[pos];
-      if (v == kEmpty) {
-        v = atomicCAS((unsigned long long*)&a.slots[pos], (unsigned long long)kEmpty,
-                      (unsigned long long)mine);
-        if (v == kEmpty) break;  // claimed
-      }
-      if (v & kNewFlag) {
-        // another survivor owns the slot; its key never changes
-        if (key_eq<W>(a.skey + (uint64_t)(uint32_t)v * W, key)) {
-          atomicMin((unsigned long long*)&a.slots[pos], (unsigned long long)mine);
-          break;
-        }
-      } else if (((v >> kRowBits) & 0xFFFFFFull) == fp && key_eq<W>(a.rows + (v & kRowMask) * W, key)) {
-        break;  // stored already (the generator filters these; kept for safety)
-      }
-      pos = (pos + 1) & a.slot_mask;
-    }
-    a.spos[sid] = pos;
+    a.spos[sid] = table_insert<W, kInl>(a.slots, a.sref, a.slot_mask, a.rows, a.skey, key, hash_key<W>(key),
+                                        new_ref(a.se[sid], sid));
   }
 }
 
@@ -348,7 +329,7 @@ __device__ void account_chunk(const ChunkArgs& a, uint32_t ans, uint32_t answer_
   ctrl_clear(a.ctrl);
 }
 
-template <int W>
+template <int W, bool kInl>
 __device__ __forceinline__ void store_winner(const ChunkArgs& a, uint32_t sid, uint32_t e, uint64_t row) {
   uint64_t key[W];
 #pragma unroll
@@ -357,14 +338,14 @@ __device__ __forceinline__ void store_winner(const ChunkArgs& a, uint32_t sid, u
     a.rows_w[row * W + k] = key[k];
   }
   a.aux[row] = a.chunk_e0 + e;
-  a.slots[a.spos[sid]] = (fingerprint(hash_key<W>(key)) << kRowBits) | row;
+  table_publish<W, kInl>(a.slots, a.sref, a.spos[sid], key, row);
 }
 
 constexpr uint32_t kSmallWords = (uint32_t)(kSmallChunk / 32);
 
 // Whole finalization of a small chunk in one workgroup: winner bitmap in LDS,
 // its prefix scan, ordered append, accounting.
-template <int W>
+template <int W, bool kInl>
 __global__ __launch_bounds__(1024) void finalize_small(ChunkArgs a) {
   __shared__ uint32_t bm[kSmallWords];
   __shared__ uint32_t pre[kSmallWords];
@@ -382,7 +363,8 @@ __global__ __launch_bounds__(1024) void finalize_small(ChunkArgs a) {
   __syncthreads();
   for (uint32_t sid = t; sid < ns; sid += 1024) {
     const uint32_t e = a.se[sid];
-    if (a.slots[a.spos[sid]] == new_ref(e, sid)) atomicOr(&bm[e >> 5], 1u << (e & 31));
+    if (table_is_winner<kInl>(a.slots, a.sref, a.spos[sid], new_ref(e, sid)))
+      atomicOr(&bm[e >> 5], 1u << (e & 31));
   }
   __syncthreads();
   const uint32_t v = (t < words) ? (uint32_t)__popc(bm[t]) : 0u;
@@ -408,7 +390,7 @@ __global__ __launch_bounds__(1024) void finalize_small(ChunkArgs a) {
     if (e == ans) s_rank = rank;
     if (ans != ~0u && e >= ans) continue;  // the answer and later ones are not stored
     if (rank < room)
-      store_winner<W>(a, sid, e, row_base + rank);
+      store_winner<W, kInl>(a, sid, e, row_base + rank);
     else if (rank == room)
       s_over = e;
   }
@@ -418,12 +400,14 @@ __global__ __launch_bounds__(1024) void finalize_small(ChunkArgs a) {
 
 // ---- grid path for large chunks ----
 
+template <bool kInl>
 __global__ __launch_bounds__(256) void mark_winners(ChunkArgs a) {
   if (a.st->stop) return;
   const uint32_t ns = a.ctrl->n_surv;
   for (uint32_t sid = blockIdx.x * blockDim.x + threadIdx.x; sid < ns; sid += gridDim.x * blockDim.x) {
     const uint32_t e = a.se[sid];
-    if (a.slots[a.spos[sid]] == new_ref(e, sid)) atomicOr(&a.bitmap[e >> 5], 1u << (e & 31));
+    if (table_is_winner<kInl>(a.slots, a.sref, a.spos[sid], new_ref(e, sid)))
+      atomicOr(&a.bitmap[e >> 5], 1u << (e & 31));
   }
 }
 
@@ -499,7 +483,7 @@ __global__ __launch_bounds__(256) void scan_down(ChunkArgs a) {
   }
 }
 
-template <int W>
+template <int W, bool kInl>
 __global__ __launch_bounds__(256) void compact_winners(ChunkArgs a) {
   if (a.st->stop) return;
   const uint32_t ns = a.ctrl->n_surv;
@@ -515,7 +499,7 @@ __global__ __launch_bounds__(256) void compact_winners(ChunkArgs a) {
     if (e == ans) a.ctrl->answer_rank = rank;
     if (ans != ~0u && e >= ans) continue;
     if (rank < room)
-      store_winner<W>(a, sid, e, row_base + rank);
+      store_winner<W, kInl>(a, sid, e, row_base + rank);
     else if (rank == room)
       a.ctrl->overflow_e = e;
   }
@@ -533,7 +517,7 @@ inline uint32_t grid_for(uint64_t n, uint32_t block, uint32_t cap = 0x7fffffffu)
   return (uint32_t)g;
 }
 
-template <int W>
+template <int W, bool kInl>
 hipError_t launch_concat_w(const GenArgs& a, hipStream_t s) {
   const uint64_t nR = a.rcount;
   const uint64_t i_lo = a.e0 / nR, i_hi = (a.e1 - 1) / nR;
@@ -552,35 +536,42 @@ hipError_t launch_concat_w(const GenArgs& a, hipStream_t s) {
   const uint64_t gx = (nT + yt - 1) / yt, gy = (rowsx + xi - 1) / xi;
   if (gx * gy > 0x7fffffffull) return hipErrorInvalidConfiguration;
   const dim3 grid((uint32_t)(gx * gy));
-  if (a.max_len < 32)
-    hipLaunchKernelGGL((gen_concat<W, true>), grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi, gt_lds,
+  const bool shrt = a.max_len < 32;
+  if (shrt && gt_lds)
+    hipLaunchKernelGGL((gen_concat<W, true, kInl, true>), grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
+                       (uint32_t)gx);
+  else if (shrt)
+    hipLaunchKernelGGL((gen_concat<W, true, kInl, false>), grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
+                       (uint32_t)gx);
+  else if (gt_lds)
+    hipLaunchKernelGGL((gen_concat<W, false, kInl, true>), grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
                        (uint32_t)gx);
   else
-    hipLaunchKernelGGL((gen_concat<W, false>), grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi, gt_lds,
+    hipLaunchKernelGGL((gen_concat<W, false, kInl, false>), grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
                        (uint32_t)gx);
   return hipGetLastError();
 }
 
-template <int W>
+template <int W, bool kInl>
 hipError_t launch_gen_w(int op, const GenArgs& a, bool same_level, hipStream_t s) {
   const uint64_t cnt = a.e1 - a.e0;
   switch (op) {
     case OP_CHAR:
-      hipLaunchKernelGGL(gen_char<W>, dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((gen_char<W, kInl>), dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
       break;
     case OP_QUESTION:
-      hipLaunchKernelGGL(gen_question<W>, dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((gen_question<W, kInl>), dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
       break;
     case OP_STAR:
-      hipLaunchKernelGGL(gen_star<W>, dim3(grid_for(cnt, 64)), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((gen_star<W, kInl>), dim3(grid_for(cnt, 64)), dim3(256), 0, s, a);
       break;
     case OP_CONCAT:
-      return launch_concat_w<W>(a, s);
+      return launch_concat_w<W, kInl>(a, s);
     case OP_UNION:
       if (same_level)
-        hipLaunchKernelGGL((gen_union<W, true>), dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((gen_union<W, true, kInl>), dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
       else
-        hipLaunchKernelGGL((gen_union<W, false>), dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((gen_union<W, false, kInl>), dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
       break;
     default:
       return hipErrorInvalidValue;
@@ -590,15 +581,26 @@ hipError_t launch_gen_w(int op, const GenArgs& a, bool same_level, hipStream_t s
 
 }  // namespace
 
-#define REI_DISPATCH_W(W, CALL)                          \
-  switch (W) {                                           \
-    case 1: { constexpr int kW = 1; CALL; } break;       \
-    case 2: { constexpr int kW = 2; CALL; } break;       \
-    case 4: { constexpr int kW = 4; CALL; } break;       \
-    case 8: { constexpr int kW = 8; CALL; } break;       \
-    case 16: { constexpr int kW = 16; CALL; } break;     \
-    case 32: { constexpr int kW = 32; CALL; } break;     \
-    default: return hipErrorInvalidValue;                \
+// W words per language; inl selects the inline-key table (only with W = 1).
+#define REI_DISPATCH_WI(W, INL, CALL)                                        \
+  switch (W) {                                                               \
+    case 1:                                                                  \
+      if (INL) {                                                             \
+        constexpr int kW = 1;                                                \
+        constexpr bool kI = true;                                            \
+        CALL;                                                                \
+      } else {                                                               \
+        constexpr int kW = 1;                                                \
+        constexpr bool kI = false;                                           \
+        CALL;                                                                \
+      }                                                                      \
+      break;                                                                 \
+    case 2: { constexpr int kW = 2; constexpr bool kI = false; CALL; } break;   \
+    case 4: { constexpr int kW = 4; constexpr bool kI = false; CALL; } break;   \
+    case 8: { constexpr int kW = 8; constexpr bool kI = false; CALL; } break;   \
+    case 16: { constexpr int kW = 16; constexpr bool kI = false; CALL; } break; \
+    case 32: { constexpr int kW = 32; constexpr bool kI = false; CALL; } break; \
+    default: return hipErrorInvalidValue;                                    \
   }
 
 hipError_t launch_fill(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
@@ -612,40 +614,43 @@ hipError_t launch_state_reset(Ctrl* c, DevState* st, uint64_t row_cap, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_rehash(int W, const uint64_t* rows, uint64_t nrows, uint64_t* slots,
+hipError_t launch_rehash(int W, bool inl, const uint64_t* rows, uint64_t nrows, uint64_t* slots,
                          uint64_t slot_mask, hipStream_t s) {
   if (nrows == 0) return hipSuccess;
-  REI_DISPATCH_W(W, hipLaunchKernelGGL(rehash_rows<kW>, dim3(grid_for(nrows, 256, 65536)),
-                                       dim3(256), 0, s, rows, nrows, slots, slot_mask));
+  REI_DISPATCH_WI(W, inl, hipLaunchKernelGGL((rehash_rows<kW, kI>), dim3(grid_for(nrows, 256, 65536)),
+                                             dim3(256), 0, s, rows, nrows, slots, slot_mask));
   return hipGetLastError();
 }
 
 hipError_t launch_gen(int W, int op, const GenArgs& a, bool same_level, hipStream_t s) {
   if (a.e1 <= a.e0) return hipSuccess;
-  REI_DISPATCH_W(W, return launch_gen_w<kW>(op, a, same_level, s));
+  REI_DISPATCH_WI(W, a.inl, return (launch_gen_w<kW, kI>(op, a, same_level, s)));
   return hipGetLastError();
 }
 
 hipError_t launch_insert(int W, const ChunkArgs& a, hipStream_t s) {
-  REI_DISPATCH_W(W, hipLaunchKernelGGL(insert_survivors<kW>, dim3(grid_for(a.len, 256, 8192)),
-                                       dim3(256), 0, s, a));
+  REI_DISPATCH_WI(W, a.inl, hipLaunchKernelGGL((insert_survivors<kW, kI>), dim3(grid_for(a.len, 256, 8192)),
+                                               dim3(256), 0, s, a));
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(int W, const ChunkArgs& a, hipStream_t s) {
   if (a.len <= kSmallChunk) {
-    REI_DISPATCH_W(W, hipLaunchKernelGGL(finalize_small<kW>, dim3(1), dim3(1024), 0, s, a));
+    REI_DISPATCH_WI(W, a.inl, hipLaunchKernelGGL((finalize_small<kW, kI>), dim3(1), dim3(1024), 0, s, a));
     return hipGetLastError();
   }
   hipLaunchKernelGGL(fill_u32, dim3(grid_for(a.n_bitmap_words, 256, 4096)), dim3(256), 0, s, a.bitmap,
                      (uint64_t)a.n_bitmap_words, 0u);
   const uint32_t g = grid_for(a.len, 256, 8192);
-  hipLaunchKernelGGL(mark_winners, dim3(g), dim3(256), 0, s, a);
+  if (a.inl)
+    hipLaunchKernelGGL(mark_winners<true>, dim3(g), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(mark_winners<false>, dim3(g), dim3(256), 0, s, a);
   const uint32_t nb = (a.n_bitmap_words + kScanBlock - 1) / kScanBlock;
   hipLaunchKernelGGL(scan_reduce, dim3(nb), dim3(256), 0, s, a);
   hipLaunchKernelGGL(scan_top, dim3(1), dim3(1024), 0, s, a, nb);
   hipLaunchKernelGGL(scan_down, dim3(nb), dim3(256), 0, s, a);
-  REI_DISPATCH_W(W, hipLaunchKernelGGL(compact_winners<kW>, dim3(g), dim3(256), 0, s, a));
+  REI_DISPATCH_WI(W, a.inl, hipLaunchKernelGGL((compact_winners<kW, kI>), dim3(g), dim3(256), 0, s, a));
   hipLaunchKernelGGL(account_large, dim3(1), dim3(1), 0, s, a);
   return hipGetLastError();
 }
