@@ -60,17 +60,24 @@ __device__ __forceinline__ void concat_tile(const uint64_t* T, const uint64_t* u
   }
 }
 
+// Threads per instance: 16 waves, or 8 when a language has 8 words (the
+// per-wave operand tiles then stay within 32 KB of LDS).
+template <int W>
+constexpr uint32_t batch_threads() { return W <= 4 ? 1024u : 512u; }
+
 template <int W, bool kInl>
-__global__ __launch_bounds__(256) void solve_batch(const BatchDesc* descs, uint32_t n_inst) {
+__global__ __launch_bounds__(batch_threads<W>()) void solve_batch(const BatchDesc* descs, uint32_t n_inst) {
+  constexpr uint32_t kT = batch_threads<W>();
+  constexpr uint32_t kWaves = kT / 64;
   __shared__ uint64_t s_lstart[kBatchMaxCost + 2], s_lcount[kBatchMaxCost + 2];
   __shared__ BlockD s_blk[kMaxBlocks];
   __shared__ uint32_t s_nblk;
   __shared__ uint32_t s_nsurv, s_ans, s_rank, s_over, s_stop;
   __shared__ uint64_t s_total;
   __shared__ uint32_t s_bm[kWords], s_pre[kWords];
-  __shared__ uint32_t s_sc[256];
-  __shared__ uint64_t s_tile[4][64 * W];
-  __shared__ uint64_t s_uni[4][W];
+  __shared__ uint32_t s_sc[kT];
+  __shared__ uint64_t s_tile[kWaves][64 * W];
+  __shared__ uint64_t s_uni[kWaves][W];
 
   if (blockIdx.x >= n_inst) return;
   const BatchDesc d = descs[blockIdx.x];
@@ -79,16 +86,16 @@ __global__ __launch_bounds__(256) void solve_batch(const BatchDesc* descs, uint3
   const Sink sink{d.skey, d.se, &s_nsurv, &s_ans};
 
   // start: empty table, zero counters
-  for (uint64_t i = tid; i <= d.slot_mask; i += 256) {
+  for (uint64_t i = tid; i <= d.slot_mask; i += kT) {
     d.slots[i] = kEmpty;
     if (kInl) d.sref[i] = kEmpty;
   }
-  for (uint32_t c = tid; c < d.max_cost + 2; c += 256) {
+  for (uint32_t c = tid; c < d.max_cost + 2; c += kT) {
     d.lcount[c] = 0;
     d.uniq[c] = 0;
     d.cand[c] = 0;
   }
-  for (uint32_t c = tid; c < kBatchMaxCost + 2; c += 256) {
+  for (uint32_t c = tid; c < kBatchMaxCost + 2; c += kT) {
     s_lstart[c] = 0;
     s_lcount[c] = 0;
   }
@@ -145,7 +152,7 @@ __global__ __launch_bounds__(256) void solve_batch(const BatchDesc* descs, uint3
 
         // ---- generate and probe
         if (blk.op == OP_CHAR || blk.op == OP_QUESTION || blk.op == OP_UNION) {
-          for (uint64_t base = e0 + 64 * wave; base < e1; base += 256) {
+          for (uint64_t base = e0 + 64 * wave; base < e1; base += kT) {
             const uint64_t e = base + lane;
             const bool valid = e < e1;
             uint64_t key[W];
@@ -188,16 +195,16 @@ __global__ __launch_bounds__(256) void solve_batch(const BatchDesc* descs, uint3
           uint64_t* Xt = s_tile[0];
           uint64_t* Yt = s_tile[1];
           for (uint64_t g0 = e0; g0 < e1; g0 += 64) {
-            for (int k = wave; k < W; k += 4) {
+            for (int k = wave; k < W; k += kWaves) {
               const uint64_t e = g0 + lane;
               const uint64_t v = (e < e1) ? d.rows[(lst + e) * W + k] : 0ull;
               Xt[64 * k + lane] = transpose64(v);
             }
-            for (uint32_t w = tid; w < 64u * W; w += 256) Yt[w] = (w == 0) ? ~0ull : 0ull;
+            for (uint32_t w = tid; w < 64u * W; w += kT) Yt[w] = (w == 0) ? ~0ull : 0ull;
             __syncthreads();
             for (uint32_t l = 1; l <= d.max_len; ++l) {
               const uint32_t lo = d.len_off[l], hi = d.len_off[l + 1];
-              for (uint32_t w = lo + tid; w < hi; w += 256) {
+              for (uint32_t w = lo + tid; w < hi; w += kT) {
                 uint64_t acc = 0;
                 const uint32_t q1 = d.gt_off[w + 1];
                 for (uint32_t q = d.gt_off[w] + 1; q < q1; ++q) {  // cut 0 has u = eps
@@ -226,7 +233,7 @@ __global__ __launch_bounds__(256) void solve_batch(const BatchDesc* descs, uint3
             // right operands across the lanes
             const uint64_t nT = (nR + 63) / 64;
             const uint64_t items = (i_hi - i_lo + 1) * nT;
-            for (uint64_t it = wave; it < items; it += 4) {
+            for (uint64_t it = wave; it < items; it += kWaves) {
               const uint64_t i = i_lo + it / nT, jt = it % nT;
               const uint64_t ef = i * nR + 64 * jt, el = i * nR + min(64 * jt + 64, nR);
               if (el <= e0 || ef >= e1) continue;
@@ -246,7 +253,7 @@ __global__ __launch_bounds__(256) void solve_batch(const BatchDesc* descs, uint3
             // left operands across the lanes (the right level is small)
             const uint64_t it_lo = i_lo / 64, it_hi = i_hi / 64;
             const uint64_t items = (it_hi - it_lo + 1) * nR;
-            for (uint64_t it = wave; it < items; it += 4) {
+            for (uint64_t it = wave; it < items; it += kWaves) {
               const uint64_t xt = it_lo + it / nR, j = it % nR;
               const uint64_t ef = (64 * xt) * nR + j, el = (64 * xt + 63) * nR + j;
               if (el < e0 || ef >= e1) continue;
@@ -268,7 +275,7 @@ __global__ __launch_bounds__(256) void solve_batch(const BatchDesc* descs, uint3
 
         // ---- insert survivors
         const uint32_t ns = s_nsurv;
-        for (uint32_t sid = tid; sid < ns; sid += 256) {
+        for (uint32_t sid = tid; sid < ns; sid += kT) {
           uint64_t key[W];
 #pragma unroll
           for (int k = 0; k < W; ++k) key[k] = d.skey[(uint64_t)sid * W + k];
@@ -279,9 +286,9 @@ __global__ __launch_bounds__(256) void solve_batch(const BatchDesc* descs, uint3
 
         // ---- winners, ranks, ordered append, accounting
         const uint32_t words = (len + 31) / 32;
-        for (uint32_t i = tid; i < words; i += 256) s_bm[i] = 0;
+        for (uint32_t i = tid; i < words; i += kT) s_bm[i] = 0;
         __syncthreads();
-        for (uint32_t sid = tid; sid < ns; sid += 256) {
+        for (uint32_t sid = tid; sid < ns; sid += kT) {
           const uint32_t e = d.se[sid];
           if (table_is_winner<kInl>(d.slots, d.sref, d.spos[sid], new_ref(e, sid)))
             atomicOr(&s_bm[e >> 5], 1u << (e & 31));
@@ -290,20 +297,20 @@ __global__ __launch_bounds__(256) void solve_batch(const BatchDesc* descs, uint3
         const uint32_t v = (tid < words) ? (uint32_t)__popc(s_bm[tid]) : 0u;
         s_sc[tid] = v;
         __syncthreads();
-        for (uint32_t off = 1; off < 256; off <<= 1) {
+        for (uint32_t off = 1; off < kT; off <<= 1) {
           const uint32_t x = (tid >= off) ? s_sc[tid - off] : 0u;
           __syncthreads();
           s_sc[tid] += x;
           __syncthreads();
         }
         if (tid < words) s_pre[tid] = s_sc[tid] - v;
-        const uint32_t winners = s_sc[255];
+        const uint32_t winners = s_sc[kT - 1];
         __syncthreads();
         const uint64_t total = s_total;
         const uint64_t room = d.row_cap > total ? d.row_cap - total : 0;
         const uint64_t alloc_room = d.rows_alloc > total ? d.rows_alloc - total : 0;
         const uint32_t ans = s_ans;
-        for (uint32_t sid = tid; sid < ns; sid += 256) {
+        for (uint32_t sid = tid; sid < ns; sid += kT) {
           const uint32_t e = d.se[sid];
           const uint32_t word = s_bm[e >> 5];
           const uint32_t bit = 1u << (e & 31);
@@ -385,13 +392,13 @@ hipError_t launch_solve_batch(int W, bool inl, const BatchDesc* d_descs, uint32_
   switch (W) {
     case 1:
       if (inl)
-        hipLaunchKernelGGL((solve_batch<1, true>), dim3(n), dim3(256), 0, s, d_descs, n);
+        hipLaunchKernelGGL((solve_batch<1, true>), dim3(n), dim3(batch_threads<1>()), 0, s, d_descs, n);
       else
-        hipLaunchKernelGGL((solve_batch<1, false>), dim3(n), dim3(256), 0, s, d_descs, n);
+        hipLaunchKernelGGL((solve_batch<1, false>), dim3(n), dim3(batch_threads<1>()), 0, s, d_descs, n);
       break;
-    case 2: hipLaunchKernelGGL((solve_batch<2, false>), dim3(n), dim3(256), 0, s, d_descs, n); break;
-    case 4: hipLaunchKernelGGL((solve_batch<4, false>), dim3(n), dim3(256), 0, s, d_descs, n); break;
-    case 8: hipLaunchKernelGGL((solve_batch<8, false>), dim3(n), dim3(256), 0, s, d_descs, n); break;
+    case 2: hipLaunchKernelGGL((solve_batch<2, false>), dim3(n), dim3(batch_threads<2>()), 0, s, d_descs, n); break;
+    case 4: hipLaunchKernelGGL((solve_batch<4, false>), dim3(n), dim3(batch_threads<4>()), 0, s, d_descs, n); break;
+    case 8: hipLaunchKernelGGL((solve_batch<8, false>), dim3(n), dim3(batch_threads<8>()), 0, s, d_descs, n); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -96,6 +96,9 @@ struct rei_instance {
 
   // levels, indexed by cost
   std::vector<uint64_t> lstart, lcount;
+  // host copy of the back-pointers for printing (filled on first use)
+  std::vector<uint64_t> h_aux;
+  bool h_aux_valid = false;
 
   // result
   std::vector<uint64_t> uniq, cand;
@@ -441,9 +444,30 @@ uint32_t row_cost(const rei_instance* in, uint64_t row) {
   return 0;
 }
 
+// Back-pointer of a stored row.  Caches with up to 4M rows are copied to the
+// host in one transfer on first use; larger ones are read row by row.
+rei_status row_aux(rei_instance* in, uint64_t row, uint64_t* e) {
+  if (!in->h_aux_valid) {
+    uint64_t rows = 0;
+    for (uint32_t c = in->costs.c_char; c < in->lcount.size(); ++c) rows += in->lcount[c];
+    if (rows <= (4ull << 20)) {
+      in->h_aux.resize(rows);
+      if (rows) HIP_OK(in, hipMemcpy(in->h_aux.data(), in->d_aux, rows * 8, hipMemcpyDeviceToHost));
+      in->h_aux_valid = true;
+    }
+  }
+  if (in->h_aux_valid && row < in->h_aux.size()) {
+    *e = in->h_aux[row];
+    return REI_OK;
+  }
+  HIP_OK(in, hipMemcpy(e, in->d_aux + row, 8, hipMemcpyDeviceToHost));
+  return REI_OK;
+}
+
 rei_status row_node(rei_instance* in, uint64_t row, Node* nd) {
   uint64_t e = 0;
-  HIP_OK(in, hipMemcpy(&e, in->d_aux + row, 8, hipMemcpyDeviceToHost));
+  rei_status r = row_aux(in, row, &e);
+  if (r != REI_OK) return r;
   const uint32_t c = row_cost(in, row);
   if (!c || !decode(in, c, e, nd)) {
     in->err = "corrupt back-pointer";
@@ -521,6 +545,7 @@ bool begin_solve(rei_instance* in, double t0) {
   in->regex.clear();
   in->known_rows = 0;
   in->pending = 0;
+  in->h_aux_valid = false;
   if (in->max_cost < c1) {
     fill_result(in, REI_NOT_FOUND, 0, 0, t0);
     return true;

@@ -251,3 +251,21 @@ def test_batch_repeat_and_single_agree(rei):
         assert key(a) == key(b) == key(s)
     for h in hs:
         h.close()
+
+
+@pytest.mark.parametrize("seed", [3, 6])
+def test_resolves_stay_exact(rei, seed):
+    """Regression: re-solving one instance (all buffers already large, so no
+    table rebuild between chunks) must stay exact.  These two instances
+    exposed wrong second words of concatenations when the guide table was
+    read from LDS through a generic pointer."""
+    inst = instances.single_instance(seed, (1, 1, 5, 1, 2))
+    spec = (inst.alphabet, inst.pos, inst.neg, inst.costs, inst.max_cost)
+    o = oracle.solve(*spec, threads=8)
+    h = rei.Instance(*spec)
+    for rep in range(10):
+        r = h.solve()
+        assert (r.status, r.cost, r.regex) == (o.status, o.cost, o.regex), rep
+        for c in range(0, inst.max_cost + 1):
+            assert r.unique_at(c) == o.unique[c] and r.candidates_at(c) == o.candidates[c], (rep, c)
+    h.close()
