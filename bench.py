@@ -19,6 +19,7 @@ rate on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -106,6 +107,11 @@ def main():
 
     for _ in range(args.warmup):
         step()
+    # Python's cyclic collector scans every object torch created at import;
+    # a full pass inside the timed region costs tens of milliseconds that
+    # belong to no step.  Objects made so far are moved out of its reach.
+    gc.collect()
+    gc.freeze()
     for h in handles:
         h.set_profiling(True)
     results, elapsed = timed(step, args.steps)

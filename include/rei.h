@@ -108,11 +108,13 @@ typedef struct {
 rei_status rei_solve(rei_instance *inst, void *hip_stream, rei_result *out);
 
 /* Solve n instances together: instances with at most 8 words per language
- * and max_cost <= 63 run in one launch per word width, one workgroup per
- * instance executing the whole level loop on the device (no host round trip
- * per level); the others, and any instance that outgrows its preallocated
- * rows, run rei_solve's path afterwards.  Every result equals what rei_solve
- * returns for that instance.
+ * and max_cost <= 63 run in one launch per word width (the launches run side
+ * by side), one workgroup per instance executing the whole level loop on the
+ * device (no host round trip per level or chunk; the answer's expression
+ * tree is decoded there too); the others, and any instance that outgrows its
+ * preallocated rows or reaches a level of more than 2^20 candidates, run
+ * rei_solve's path afterwards.  Every result equals what rei_solve returns
+ * for that instance.
  *   insts        n distinct instances (each used by this call only).
  *   arena_bytes  device bytes preallocated per batched instance for rows,
  *                back-pointers and table (0 = 16 MiB); capped by the
@@ -179,6 +181,11 @@ rei_status rei_row_regex(rei_instance *inst, uint32_t cost, uint64_t i, char *bu
 /* Largest number of candidates processed per chunk (0 = default).  Results
  * do not depend on it; tests vary it to check that. */
 rei_status rei_set_chunk(rei_instance *inst, uint64_t max_candidates);
+/* Largest level, in candidates, that rei_solve_batch searches inside its
+ * one-workgroup solver (0 = default 2^20).  At a larger level the instance,
+ * with every lower level kept, continues on rei_solve's path.  Results do not
+ * depend on it. */
+rei_status rei_set_batch_level(rei_instance *inst, uint64_t max_candidates);
 /* Misclassified examples allowed (REI with error, Sec. 7); 0 = precise. */
 rei_status rei_set_max_errors(rei_instance *inst, uint32_t max_errors);
 

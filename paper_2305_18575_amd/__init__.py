@@ -29,7 +29,7 @@ KERNEL_CLASSES = ["gen_char", "gen_question", "gen_star", "gen_concat", "gen_uni
 EXPORTS = ["rei_create", "rei_solve", "rei_solve_batch", "rei_server_create", "rei_server_submit",
            "rei_server_poll", "rei_server_destroy", "rei_destroy", "rei_status_str", "rei_last_error",
            "rei_create_error", "rei_ic_word", "rei_level_size", "rei_row_bits",
-           "rei_row_regex", "rei_set_chunk", "rei_set_max_errors", "rei_set_profiling",
+           "rei_row_regex", "rei_set_chunk", "rei_set_batch_level", "rei_set_max_errors", "rei_set_profiling",
            "rei_kernel_stats", "rei_kernel_name"]
 
 
@@ -112,6 +112,8 @@ def load_library():
     lib.rei_row_regex.argtypes = [vp, u32, u64, cp, ctypes.c_size_t]
     lib.rei_set_chunk.restype = ctypes.c_int
     lib.rei_set_chunk.argtypes = [vp, u64]
+    lib.rei_set_batch_level.restype = ctypes.c_int
+    lib.rei_set_batch_level.argtypes = [vp, u64]
     lib.rei_set_max_errors.restype = ctypes.c_int
     lib.rei_set_max_errors.argtypes = [vp, u32]
     lib.rei_set_profiling.restype = ctypes.c_int
@@ -217,6 +219,10 @@ class Instance:
     # ---- tuning / measurement ----
     def set_chunk(self, max_candidates: int):
         self._check(self._lib.rei_set_chunk(self._h, int(max_candidates)))
+
+    def set_batch_level(self, max_candidates: int):
+        """Largest level the batched solver keeps on one workgroup (0 = default)."""
+        self._check(self._lib.rei_set_batch_level(self._h, int(max_candidates)))
 
     def set_max_errors(self, k: int):
         self._check(self._lib.rei_set_max_errors(self._h, int(k)))

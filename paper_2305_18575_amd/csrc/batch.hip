@@ -12,20 +12,19 @@ namespace {
 
 constexpr uint32_t kWords = kBatchChunk / 32;  // winner bitmap words per chunk
 constexpr int kMaxBlocks = 2 + 2 * (int)kBatchMaxCost;
+constexpr uint32_t kTreeMax = kBatchTreeNodes;  // nodes of the answer tree written back
 
 struct BlockD {
   uint32_t op, L, R, same;
   uint64_t count;
 };
 
-// Barrier between phases whose global-memory effects later phases read: the
-// agent-scope fences make plain loads after the barrier see stores and
-// atomics from before it (the vector L1 is not kept coherent with atomics).
-__device__ __forceinline__ void phase_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-}
+// Barrier between phases whose global-memory effects later phases read.  An
+// instance's buffers are touched by its own workgroup only, and all waves of
+// a workgroup run on one CU, so workgroup scope suffices: the barrier makes
+// every store and atomic issued before it visible to every wave after it.
+// (Agent scope would write back and invalidate the whole L2 at each phase.)
+__device__ __forceinline__ void phase_barrier() { __syncthreads(); }
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -60,6 +59,67 @@ __device__ __forceinline__ void concat_tile(const uint64_t* T, const uint64_t* u
   }
 }
 
+// Decodes level index e of level c into its constructor and operands (rows),
+// walking the level's blocks in enumeration order (Q, S, C by left cost, U by
+// left cost); the counts of levels below c are final.  lstart and lcount are
+// the workgroup's level tables in LDS.
+__device__ __forceinline__ bool decode_index(const BatchDesc& d, const uint64_t* lstart, const uint64_t* lcount,
+                                             uint32_t c, uint64_t e, uint32_t* op, uint64_t* a, uint64_t* b) {
+  const int64_t c1 = d.c1, cc = c;
+  auto lc = [&](int64_t k) -> uint64_t { return (k >= c1 && k < cc) ? lcount[k] : 0ull; };
+  *b = 0;
+  if (cc == c1) {
+    *op = OP_CHAR;
+    *a = e;
+    return e < d.nsigma;
+  }
+  uint64_t n = lc(cc - d.c2);
+  if (e < n) {
+    *op = OP_QUESTION;
+    *a = lstart[cc - d.c2] + e;
+    return true;
+  }
+  e -= n;
+  n = lc(cc - d.c3);
+  if (e < n) {
+    *op = OP_STAR;
+    *a = lstart[cc - d.c3] + e;
+    return true;
+  }
+  e -= n;
+  for (int64_t L = c1; cc - (int64_t)d.c4 - L >= c1; ++L) {
+    const int64_t R = cc - d.c4 - L;
+    n = lc(L) * lc(R);
+    if (e < n) {
+      *op = OP_CONCAT;
+      *a = lstart[L] + e / lc(R);
+      *b = lstart[R] + e % lc(R);
+      return true;
+    }
+    e -= n;
+  }
+  for (int64_t L = c1; L <= cc - (int64_t)d.c5 - L; ++L) {
+    const int64_t R = cc - d.c5 - L;
+    const uint64_t x = lc(L), y = lc(R);
+    n = (L < R) ? x * y : (x ? x * (x - 1) / 2 : 0);
+    if (e < n) {
+      *op = OP_UNION;
+      if (L == R) {
+        uint64_t i = 0, j = 0;
+        tri_decode(e, x, &i, &j);
+        *a = lstart[L] + i;
+        *b = lstart[L] + j;
+      } else {
+        *a = lstart[L] + e / y;
+        *b = lstart[R] + e % y;
+      }
+      return true;
+    }
+    e -= n;
+  }
+  return false;
+}
+
 // Threads per instance: 16 waves, or 8 when a language has 8 words (the
 // per-wave operand tiles then stay within 32 KB of LDS).
 template <int W>
@@ -70,9 +130,11 @@ __global__ __launch_bounds__(batch_threads<W>()) void solve_batch(const BatchDes
   constexpr uint32_t kT = batch_threads<W>();
   constexpr uint32_t kWaves = kT / 64;
   __shared__ uint64_t s_lstart[kBatchMaxCost + 2], s_lcount[kBatchMaxCost + 2];
+  __shared__ uint64_t s_uniq[kBatchMaxCost + 2], s_cand[kBatchMaxCost + 2];
   __shared__ BlockD s_blk[kMaxBlocks];
+  __shared__ uint64_t s_bstart[kMaxBlocks + 1];  // level index of each block's first candidate
   __shared__ uint32_t s_nblk;
-  __shared__ uint32_t s_nsurv, s_ans, s_rank, s_over, s_stop;
+  __shared__ uint32_t s_nsurv, s_ans, s_rank, s_over, s_stop, s_resume;
   __shared__ uint64_t s_total;
   __shared__ uint32_t s_bm[kWords], s_pre[kWords];
   __shared__ uint32_t s_sc[kT];
@@ -90,18 +152,16 @@ __global__ __launch_bounds__(batch_threads<W>()) void solve_batch(const BatchDes
     d.slots[i] = kEmpty;
     if (kInl) d.sref[i] = kEmpty;
   }
-  for (uint32_t c = tid; c < d.max_cost + 2; c += kT) {
-    d.lcount[c] = 0;
-    d.uniq[c] = 0;
-    d.cand[c] = 0;
-  }
   for (uint32_t c = tid; c < kBatchMaxCost + 2; c += kT) {
     s_lstart[c] = 0;
     s_lcount[c] = 0;
+    s_uniq[c] = 0;
+    s_cand[c] = 0;
   }
   if (tid == 0) {
     s_total = 0;
     s_stop = STOP_NONE;
+    s_resume = 0;
   }
   phase_barrier();
 
@@ -132,23 +192,41 @@ __global__ __launch_bounds__(batch_threads<W>()) void solve_batch(const BatchDes
         }
       }
       s_nblk = nb;
+      s_bstart[0] = 0;
+      for (uint32_t b = 0; b < nb; ++b) s_bstart[b + 1] = s_bstart[b] + s_blk[b].count;
+      // a level this large is work for the whole device: hand the instance,
+      // with its lower levels stored, to the per-chunk path
+      if (s_bstart[nb] > d.level_max) {
+        s_stop = STOP_HANDOFF;
+        s_resume = c;
+      }
     }
     __syncthreads();
-    uint64_t e_base = 0;
-    for (uint32_t bi = 0; bi < s_nblk && s_stop == STOP_NONE; ++bi) {
-      const BlockD blk = s_blk[bi];
-      const uint64_t lst = s_lstart[blk.L], lct = s_lcount[blk.L];
-      const uint64_t rst = s_lstart[blk.R], rct = s_lcount[blk.R];
-      for (uint64_t e0 = 0; e0 < blk.count && s_stop == STOP_NONE; e0 += kBatchChunk) {
-        const uint64_t e1 = min(blk.count, e0 + (uint64_t)kBatchChunk);
-        const uint32_t len = (uint32_t)(e1 - e0);
-        if (tid == 0) {
-          s_nsurv = 0;
-          s_ans = ~0u;
-          s_rank = ~0u;
-          s_over = ~0u;
-        }
-        __syncthreads();
+    const uint32_t nblk = s_nblk;
+    const uint64_t level_total = s_bstart[nblk];
+    // Chunks cover consecutive level indices [E0, E1) and may span several
+    // constructor blocks, so small blocks share one round of phases.
+    for (uint64_t E0 = 0; E0 < level_total && s_stop == STOP_NONE; E0 += kBatchChunk) {
+      const uint64_t E1 = min(level_total, E0 + (uint64_t)kBatchChunk);
+      const uint32_t len = (uint32_t)(E1 - E0);
+      if (tid == 0) {
+        s_nsurv = 0;
+        s_ans = ~0u;
+        s_rank = ~0u;
+        s_over = ~0u;
+      }
+      __syncthreads();
+      for (uint32_t bi = 0; bi < nblk; ++bi) {
+        const uint64_t bs = s_bstart[bi], be = s_bstart[bi + 1];
+        if (be <= E0) continue;
+        if (bs >= E1) break;
+        const BlockD blk = s_blk[bi];
+        const uint64_t lst = s_lstart[blk.L], lct = s_lcount[blk.L];
+        const uint64_t rst = s_lstart[blk.R], rct = s_lcount[blk.R];
+        // block-local candidate range of this chunk; candidate e of the block
+        // has chunk-relative index bs + e - E0
+        const uint64_t e0 = max(E0, bs) - bs, e1 = min(E1, be) - bs;
+        const uint64_t rel0 = bs - E0;  // modulo 2^64: rel0 + e >= 0 for e >= e0
 
         // ---- generate and probe
         if (blk.op == OP_CHAR || blk.op == OP_QUESTION || blk.op == OP_UNION) {
@@ -189,7 +267,7 @@ __global__ __launch_bounds__(batch_threads<W>()) void solve_batch(const BatchDes
               }
               dup = eqx || eqy;
             }
-            filter_emit<W, kInl>(probe, sink, valid, dup, key, (uint32_t)(e - e0));
+            filter_emit<W, kInl>(probe, sink, valid, dup, key, (uint32_t)(rel0 + e));
           }
         } else if (blk.op == OP_STAR) {
           uint64_t* Xt = s_tile[0];
@@ -220,7 +298,7 @@ __global__ __launch_bounds__(batch_threads<W>()) void solve_batch(const BatchDes
 #pragma unroll
               for (int k = 0; k < W; ++k) key[k] = transpose64(Yt[64 * k + lane]);
               const uint64_t e = g0 + lane;
-              filter_emit<W, kInl>(probe, sink, e < e1, false, key, (uint32_t)(e - e0));
+              filter_emit<W, kInl>(probe, sink, e < e1, false, key, (uint32_t)(rel0 + e));
             }
             __syncthreads();
           }
@@ -246,7 +324,7 @@ __global__ __launch_bounds__(batch_threads<W>()) void solve_batch(const BatchDes
               uint64_t key[W];
               concat_tile<W, false>(T, U, d, key);
               const uint64_t e = i * nR + jr;
-              filter_emit<W, kInl>(probe, sink, jr < nR && e >= e0 && e < e1, false, key, (uint32_t)(e - e0));
+              filter_emit<W, kInl>(probe, sink, jr < nR && e >= e0 && e < e1, false, key, (uint32_t)(rel0 + e));
               wave_sync();
             }
           } else {
@@ -266,12 +344,13 @@ __global__ __launch_bounds__(batch_threads<W>()) void solve_batch(const BatchDes
               uint64_t key[W];
               concat_tile<W, true>(T, U, d, key);
               const uint64_t e = ir * nR + j;
-              filter_emit<W, kInl>(probe, sink, ir < nL && e >= e0 && e < e1, false, key, (uint32_t)(e - e0));
+              filter_emit<W, kInl>(probe, sink, ir < nL && e >= e0 && e < e1, false, key, (uint32_t)(rel0 + e));
               wave_sync();
             }
           }
         }
-        phase_barrier();
+      }
+      phase_barrier();
 
         // ---- insert survivors
         const uint32_t ns = s_nsurv;
@@ -326,7 +405,7 @@ __global__ __launch_bounds__(batch_threads<W>()) void solve_batch(const BatchDes
               key[k] = d.skey[(uint64_t)sid * W + k];
               d.rows[row * W + k] = key[k];
             }
-            d.aux[row] = e_base + e0 + e;
+            d.aux[row] = E0 + e;
             table_publish<W, kInl>(d.slots, d.sref, d.spos[sid], key, row);
           } else if (rank == room) {
             s_over = e;
@@ -348,7 +427,7 @@ __global__ __launch_bounds__(batch_threads<W>()) void solve_batch(const BatchDes
               du = (uint64_t)s_rank + 1;
               stop = STOP_ANSWER;
               ans_cost = c;
-              ans_e = e_base + e0 + ans;
+              ans_e = E0 + ans;
             }
           } else if ((uint64_t)winners > room) {
             stored = room;
@@ -365,23 +444,69 @@ __global__ __launch_bounds__(batch_threads<W>()) void solve_batch(const BatchDes
           } else {
             s_total = total + stored;
             s_lcount[c] += stored;
-            d.lcount[c] += stored;
-            d.uniq[c] += du;
-            d.cand[c] += dc;
+            s_uniq[c] += du;
+            s_cand[c] += dc;
           }
           s_stop = stop;
-          d.st->answer_cost = ans_cost;
-          d.st->answer_e = ans_e;
         }
         phase_barrier();
-      }
-      e_base += blk.count;
     }
   }
+
+  // ---- results, written straight to the instance's host-visible buffers
   if (tid == 0) {
-    d.st->total_rows = s_total;
-    d.st->row_cap = d.row_cap;
-    d.st->stop = s_stop;
+    // The answer's expression tree (A12): the answer candidate, then every
+    // stored row below it, each decoded from its back-pointer (level index)
+    // with the block structure of its level.  Trees have at most one node
+    // per unit of cost; a count of 0 tells the host to decode from the
+    // back-pointers itself.
+    uint32_t k = 0;
+    if (s_stop == STOP_ANSWER) {
+      uint64_t* stk = s_tile[0];  // free after the search
+      uint32_t sp = 0;
+      bool ok = true;
+      auto node = [&](uint64_t row, uint32_t c, uint64_t e) {
+        uint32_t op = 0;
+        uint64_t a = 0, b = 0;
+        if (k >= kTreeMax || sp + 2 > 64 || !decode_index(d, s_lstart, s_lcount, c, e, &op, &a, &b)) {
+          ok = false;
+          return;
+        }
+        uint64_t* o = d.htree + 1 + 4 * k++;
+        o[0] = row;
+        o[1] = op;
+        o[2] = a;
+        o[3] = b;
+        if (op != OP_CHAR) stk[sp++] = a;
+        if (op == OP_CONCAT || op == OP_UNION) stk[sp++] = b;
+      };
+      node(~0ull, ans_cost, ans_e);
+      while (ok && sp) {
+        const uint64_t row = stk[--sp];
+        uint32_t rc = 0;
+        for (uint32_t c = d.c1; c <= d.max_cost; ++c)
+          if (row >= s_lstart[c] && row < s_lstart[c] + s_lcount[c]) rc = c;
+        if (!rc) {
+          ok = false;
+          break;
+        }
+        node(row, rc, d.aux[row]);
+      }
+      if (!ok) k = 0;
+    }
+    d.htree[0] = k;
+    d.hst->total_rows = s_total;
+    d.hst->row_cap = d.row_cap;
+    d.hst->stop = s_stop;
+    d.hst->answer_cost = ans_cost;
+    d.hst->answer_e = ans_e;
+    d.hst->resume_level = s_resume;
+  }
+  const uint32_t L = d.max_cost + 2;
+  for (uint32_t i = tid; i < L; i += kT) {
+    d.hlev[i] = s_lcount[i];
+    d.hlev[L + i] = s_uniq[i];
+    d.hlev[2 * L + i] = s_cand[i];
   }
 }
 

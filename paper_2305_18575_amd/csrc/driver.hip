@@ -53,6 +53,7 @@ struct rei_instance {
   uint64_t row_cap = 0;
   uint32_t max_err = 0;
   uint64_t chunk_max = kDefaultChunk;
+  uint64_t batch_level_max = kBatchLevelMax;
   int device = 0;
   double seconds_stage = 0;
 
@@ -89,9 +90,19 @@ struct rei_instance {
   uint64_t* d_levels = nullptr;
   DevState* h_state = nullptr;    // pinned mirrors
   uint64_t* h_levels = nullptr;
+  uint64_t* h_tree = nullptr;     // answer tree written by the batched solver
+  // the same pinned buffers as the device addresses them
+  DevState* v_state = nullptr;
+  uint64_t* v_levels = nullptr;
+  uint64_t* v_tree = nullptr;
+  // nodes of the answer tree (row, op, a, b) decoded on the device by the
+  // batched solver; printing looks rows up here before reading back-pointers
+  std::vector<uint64_t> tree;
 
   // rows known stored at the last synchronisation, candidates enqueued since
   uint64_t known_rows = 0;
+  // set when the batched solver handed the instance over at this level
+  uint32_t resume_level = 0;
   uint64_t pending = 0;
 
   // levels, indexed by cost
@@ -465,6 +476,13 @@ rei_status row_aux(rei_instance* in, uint64_t row, uint64_t* e) {
 }
 
 rei_status row_node(rei_instance* in, uint64_t row, Node* nd) {
+  for (size_t k = 0; k + 3 < in->tree.size(); k += 4)
+    if (in->tree[k] == row) {
+      nd->op = (int)in->tree[k + 1];
+      nd->a = in->tree[k + 2];
+      nd->b = in->tree[k + 3];
+      return REI_OK;
+    }
   uint64_t e = 0;
   rei_status r = row_aux(in, row, &e);
   if (r != REI_OK) return r;
@@ -546,6 +564,8 @@ bool begin_solve(rei_instance* in, double t0) {
   in->known_rows = 0;
   in->pending = 0;
   in->h_aux_valid = false;
+  in->tree.clear();
+  in->resume_level = 0;
   if (in->max_cost < c1) {
     fill_result(in, REI_NOT_FOUND, 0, 0, t0);
     return true;
@@ -599,6 +619,11 @@ rei_status finish_solve(rei_instance* in, double t0) {
       in->err = "answer index does not decode";
       return REI_ERR_DEVICE;
     }
+    if (!in->tree.empty() && (in->tree[0] != ~0ull || in->tree[1] != (uint64_t)nd.op || in->tree[2] != nd.a ||
+                              in->tree[3] != nd.b)) {
+      in->err = "device answer tree disagrees with the host decode";
+      return REI_ERR_DEVICE;
+    }
     if ((r = print_node(in, nd, &in->regex)) != REI_OK) return r;
   }
   if (in->prof && (r = prof_collect(in)) != REI_OK) return r;
@@ -612,18 +637,47 @@ rei_status search_levels(rei_instance* in, hipStream_t s) {
   const uint32_t c1 = in->costs.c_char;
   const uint64_t L = in->max_cost + 2;
   rei_status r;
-  // a fresh search: nothing stored yet (also when a batched attempt ran out
-  // of its preallocated rows and left some behind)
-  in->known_rows = 0;
   in->pending = 0;
+  in->tree.clear();
   std::fill(in->lstart.begin(), in->lstart.end(), 0);
   std::fill(in->lcount.begin(), in->lcount.end(), 0);
+  const uint32_t c_from = in->resume_level;
+  in->resume_level = 0;
   LAUNCH(in, s, REI_K_OTHER, 1, launch_state_reset(in->d_ctrl, in->d_state, in->row_cap, s));
-  LAUNCH(in, s, REI_K_OTHER, 3 * L, launch_fill(in->d_levels, 3 * L, 0, s));
-  if ((r = ensure_table(in, 1024, s, true)) != REI_OK) return r;
+  if (c_from > c1) {
+    // The batched solver stored every level below c_from (rows, back-pointers,
+    // table entries) and wrote its state and counters to the pinned mirrors:
+    // put them back on the device and continue from level c_from.
+    in->known_rows = in->h_state->total_rows;
+    uint64_t start = 0;
+    for (uint32_t c = c1; c < c_from; ++c) {
+      in->lstart[c] = start;
+      in->lcount[c] = in->h_levels[c];
+      start += in->lcount[c];
+    }
+    if (start != in->known_rows) {
+      in->err = "batched solver state is inconsistent";
+      return REI_ERR_DEVICE;
+    }
+    DevState* hs = in->h_state;
+    hs->row_cap = in->row_cap;
+    hs->stop = STOP_NONE;
+    hs->answer_cost = 0;
+    hs->answer_e = 0;
+    hs->resume_level = 0;
+    HIP_OK(in, hipMemcpyAsync(in->d_state, hs, sizeof(DevState), hipMemcpyHostToDevice, s));
+    HIP_OK(in, hipMemcpyAsync(in->d_levels, in->h_levels, 3 * L * 8, hipMemcpyHostToDevice, s));
+    if ((r = ensure_table(in, in->known_rows + 1024, s, false)) != REI_OK) return r;
+  } else {
+    // a fresh search: nothing stored yet (also when a batched attempt ran out
+    // of its preallocated rows and left some behind)
+    in->known_rows = 0;
+    LAUNCH(in, s, REI_K_OTHER, 3 * L, launch_fill(in->d_levels, 3 * L, 0, s));
+    if ((r = ensure_table(in, 1024, s, true)) != REI_OK) return r;
+  }
   std::vector<Block> blocks;
   bool stopped = false;
-  for (uint32_t c = c1; c <= in->max_cost && !stopped; ++c) {
+  for (uint32_t c = c_from > c1 ? c_from : c1; c <= in->max_cost && !stopped; ++c) {
     in->lstart[c] = in->known_rows;
     if (!make_blocks(in, c, &blocks)) {
       in->err = "candidate count overflows 64 bits";
@@ -672,6 +726,77 @@ bool batchable(const rei_instance* in) {
 
 // ---- batched solving -------------------------------------------------------
 
+// Descriptor arrays (pinned host memory the kernel reads directly), side
+// streams and events for the batched launches, kept for reuse: allocating
+// or freeing them per solve would wait for the whole device.
+struct DescBuf {
+  BatchDesc* h = nullptr;
+  BatchDesc* d = nullptr;  // the device's address of the same memory
+  size_t cap = 0;
+};
+struct SideStream {
+  int device = 0;
+  hipStream_t s = nullptr;
+  hipEvent_t join = nullptr;
+};
+std::mutex g_pool_mu;
+std::vector<DescBuf> g_desc_free;
+std::vector<SideStream> g_side_free;
+std::vector<std::pair<int, hipEvent_t>> g_event_free;
+
+rei_status desc_acquire(rei_instance* in, size_t n, DescBuf* out) {
+  {
+    std::lock_guard<std::mutex> g(g_pool_mu);
+    for (size_t k = 0; k < g_desc_free.size(); ++k)
+      if (g_desc_free[k].cap >= n) {
+        *out = g_desc_free[k];
+        g_desc_free.erase(g_desc_free.begin() + k);
+        return REI_OK;
+      }
+  }
+  DescBuf b;
+  b.cap = std::max<size_t>(n, 256);
+  HIP_OK(in, hipHostMalloc((void**)&b.h, b.cap * sizeof(BatchDesc), hipHostMallocMapped | hipHostMallocPortable));
+  HIP_OK(in, hipHostGetDevicePointer((void**)&b.d, b.h, 0));
+  *out = b;
+  return REI_OK;
+}
+
+rei_status side_acquire(rei_instance* in, SideStream* out) {
+  {
+    std::lock_guard<std::mutex> g(g_pool_mu);
+    for (size_t k = 0; k < g_side_free.size(); ++k)
+      if (g_side_free[k].device == in->device) {
+        *out = g_side_free[k];
+        g_side_free.erase(g_side_free.begin() + k);
+        return REI_OK;
+      }
+  }
+  SideStream ss;
+  ss.device = in->device;
+  HIP_OK(in, hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking));
+  HIP_OK(in, hipEventCreateWithFlags(&ss.join, hipEventDisableTiming));
+  *out = ss;
+  return REI_OK;
+}
+
+rei_status event_acquire(rei_instance* in, hipEvent_t* out) {
+  {
+    std::lock_guard<std::mutex> g(g_pool_mu);
+    for (size_t k = 0; k < g_event_free.size(); ++k)
+      if (g_event_free[k].first == in->device) {
+        *out = g_event_free[k].second;
+        g_event_free.erase(g_event_free.begin() + k);
+        return REI_OK;
+      }
+  }
+  HIP_OK(in, hipEventCreateWithFlags(out, hipEventDisableTiming));
+  return REI_OK;
+}
+
+struct BatchRun;
+void batch_release(BatchRun* run);
+
 struct BatchRun {
   hipStream_t s = nullptr;
   double t0 = 0;
@@ -679,14 +804,15 @@ struct BatchRun {
   // batched, by group: index 0 = one word with keys inline, else W
   std::vector<rei_instance*> members[kBatchMaxW + 1];
   std::vector<rei_instance*> finished;                // results complete
-  std::vector<BatchDesc*> dbufs;
+  std::vector<DescBuf> descs;                         // pooled, returned by batch_release
+  std::vector<SideStream> sides;
+  hipEvent_t fork = nullptr;
   rei_instance* pin = nullptr;  // holds the batched launches' timings
   size_t rec_first = 0;
   std::vector<int> rec_w;
 };
 
 BatchDesc make_desc(const rei_instance* in) {
-  const uint64_t L = in->max_cost + 2;
   BatchDesc d{};
   d.gt_off = in->d_gt_off;
   d.gt_pair = in->d_gt_pair;
@@ -712,14 +838,14 @@ BatchDesc make_desc(const rei_instance* in) {
   d.slots = in->d_slots;
   d.sref = in->d_sref;
   d.inl = in->inl ? 1u : 0u;
+  d.level_max = in->batch_level_max;
   d.slot_mask = in->slots_cap - 1;
   d.skey = in->d_skey;
   d.se = in->d_se;
   d.spos = in->d_spos;
-  d.st = in->d_state;
-  d.lcount = in->d_levels;
-  d.uniq = in->d_levels + L;
-  d.cand = in->d_levels + 2 * L;
+  d.hst = in->v_state;
+  d.hlev = in->v_levels;
+  d.htree = in->v_tree;
   return d;
 }
 
@@ -761,40 +887,79 @@ rei_status batch_launch(rei_instance* const* insts, size_t n, hipStream_t s, uin
   }
   run->pin = n ? insts[0] : nullptr;
   run->rec_first = run->pin ? run->pin->recs.size() : 0;
+  // One launch per word width; the first on s, the others on side streams
+  // that start after s's earlier work and that s waits for, so the groups
+  // run side by side.
+  bool first = true;
   for (int g = 0; g <= kBatchMaxW; g = g ? 2 * g : 1) {
     if (groups[g].empty()) continue;
     rei_instance* in0 = run->members[g][0];
-    BatchDesc* dd = nullptr;
-    HIP_OK(in0, hipMalloc(&dd, groups[g].size() * sizeof(BatchDesc)));
-    run->dbufs.push_back(dd);
-    HIP_OK(in0, hipMemcpyAsync(dd, groups[g].data(), groups[g].size() * sizeof(BatchDesc),
-                               hipMemcpyHostToDevice, s));
+    DescBuf db;
+    if ((r = desc_acquire(in0, groups[g].size(), &db)) != REI_OK) return r;
+    run->descs.push_back(db);
+    std::memcpy(db.h, groups[g].data(), groups[g].size() * sizeof(BatchDesc));
+    hipStream_t gs = s;
+    if (!first) {
+      if (!run->fork) {
+        if ((r = event_acquire(in0, &run->fork)) != REI_OK) return r;
+        HIP_OK(in0, hipEventRecord(run->fork, s));
+      }
+      SideStream ss;
+      if ((r = side_acquire(in0, &ss)) != REI_OK) return r;
+      run->sides.push_back(ss);
+      HIP_OK(in0, hipStreamWaitEvent(ss.s, run->fork, 0));
+      gs = ss.s;
+    }
     hipEvent_t ev = nullptr;
-    if ((r = prof_begin(run->pin, s, &ev)) != REI_OK) return r;
-    HIP_OK(in0, launch_solve_batch(g ? g : 1, g == 0, dd, (uint32_t)groups[g].size(), s));
-    if ((r = prof_end(run->pin, s, REI_K_BATCH, ev, 0)) != REI_OK) return r;
+    if ((r = prof_begin(run->pin, gs, &ev)) != REI_OK) return r;
+    HIP_OK(in0, launch_solve_batch(g ? g : 1, g == 0, db.d, (uint32_t)groups[g].size(), gs));
+    if ((r = prof_end(run->pin, gs, REI_K_BATCH, ev, 0)) != REI_OK) return r;
     if (run->pin->prof) run->rec_w.push_back(g);
+    if (!first) {
+      HIP_OK(in0, hipEventRecord(run->sides.back().join, gs));
+      HIP_OK(in0, hipStreamWaitEvent(s, run->sides.back().join, 0));
+    }
+    first = false;
   }
   return REI_OK;
+}
+
+// Returns the run's pooled resources; the launches must have finished (or
+// never been enqueued).
+void batch_release(BatchRun* run) {
+  std::lock_guard<std::mutex> g(g_pool_mu);
+  for (auto& d : run->descs) g_desc_free.push_back(d);
+  run->descs.clear();
+  for (auto& ss : run->sides) g_side_free.push_back(ss);
+  run->sides.clear();
+  if (run->fork) g_event_free.push_back({run->pin ? run->pin->device : 0, run->fork});
+  run->fork = nullptr;
 }
 
 // After run->s has finished the launches: results of the batched instances;
 // those that outgrew their preallocated rows are appended to run->grid.
 rei_status batch_collect(BatchRun* run) {
   rei_status r;
-  for (auto* p : run->dbufs) (void)hipFree(p);
-  run->dbufs.clear();
+  if (run->pin) HIP_OK(run->pin, hipStreamSynchronize(run->s));
+  batch_release(run);
   uint64_t group_cand[kBatchMaxW + 1] = {0};
   std::vector<rei_instance*> done;
   for (int g = 0; g <= kBatchMaxW; g = g ? 2 * g : 1)
     for (rei_instance* in : run->members[g]) {
-      if ((r = sync_state(in, run->s)) != REI_OK) return r;
+      // the kernel wrote the state, the level counters and the answer tree
+      // into this instance's pinned buffers
+      in->known_rows = in->h_state->total_rows;
+      in->pending = 0;
       const uint64_t L = in->max_cost + 2;
+      const uint64_t k = std::min<uint64_t>(in->h_tree[0], kBatchTreeNodes);
+      in->tree.assign(in->h_tree + 1, in->h_tree + 1 + 4 * k);
       for (uint64_t c = 0; c < L; ++c) group_cand[g] += in->h_levels[2 * L + c];
-      if (in->h_state->stop == STOP_CAPACITY)
+      if (in->h_state->stop == STOP_CAPACITY || in->h_state->stop == STOP_HANDOFF) {
+        in->resume_level = in->h_state->stop == STOP_HANDOFF ? (uint32_t)in->h_state->resume_level : 0;
         run->grid.push_back(in);
-      else
+      } else {
         done.push_back(in);
+      }
     }
   for (size_t q = 0; q < run->rec_w.size(); ++q) run->pin->recs[run->rec_first + q].units = group_cand[run->rec_w[q]];
   for (rei_instance* in : done) {
@@ -828,8 +993,10 @@ void free_device(rei_instance* in) {
   dfree(in->d_levels);
   if (in->h_state) (void)hipHostFree(in->h_state);
   if (in->h_levels) (void)hipHostFree(in->h_levels);
+  if (in->h_tree) (void)hipHostFree(in->h_tree);
   in->h_state = nullptr;
   in->h_levels = nullptr;
+  in->h_tree = nullptr;
   for (auto& r : in->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -860,8 +1027,14 @@ rei_status create_device(rei_instance* in) {
   HIP_OK(in, hipMalloc(&in->d_state, sizeof(DevState)));
   const uint64_t L = in->max_cost + 2;
   HIP_OK(in, hipMalloc(&in->d_levels, 3 * L * 8));
-  HIP_OK(in, hipHostMalloc((void**)&in->h_state, sizeof(DevState), hipHostMallocDefault));
-  HIP_OK(in, hipHostMalloc((void**)&in->h_levels, 3 * L * 8, hipHostMallocDefault));
+  const unsigned fl = hipHostMallocMapped | hipHostMallocPortable;
+  HIP_OK(in, hipHostMalloc((void**)&in->h_state, sizeof(DevState), fl));
+  HIP_OK(in, hipHostMalloc((void**)&in->h_levels, 3 * L * 8, fl));
+  HIP_OK(in, hipHostMalloc((void**)&in->h_tree, (1 + 4 * kBatchTreeNodes) * 8, fl));
+  in->h_tree[0] = 0;
+  HIP_OK(in, hipHostGetDevicePointer((void**)&in->v_state, in->h_state, 0));
+  HIP_OK(in, hipHostGetDevicePointer((void**)&in->v_levels, in->h_levels, 0));
+  HIP_OK(in, hipHostGetDevicePointer((void**)&in->v_tree, in->h_tree, 0));
   return REI_OK;
 }
 
@@ -940,13 +1113,14 @@ rei_status rei_solve_batch(rei_instance* const* insts, size_t n, void* hip_strea
   rei_status r;
   try {
     if ((r = batch_launch(insts, n, s, arena_bytes, &run)) != REI_OK) {
-      for (auto* p : run.dbufs) (void)hipFree(p);
+      (void)hipStreamSynchronize(s);
+      batch_release(&run);
       return r;
     }
     hipError_t se = hipStreamSynchronize(s);
     if (se != hipSuccess) {
       for (size_t i = 0; i < n; ++i) insts[i]->err = std::string("batched launch: ") + hipGetErrorString(se);
-      for (auto* p : run.dbufs) (void)hipFree(p);
+      batch_release(&run);
       return REI_ERR_DEVICE;
     }
     if ((r = batch_collect(&run)) != REI_OK) return r;
@@ -1027,6 +1201,12 @@ rei_status rei_set_chunk(rei_instance* inst, uint64_t max_candidates) {
   if (max_candidates == 0) max_candidates = kDefaultChunk;
   if (max_candidates > kMaxChunk) return REI_ERR_INVALID_ARG;
   inst->chunk_max = max_candidates;
+  return REI_OK;
+}
+
+rei_status rei_set_batch_level(rei_instance* inst, uint64_t max_candidates) {
+  if (!inst) return REI_ERR_INVALID_ARG;
+  inst->batch_level_max = max_candidates ? max_candidates : kBatchLevelMax;
   return REI_OK;
 }
 
@@ -1232,8 +1412,7 @@ void server_sched(rei_server* sv) {
       lk.lock();
       if (r != REI_OK || e != hipSuccess) {
         (void)hipStreamSynchronize(s);
-        for (auto* p : f.run.dbufs) (void)hipFree(p);
-        f.run.dbufs.clear();
+        batch_release(&f.run);
         if (f.ev) (void)hipEventDestroy(f.ev);
         sv->stream_busy[free_stream] = false;
         for (uint64_t t : take) server_finish(sv, t, r != REI_OK ? r : REI_ERR_DEVICE);

@@ -60,16 +60,20 @@ struct Ctrl {
 
 // Search state in device memory, advanced by the last kernel of each chunk,
 // so chunks are enqueued without waiting for the host.
-enum StopCode : uint32_t { STOP_NONE = 0, STOP_ANSWER = 1, STOP_OOM = 2, STOP_CAPACITY = 3 };
+enum StopCode : uint32_t { STOP_NONE = 0, STOP_ANSWER = 1, STOP_OOM = 2, STOP_CAPACITY = 3, STOP_HANDOFF = 4 };
 // STOP_CAPACITY: the batched solver ran out of its preallocated rows; the
-// instance is solved again on the per-chunk path.
+// instance is solved again, from the start, on the per-chunk path.
+// STOP_HANDOFF: the batched solver reached a level of more than
+// kBatchLevelMax candidates (resume_level) with every lower level stored;
+// the per-chunk path continues from there.
 struct DevState {
   uint64_t total_rows;      // rows stored (all levels)
   uint64_t row_cap;         // rows that fit the cache budget
   uint32_t stop;            // StopCode; kernels of later chunks return at once
   uint32_t answer_cost;
   uint64_t answer_e;        // level enumeration index of the answer
-  uint64_t pad[4];
+  uint64_t resume_level;    // STOP_HANDOFF: the first level not searched
+  uint64_t pad[3];
 };
 
 // Arguments shared by all generator kernels.
@@ -147,6 +151,8 @@ const char* gen_kernel_name(int op);
 constexpr uint32_t kBatchChunk = 8192;   // candidates per chunk
 constexpr uint32_t kBatchMaxCost = 63;   // largest max_cost handled in a batch
 constexpr int kBatchMaxW = 8;            // largest words per language
+constexpr uint64_t kBatchLevelMax = 1ull << 20;  // default: candidates of one level a workgroup takes on
+constexpr uint32_t kBatchTreeNodes = 64; // answer-tree nodes written back (cost <= 63 needs <= 63)
 
 struct BatchDesc {
   // staged tables
@@ -167,13 +173,14 @@ struct BatchDesc {
   uint64_t* sref;
   uint64_t slot_mask;         // table holds rows_alloc + kBatchChunk entries at load <= 1/2
   uint32_t inl, pad2;
+  uint64_t level_max;         // larger levels are handed to the per-chunk path
   uint64_t* skey;             // kBatchChunk survivors
   uint32_t* se;
   uint64_t* spos;
-  DevState* st;
-  uint64_t* lcount;           // per cost: rows, unique, candidates (max_cost + 2 each)
-  uint64_t* uniq;
-  uint64_t* cand;
+  // results, in host-visible (pinned) memory, written once at the end:
+  DevState* hst;              // final search state
+  uint64_t* hlev;             // per cost: rows, unique, candidates (max_cost + 2 each)
+  uint64_t* htree;            // [node count, then per node: row (~0 = the answer), op, a, b]
 };
 
 // Launches one workgroup per descriptor (all with the same W).

@@ -269,3 +269,44 @@ def test_resolves_stay_exact(rei, seed):
         for c in range(0, inst.max_cost + 1):
             assert r.unique_at(c) == o.unique[c] and r.candidates_at(c) == o.candidates[c], (rep, c)
     h.close()
+
+
+def test_batch_hands_large_levels_to_grid(rei, golden):
+    """An instance whose levels outgrow one workgroup (Table 1 row 1, minimal
+    cost 28) is handed to the per-chunk path inside a batched call; its
+    result equals rei_solve's, and a small instance in the same call still
+    equals the oracle."""
+    t = golden["table1_row1"]
+    small = instances.single_instance(0, (1, 1, 1, 1, 1))
+    big = rei.Instance(t["alphabet"], t["pos"], t["neg"], (1, 1, 1, 1, 1), 30, 8 << 30)
+    h = rei.Instance(small.alphabet, small.pos, small.neg, small.costs, small.max_cost)
+    print("\nbatch: Table 1 row 1 + single seed 0", flush=True)
+    rb, rs = rei.solve_batch([big, h])
+    alone = big.solve()
+    key = lambda r: (r.status, r.cost, r.regex, r.unique, r.candidates)
+    assert key(rb) == key(alone)
+    assert (rb.status, rb.cost) == ("OK", 28)
+    check_against_oracle(rs, (small.alphabet, small.pos, small.neg, small.costs, small.max_cost))
+    big.close()
+    h.close()
+
+
+@pytest.mark.parametrize("level_max", [1, 300, 5000])
+def test_batch_handoff_resumes_exactly(rei, level_max):
+    """Instances handed to the per-chunk path at a level boundary continue
+    with the levels the workgroup stored (rows, back-pointers, table); the
+    results equal the oracle's for every hand-off level, word width and
+    table form."""
+    specs = batch_specs()[::3]
+    for seed in (3, 6):
+        i = instances.single_instance(seed, (1, 1, 5, 1, 2))
+        specs.append((i.alphabet, i.pos, i.neg, i.costs, i.max_cost))
+    print(f"\nbatch of {len(specs)} instances, hand-off above {level_max} candidates", flush=True)
+    hs = [rei.Instance(a, p, n, c, m) for (a, p, n, c, m) in specs]
+    for h in hs:
+        h.set_batch_level(level_max)
+    res = rei.solve_batch(hs)
+    for r, spec in zip(res, specs):
+        check_against_oracle(r, spec)
+    for h in hs:
+        h.close()
