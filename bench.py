@@ -70,6 +70,11 @@ def main():
                     help="requests per serving run (0 = skip the serving measurement)")
     ap.add_argument("--sequential", action="store_true",
                     help="time rei_solve per instance as the step instead of rei_solve_batch")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="do not also time the other mode (batched vs sequential)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before timing, copy this many MiB device to device once: a kernel of "
+                         "known traffic that calibrates FETCH_SIZE / WRITE_SIZE counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the search is "
@@ -89,6 +94,12 @@ def main():
             h.set_max_errors(args.max_errors)
         handles.append(h)
     stream = torch.cuda.current_stream().cuda_stream
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step_sequential():
         return [h.solve(stream) for h in handles]
@@ -118,14 +129,17 @@ def main():
     for h in handles:
         h.set_profiling(False)
     other = step_batch if args.sequential else step_sequential
-    other()
-    other_results, other_elapsed = timed(other, args.steps)
-    key = lambda r: (r.status, r.cost, r.regex, tuple(r.unique), tuple(r.candidates))
-    same = all(key(a) == key(b) for ra, rb in zip(results, other_results) for a, b in zip(ra, rb))
+    same = None
+    other_value = None
+    if not args.no_compare:
+        other()
+        other_results, other_elapsed = timed(other, args.steps)
+        key = lambda r: (r.status, r.cost, r.regex, tuple(r.unique), tuple(r.candidates))
+        same = all(key(a) == key(b) for ra, rb in zip(results, other_results) for a, b in zip(ra, rb))
+        other_value = sum(r.total_unique for batch in other_results for r in batch) / other_elapsed
 
     uniq = sum(r.total_unique for batch in results for r in batch)
     value = uniq / elapsed
-    other_value = sum(r.total_unique for batch in other_results for r in batch) / other_elapsed
     solve_ms = sorted(r.seconds_solve * 1e3 for batch in results for r in batch)
 
     def pct(p):
@@ -214,8 +228,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "instances_per_step": len(insts),
                    "mode": "rei_solve per instance" if args.sequential else "rei_solve_batch"},
-        ("batched_value" if args.sequential else "sequential_value"): round(other_value, 3),
-        "batched_over_sequential": round((other_value / value) if args.sequential else (value / other_value), 3),
+        ("batched_value" if args.sequential else "sequential_value"):
+            None if other_value is None else round(other_value, 3),
+        "batched_over_sequential": None if other_value is None else
+            round((other_value / value) if args.sequential else (value / other_value), 3),
         "identical_results": same,
         "instances_per_sec": round(len(insts) * args.steps / elapsed, 3),
         "time_to_minimal_regex_ms": {"mean": round(sum(solve_ms) / len(solve_ms), 4),

@@ -38,18 +38,19 @@ __device__ __forceinline__ void wave_sync() {
 // kLeft = true:  tile = left rows,  out_t(w) = OR over cuts (u, v) with
 //                uniform(v) of T[u].
 // Lane t receives the W words of candidate t.
+// The guide table (gto, gtp) is the workgroup's LDS copy.
 template <int W, bool kLeft>
-__device__ __forceinline__ void concat_tile(const uint64_t* T, const uint64_t* uni, const BatchDesc& d,
-                                            uint64_t (&key)[W]) {
+__device__ __forceinline__ void concat_tile(const uint64_t* T, const uint64_t* uni, const uint32_t* gto,
+                                            const uint32_t* gtp, uint32_t n, uint64_t (&key)[W]) {
   const uint32_t lane = lane_id();
 #pragma unroll
   for (int k = 0; k < W; ++k) {
     const uint32_t w = 64u * k + lane;
     uint64_t acc = 0;
-    if (w < d.n) {
-      const uint32_t q1 = d.gt_off[w + 1];
-      for (uint32_t q = d.gt_off[w]; q < q1; ++q) {
-        const uint32_t p = d.gt_pair[q];
+    if (w < n) {
+      const uint32_t q1 = gto[w + 1];
+      for (uint32_t q = gto[w]; q < q1; ++q) {
+        const uint32_t p = gtp[q];
         const uint32_t ui = kLeft ? (p & 0xFFFFu) : (p >> 16);
         const uint32_t si = kLeft ? (p >> 16) : (p & 0xFFFFu);
         if ((uni[ui >> 6] >> (ui & 63)) & 1ull) acc |= T[si];
@@ -140,18 +141,28 @@ __global__ __launch_bounds__(batch_threads<W>()) void solve_batch(const BatchDes
   __shared__ uint32_t s_sc[kT];
   __shared__ uint64_t s_tile[kWaves][64 * W];
   __shared__ uint64_t s_uni[kWaves][W];
+  __shared__ uint32_t s_gto[kBatchMaxIc + 1], s_gtp[kBatchMaxPairs], s_lo[kBatchMaxIc + 2];
 
   if (blockIdx.x >= n_inst) return;
   const BatchDesc d = descs[blockIdx.x];
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const Probe probe{d.rows, d.slots, d.slot_mask, d.pmask, d.nmask, d.max_err};
+  // The dedup table starts small and grows (cleared and rebuilt from the
+  // stored rows) while rows accumulate, up to the arena's slot_mask: a
+  // small instance clears a few hundred KB instead of its whole arena.
+  uint64_t tmask = min(d.slot_mask, (uint64_t)(4 * kBatchChunk) - 1);
+  Probe probe{d.rows, d.slots, tmask, d.pmask, d.nmask, d.max_err};
   const Sink sink{d.skey, d.se, &s_nsurv, &s_ans};
 
   // start: empty table, zero counters
-  for (uint64_t i = tid; i <= d.slot_mask; i += kT) {
+  for (uint64_t i = tid; i <= tmask; i += kT) {
     d.slots[i] = kEmpty;
     if (kInl) d.sref[i] = kEmpty;
   }
+  // guide table and words-by-length offsets into LDS (batchable instances
+  // have at most kBatchMaxIc words and kBatchMaxPairs cuts)
+  for (uint32_t i = tid; i <= d.n; i += kT) s_gto[i] = d.gt_off[i];
+  for (uint32_t i = tid; i < d.n_pairs; i += kT) s_gtp[i] = d.gt_pair[i];
+  for (uint32_t i = tid; i < d.max_len + 2; i += kT) s_lo[i] = d.len_off[i];
   for (uint32_t c = tid; c < kBatchMaxCost + 2; c += kT) {
     s_lstart[c] = 0;
     s_lcount[c] = 0;
@@ -209,6 +220,28 @@ __global__ __launch_bounds__(batch_threads<W>()) void solve_batch(const BatchDes
     for (uint64_t E0 = 0; E0 < level_total && s_stop == STOP_NONE; E0 += kBatchChunk) {
       const uint64_t E1 = min(level_total, E0 + (uint64_t)kBatchChunk);
       const uint32_t len = (uint32_t)(E1 - E0);
+      {
+        // keep the load at most 1/2 with this chunk's survivors inserted
+        const uint64_t total = s_total;
+        if (2 * (total + len) > tmask + 1) {
+          uint64_t cap = tmask + 1;
+          while (cap < 4 * (total + kBatchChunk) && cap <= d.slot_mask) cap *= 2;
+          tmask = min(d.slot_mask, cap - 1);
+          for (uint64_t i = tid; i <= tmask; i += kT) {
+            d.slots[i] = kEmpty;
+            if (kInl) d.sref[i] = kEmpty;
+          }
+          __syncthreads();
+          for (uint64_t row = tid; row < total; row += kT) {
+            uint64_t key[W];
+#pragma unroll
+            for (int k = 0; k < W; ++k) key[k] = d.rows[row * W + k];
+            table_rebuild_one<W, kInl>(d.slots, tmask, key, row);
+          }
+          probe.slot_mask = tmask;
+          __syncthreads();
+        }
+      }
       if (tid == 0) {
         s_nsurv = 0;
         s_ans = ~0u;
@@ -281,12 +314,12 @@ __global__ __launch_bounds__(batch_threads<W>()) void solve_batch(const BatchDes
             for (uint32_t w = tid; w < 64u * W; w += kT) Yt[w] = (w == 0) ? ~0ull : 0ull;
             __syncthreads();
             for (uint32_t l = 1; l <= d.max_len; ++l) {
-              const uint32_t lo = d.len_off[l], hi = d.len_off[l + 1];
+              const uint32_t lo = s_lo[l], hi = s_lo[l + 1];
               for (uint32_t w = lo + tid; w < hi; w += kT) {
                 uint64_t acc = 0;
-                const uint32_t q1 = d.gt_off[w + 1];
-                for (uint32_t q = d.gt_off[w] + 1; q < q1; ++q) {  // cut 0 has u = eps
-                  const uint32_t p = d.gt_pair[q];
+                const uint32_t q1 = s_gto[w + 1];
+                for (uint32_t q = s_gto[w] + 1; q < q1; ++q) {  // cut 0 has u = eps
+                  const uint32_t p = s_gtp[q];
                   acc |= Xt[p >> 16] & Yt[p & 0xFFFFu];
                 }
                 Yt[w] = acc;
@@ -322,7 +355,7 @@ __global__ __launch_bounds__(batch_threads<W>()) void solve_batch(const BatchDes
               if (lane < (uint32_t)W) U[lane] = d.rows[(lst + i) * W + lane];
               wave_sync();
               uint64_t key[W];
-              concat_tile<W, false>(T, U, d, key);
+              concat_tile<W, false>(T, U, s_gto, s_gtp, d.n, key);
               const uint64_t e = i * nR + jr;
               filter_emit<W, kInl>(probe, sink, jr < nR && e >= e0 && e < e1, false, key, (uint32_t)(rel0 + e));
               wave_sync();
@@ -342,7 +375,7 @@ __global__ __launch_bounds__(batch_threads<W>()) void solve_batch(const BatchDes
               if (lane < (uint32_t)W) U[lane] = d.rows[(rst + j) * W + lane];
               wave_sync();
               uint64_t key[W];
-              concat_tile<W, true>(T, U, d, key);
+              concat_tile<W, true>(T, U, s_gto, s_gtp, d.n, key);
               const uint64_t e = ir * nR + j;
               filter_emit<W, kInl>(probe, sink, ir < nL && e >= e0 && e < e1, false, key, (uint32_t)(rel0 + e));
               wave_sync();
@@ -358,7 +391,7 @@ __global__ __launch_bounds__(batch_threads<W>()) void solve_batch(const BatchDes
           uint64_t key[W];
 #pragma unroll
           for (int k = 0; k < W; ++k) key[k] = d.skey[(uint64_t)sid * W + k];
-          d.spos[sid] = table_insert<W, kInl>(d.slots, d.sref, d.slot_mask, d.rows, d.skey, key, hash_key<W>(key),
+          d.spos[sid] = table_insert<W, kInl>(d.slots, d.sref, tmask, d.rows, d.skey, key, hash_key<W>(key),
                                               new_ref(d.se[sid], sid));
         }
         phase_barrier();

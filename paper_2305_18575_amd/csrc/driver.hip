@@ -149,11 +149,16 @@ uint64_t pow2_at_least(uint64_t x) {
   return p;
 }
 
+// Timing-only events: no system-scope fence (cache write-back and
+// invalidation) when they complete, so they neither perturb nor pad the
+// launches they bracket.  They are read only after the stream has drained.
+constexpr unsigned kTimingEvent = hipEventDisableSystemFence;
+
 rei_status prof_begin(rei_instance* in, hipStream_t s, hipEvent_t* ev) {
   if (!in->prof) return REI_OK;
   if (in->pool.empty()) {
     hipEvent_t e;
-    HIP_OK(in, hipEventCreate(&e));
+    HIP_OK(in, hipEventCreateWithFlags(&e, kTimingEvent));
     in->pool.push_back(e);
   }
   *ev = in->pool.back();
@@ -166,7 +171,7 @@ rei_status prof_end(rei_instance* in, hipStream_t s, int k, hipEvent_t a, uint64
   if (!in->prof) return REI_OK;
   hipEvent_t b;
   if (in->pool.empty()) {
-    HIP_OK(in, hipEventCreate(&b));
+    HIP_OK(in, hipEventCreateWithFlags(&b, kTimingEvent));
   } else {
     b = in->pool.back();
     in->pool.pop_back();
@@ -645,9 +650,10 @@ rei_status search_levels(rei_instance* in, hipStream_t s) {
   in->resume_level = 0;
   LAUNCH(in, s, REI_K_OTHER, 1, launch_state_reset(in->d_ctrl, in->d_state, in->row_cap, s));
   if (c_from > c1) {
-    // The batched solver stored every level below c_from (rows, back-pointers,
-    // table entries) and wrote its state and counters to the pinned mirrors:
-    // put them back on the device and continue from level c_from.
+    // The batched solver stored every level below c_from (rows and
+    // back-pointers) and wrote its state and counters to the pinned mirrors:
+    // put them back on the device, rebuild the table from the rows and
+    // continue from level c_from.
     in->known_rows = in->h_state->total_rows;
     uint64_t start = 0;
     for (uint32_t c = c1; c < c_from; ++c) {
@@ -667,7 +673,8 @@ rei_status search_levels(rei_instance* in, hipStream_t s) {
     hs->resume_level = 0;
     HIP_OK(in, hipMemcpyAsync(in->d_state, hs, sizeof(DevState), hipMemcpyHostToDevice, s));
     HIP_OK(in, hipMemcpyAsync(in->d_levels, in->h_levels, 3 * L * 8, hipMemcpyHostToDevice, s));
-    if ((r = ensure_table(in, in->known_rows + 1024, s, false)) != REI_OK) return r;
+    // the batched solver used a prefix of the table: rebuild it at full size
+    if ((r = ensure_table(in, in->known_rows + 1024, s, true)) != REI_OK) return r;
   } else {
     // a fresh search: nothing stored yet (also when a batched attempt ran out
     // of its preallocated rows and left some behind)
@@ -721,7 +728,7 @@ uint64_t batch_rows(const rei_instance* in, uint64_t arena_bytes) {
 }
 
 bool batchable(const rei_instance* in) {
-  return in->st.W <= kBatchMaxW && in->max_cost <= kBatchMaxCost;
+  return in->st.W <= kBatchMaxW && in->max_cost <= kBatchMaxCost && in->st.gt_pair.size() <= kBatchMaxPairs;
 }
 
 // ---- batched solving -------------------------------------------------------

@@ -151,6 +151,8 @@ const char* gen_kernel_name(int op);
 constexpr uint32_t kBatchChunk = 8192;   // candidates per chunk
 constexpr uint32_t kBatchMaxCost = 63;   // largest max_cost handled in a batch
 constexpr int kBatchMaxW = 8;            // largest words per language
+constexpr uint32_t kBatchMaxIc = 64 * kBatchMaxW;  // largest |ic|
+constexpr uint32_t kBatchMaxPairs = 6144;          // largest guide table (cuts), kept in LDS
 constexpr uint64_t kBatchLevelMax = 1ull << 20;  // default: candidates of one level a workgroup takes on
 constexpr uint32_t kBatchTreeNodes = 64; // answer-tree nodes written back (cost <= 63 needs <= 63)
 
@@ -171,7 +173,8 @@ struct BatchDesc {
   uint64_t row_cap;           // rows the cache budget allows
   uint64_t* slots;
   uint64_t* sref;
-  uint64_t slot_mask;         // table holds rows_alloc + kBatchChunk entries at load <= 1/2
+  uint64_t slot_mask;         // arena's table: rows_alloc + kBatchChunk entries at load <= 1/2
+                              // (the kernel uses a growing prefix of it)
   uint32_t inl, pad2;
   uint64_t level_max;         // larger levels are handed to the per-chunk path
   uint64_t* skey;             // kBatchChunk survivors
