@@ -35,6 +35,15 @@ HBM_PEAK_GBS = 8000.0
 # random access, and the smallest HBM transaction is 64 bytes.
 PROBE_BYTES = 64
 
+# HBM bytes per launch of the dominant kernel, from FETCH_SIZE / WRITE_SIZE
+# counter runs calibrated on a 1 GiB copy (profiles/hbm_traffic_counters.md),
+# by (workload, kernel class).  Only valid for the kernels as they were
+# measured: an entry is removed when its kernel changes.
+TRAFFIC_BYTES = {
+    ("single", "solve_batch"): 137663126,
+    ("row1", "gen_concat"): 305966843,
+}
+
 
 def workload(name: str):
     from paper_2305_18575_amd import instances
@@ -161,8 +170,10 @@ def main():
     avg_ms = d["ms"] / max(1, d["launches"])
     bytes_per_launch = PROBE_BYTES * d["units"] / max(1, d["launches"])
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    traffic = TRAFFIC_BYTES.get((args.workload, dom)) if not args.max_errors else None
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
+                "algorithmic_bytes_per_launch": round(bytes_per_launch),
                 "avg_launch_us": round(avg_ms * 1e3, 3), "launches": d["launches"],
                 "candidates_per_launch": round(d["units"] / max(1, d["launches"]), 1)}
 

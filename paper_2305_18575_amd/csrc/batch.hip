@@ -550,13 +550,13 @@ hipError_t launch_solve_batch(int W, bool inl, const BatchDesc* d_descs, uint32_
   switch (W) {
     case 1:
       if (inl)
-        hipLaunchKernelGGL((solve_batch<1, true>), dim3(n), dim3(batch_threads<1>()), 0, s, d_descs, n);
+        launch_timed(solve_batch<1, true>, dim3(n), dim3(batch_threads<1>()), 0, s, d_descs, n);
       else
-        hipLaunchKernelGGL((solve_batch<1, false>), dim3(n), dim3(batch_threads<1>()), 0, s, d_descs, n);
+        launch_timed(solve_batch<1, false>, dim3(n), dim3(batch_threads<1>()), 0, s, d_descs, n);
       break;
-    case 2: hipLaunchKernelGGL((solve_batch<2, false>), dim3(n), dim3(batch_threads<2>()), 0, s, d_descs, n); break;
-    case 4: hipLaunchKernelGGL((solve_batch<4, false>), dim3(n), dim3(batch_threads<4>()), 0, s, d_descs, n); break;
-    case 8: hipLaunchKernelGGL((solve_batch<8, false>), dim3(n), dim3(batch_threads<8>()), 0, s, d_descs, n); break;
+    case 2: launch_timed(solve_batch<2, false>, dim3(n), dim3(batch_threads<2>()), 0, s, d_descs, n); break;
+    case 4: launch_timed(solve_batch<4, false>, dim3(n), dim3(batch_threads<4>()), 0, s, d_descs, n); break;
+    case 8: launch_timed(solve_batch<8, false>, dim3(n), dim3(batch_threads<8>()), 0, s, d_descs, n); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

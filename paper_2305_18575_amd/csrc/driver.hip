@@ -19,6 +19,10 @@
 
 using namespace rei;
 
+namespace rei {
+thread_local KernelTimer g_kernel_timer{nullptr, nullptr};
+}
+
 namespace {
 
 thread_local std::string g_create_error;
@@ -154,8 +158,12 @@ uint64_t pow2_at_least(uint64_t x) {
 // launches they bracket.  They are read only after the stream has drained.
 constexpr unsigned kTimingEvent = hipEventDisableSystemFence;
 
-rei_status prof_begin(rei_instance* in, hipStream_t s, hipEvent_t* ev) {
-  if (!in->prof) return REI_OK;
+// Generators and the batched solver are launched through launch_timed, which
+// records the pair at the kernel's own start and end; the other launchers
+// (several small kernels each) are bracketed by events on the stream.
+bool self_timed(int k) { return k <= REI_K_GEN_UNION || k == REI_K_BATCH; }
+
+rei_status prof_event(rei_instance* in, hipEvent_t* ev) {
   if (in->pool.empty()) {
     hipEvent_t e;
     HIP_OK(in, hipEventCreateWithFlags(&e, kTimingEvent));
@@ -163,20 +171,31 @@ rei_status prof_begin(rei_instance* in, hipStream_t s, hipEvent_t* ev) {
   }
   *ev = in->pool.back();
   in->pool.pop_back();
-  HIP_OK(in, hipEventRecord(*ev, s));
   return REI_OK;
 }
 
-rei_status prof_end(rei_instance* in, hipStream_t s, int k, hipEvent_t a, uint64_t units) {
+rei_status prof_begin(rei_instance* in, hipStream_t s, int k, hipEvent_t* a, hipEvent_t* b) {
   if (!in->prof) return REI_OK;
-  hipEvent_t b;
-  if (in->pool.empty()) {
-    HIP_OK(in, hipEventCreateWithFlags(&b, kTimingEvent));
+  rei_status r;
+  if ((r = prof_event(in, a)) != REI_OK || (r = prof_event(in, b)) != REI_OK) return r;
+  if (self_timed(k))
+    g_kernel_timer = KernelTimer{*a, *b};
+  else
+    HIP_OK(in, hipEventRecord(*a, s));
+  return REI_OK;
+}
+
+rei_status prof_end(rei_instance* in, hipStream_t s, int k, hipEvent_t a, hipEvent_t b, uint64_t units) {
+  if (!in->prof) return REI_OK;
+  if (self_timed(k)) {
+    if (g_kernel_timer.start) {  // the launcher launched nothing
+      g_kernel_timer = KernelTimer{nullptr, nullptr};
+      HIP_OK(in, hipEventRecord(a, s));
+      HIP_OK(in, hipEventRecord(b, s));
+    }
   } else {
-    b = in->pool.back();
-    in->pool.pop_back();
+    HIP_OK(in, hipEventRecord(b, s));
   }
-  HIP_OK(in, hipEventRecord(b, s));
   in->recs.push_back({k, a, b, units});
   return REI_OK;
 }
@@ -198,11 +217,11 @@ rei_status prof_collect(rei_instance* in) {
 
 #define LAUNCH(in, s, k, units, call)                     \
   do {                                                    \
-    hipEvent_t ev_ = nullptr;                             \
-    rei_status ps_ = prof_begin(in, s, &ev_);             \
+    hipEvent_t ev_ = nullptr, ev2_ = nullptr;             \
+    rei_status ps_ = prof_begin(in, s, k, &ev_, &ev2_);   \
     if (ps_ != REI_OK) return ps_;                        \
     HIP_OK(in, call);                                     \
-    ps_ = prof_end(in, s, k, ev_, units);                 \
+    ps_ = prof_end(in, s, k, ev_, ev2_, units);           \
     if (ps_ != REI_OK) return ps_;                        \
   } while (0)
 
@@ -917,10 +936,10 @@ rei_status batch_launch(rei_instance* const* insts, size_t n, hipStream_t s, uin
       HIP_OK(in0, hipStreamWaitEvent(ss.s, run->fork, 0));
       gs = ss.s;
     }
-    hipEvent_t ev = nullptr;
-    if ((r = prof_begin(run->pin, gs, &ev)) != REI_OK) return r;
+    hipEvent_t ev = nullptr, ev2 = nullptr;
+    if ((r = prof_begin(run->pin, gs, REI_K_BATCH, &ev, &ev2)) != REI_OK) return r;
     HIP_OK(in0, launch_solve_batch(g ? g : 1, g == 0, db.d, (uint32_t)groups[g].size(), gs));
-    if ((r = prof_end(run->pin, gs, REI_K_BATCH, ev, 0)) != REI_OK) return r;
+    if ((r = prof_end(run->pin, gs, REI_K_BATCH, ev, ev2, 0)) != REI_OK) return r;
     if (run->pin->prof) run->rec_w.push_back(g);
     if (!first) {
       HIP_OK(in0, hipEventRecord(run->sides.back().join, gs));

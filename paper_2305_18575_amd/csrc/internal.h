@@ -1,6 +1,7 @@
 // Internal declarations of the REI library (not part of the C ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -131,6 +132,22 @@ struct ChunkArgs {
   uint64_t chunk_e0;          // level enumeration index of chunk-relative 0
   uint64_t len;               // candidates in the chunk
 };
+
+// Events of this thread's next timed kernel launch (set by the library's
+// profiler).  launch_timed hands them to the launch itself, which records
+// them at the kernel's own start and end, so the time excludes the dispatch
+// gap that events recorded on the stream around the launch would include.
+struct KernelTimer {
+  hipEvent_t start, stop;
+};
+extern thread_local KernelTimer g_kernel_timer;
+
+template <typename F, typename... Args>
+inline void launch_timed(F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t s, Args... args) {
+  const KernelTimer t = g_kernel_timer;
+  g_kernel_timer = KernelTimer{nullptr, nullptr};
+  hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, t.start, t.stop, 0u, args...);
+}
 
 // Kernel launchers (kernels.hip).  Every launcher returns the hipError_t of
 // the launch.

@@ -538,16 +538,16 @@ hipError_t launch_concat_w(const GenArgs& a, hipStream_t s) {
   const dim3 grid((uint32_t)(gx * gy));
   const bool shrt = a.max_len < 32;
   if (shrt && gt_lds)
-    hipLaunchKernelGGL((gen_concat<W, true, kInl, true>), grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
+    launch_timed(gen_concat<W, true, kInl, true>, grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
                        (uint32_t)gx);
   else if (shrt)
-    hipLaunchKernelGGL((gen_concat<W, true, kInl, false>), grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
+    launch_timed(gen_concat<W, true, kInl, false>, grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
                        (uint32_t)gx);
   else if (gt_lds)
-    hipLaunchKernelGGL((gen_concat<W, false, kInl, true>), grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
+    launch_timed(gen_concat<W, false, kInl, true>, grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
                        (uint32_t)gx);
   else
-    hipLaunchKernelGGL((gen_concat<W, false, kInl, false>), grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
+    launch_timed(gen_concat<W, false, kInl, false>, grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
                        (uint32_t)gx);
   return hipGetLastError();
 }
@@ -557,21 +557,21 @@ hipError_t launch_gen_w(int op, const GenArgs& a, bool same_level, hipStream_t s
   const uint64_t cnt = a.e1 - a.e0;
   switch (op) {
     case OP_CHAR:
-      hipLaunchKernelGGL((gen_char<W, kInl>), dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
+      launch_timed(gen_char<W, kInl>, dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
       break;
     case OP_QUESTION:
-      hipLaunchKernelGGL((gen_question<W, kInl>), dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
+      launch_timed(gen_question<W, kInl>, dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
       break;
     case OP_STAR:
-      hipLaunchKernelGGL((gen_star<W, kInl>), dim3(grid_for(cnt, 64)), dim3(256), 0, s, a);
+      launch_timed(gen_star<W, kInl>, dim3(grid_for(cnt, 64)), dim3(256), 0, s, a);
       break;
     case OP_CONCAT:
       return launch_concat_w<W, kInl>(a, s);
     case OP_UNION:
       if (same_level)
-        hipLaunchKernelGGL((gen_union<W, true, kInl>), dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
+        launch_timed(gen_union<W, true, kInl>, dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
       else
-        hipLaunchKernelGGL((gen_union<W, false, kInl>), dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
+        launch_timed(gen_union<W, false, kInl>, dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
       break;
     default:
       return hipErrorInvalidValue;
