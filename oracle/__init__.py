@@ -51,6 +51,8 @@ def _load():
     lib.oracle_create.argtypes = [cp, strarr, ip, strarr, ip, ctypes.POINTER(ip), ip,
                                   ll, ip, ip, ctypes.POINTER(ip)]
     lib.oracle_solve.argtypes = [vp]
+    lib.oracle_set_on_the_fly.argtypes = [vp, ip]
+    lib.oracle_set_on_the_fly.restype = None
     lib.oracle_destroy.argtypes = [vp]
     for name in ("oracle_status", "oracle_cost", "oracle_ic_size", "oracle_max_cost"):
         getattr(lib, name).argtypes = [vp]
@@ -104,7 +106,8 @@ class Oracle:
 
     def __init__(self, alphabet: str, pos: Sequence[str], neg: Sequence[str],
                  costs=(1, 1, 1, 1, 1), max_cost: int = 30,
-                 row_cap: int = 1 << 40, max_errors: int = 0, threads: int = 1):
+                 row_cap: int = 1 << 40, max_errors: int = 0, threads: int = 1,
+                 on_the_fly: bool = False):
         lib = _load()
         st = ctypes.c_int(0)
         c = (ctypes.c_int * 5)(*costs)
@@ -113,6 +116,7 @@ class Oracle:
                                     int(max_errors), int(threads), ctypes.byref(st))
         if not self._h:
             raise OracleError(st.value)
+        lib.oracle_set_on_the_fly(self._h, 1 if on_the_fly else 0)
         self._lib = lib
         self.max_cost = int(max_cost)
 
@@ -168,5 +172,6 @@ class Oracle:
 
 
 def solve(alphabet, pos, neg, costs=(1, 1, 1, 1, 1), max_cost=30, row_cap=1 << 40,
-          max_errors=0, threads=1) -> OracleResult:
-    return Oracle(alphabet, pos, neg, costs, max_cost, row_cap, max_errors, threads).solve()
+          max_errors=0, threads=1, on_the_fly=False) -> OracleResult:
+    return Oracle(alphabet, pos, neg, costs, max_cost, row_cap, max_errors, threads,
+                  on_the_fly).solve()

@@ -50,8 +50,19 @@
 //
 // Row cap: at most row_cap languages are kept (all levels, base level
 // included); a new non-answer language beyond it stops the search with
-// status OUT_OF_MEMORY (the language cache is full, "OnTheFly mode" is not
-// modelled).
+// status OUT_OF_MEMORY (the language cache is full).
+//
+// OnTheFly mode (Sec. 3, "OnTheFly mode"; optional here): instead of
+// stopping at that language, the search goes on without storing and without
+// uniqueness checks, testing every further candidate for precision only.
+// The level where the cache filled (otf_level) is incomplete, and so is
+// every later level (nothing of them is stored).  A later level is still
+// enumerated block by block in the usual order while a block's operand
+// levels are complete (cost below otf_level); a block that needs an
+// incomplete level stops the search with OUT_OF_MEMORY, unless one of its
+// operand levels is complete and empty (then the block has no candidates).
+// Candidates found this way count in candidates[c]; nothing counts as new in
+// unique[c] once the cache is full.
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
@@ -88,6 +99,8 @@ struct Oracle {
   int64_t row_cap = 0;
   int max_err = 0;
   int threads = 1;
+  bool otf = false;   // OnTheFly mode allowed
+  int otf_level = 0;  // level where the cache filled (0: not reached)
 
   // staged
   std::vector<std::string> ic;
@@ -285,6 +298,18 @@ bool flush(Oracle& o, int c, std::vector<Cand>& buf) {
   }
   for (size_t k = 0; k < buf.size(); ++k) {
     o.cand[c] += 1;
+    if (o.otf_level) {
+      // OnTheFly: no storage, no uniqueness check; precision only
+      if (misclassified(o, out[k]) <= o.max_err) {
+        o.status = ST_OK;
+        o.answer_cost = c;
+        o.answer = buf[k];
+        o.answer_text = print_node(o, buf[k].op, buf[k].x, buf[k].y);
+        buf.clear();
+        return true;
+      }
+      continue;
+    }
     if (o.seen.count(out[k])) continue;
     if (misclassified(o, out[k]) <= o.max_err) {
       o.uniq[c] += 1;
@@ -296,6 +321,10 @@ bool flush(Oracle& o, int c, std::vector<Cand>& buf) {
       return true;
     }
     if ((int64_t)o.cs.size() + 1 > o.row_cap) {
+      if (o.otf) {
+        o.otf_level = c;  // this language is not kept; the rest goes on the fly
+        continue;
+      }
       o.status = ST_OUT_OF_MEMORY;
       buf.clear();
       return true;
@@ -327,13 +356,32 @@ bool build_level(Oracle& o, int c) {
     static const std::vector<int64_t> none;
     return (k >= o.c1 && k < (int)o.level.size()) ? o.level[k] : none;
   };
+  // OnTheFly: may a block over operand levels a (and b) be enumerated?  A
+  // level is complete when it lies below the level where the cache filled.
+  // Returns false after stopping the search (the candidates that come
+  // before the block in enumeration order have been processed).
+  auto usable = [&](int a, int b) -> bool {
+    if (!o.otf_level) return true;
+    auto exists = [&](int k) { return k >= o.c1; };
+    auto complete = [&](int k) { return k < o.otf_level; };
+    if (!exists(a) || (b >= 0 && !exists(b))) return true;  // no such block
+    const bool ca = complete(a), cb = b < 0 || complete(b);
+    if (ca && cb) return true;
+    if ((ca && lvl(a).empty()) || (b >= 0 && cb && lvl(b).empty())) return true;  // no candidates
+    if (flush(o, c, buf)) return false;
+    o.status = ST_OUT_OF_MEMORY;
+    return false;
+  };
   // Q, then S
+  if (!usable(c - o.c2, -1)) return true;
   for (int64_t x : lvl(c - o.c2))
     if (push(OP_QUESTION, x, -1)) return true;
+  if (!usable(c - o.c3, -1)) return true;
   for (int64_t x : lvl(c - o.c3))
     if (push(OP_STAR, x, -1)) return true;
   // C: left cost ascending
   for (int L = o.c1; c - o.c4 - L >= o.c1; ++L) {
+    if (!usable(L, c - o.c4 - L)) return true;
     const auto& A = lvl(L);
     const auto& B = lvl(c - o.c4 - L);
     for (int64_t x : A)
@@ -343,6 +391,7 @@ bool build_level(Oracle& o, int c) {
   // U: left cost ascending, left cost <= right cost
   for (int L = o.c1; L <= c - o.c5 - L; ++L) {
     int R = c - o.c5 - L;
+    if (!usable(L, R)) return true;
     const auto& A = lvl(L);
     const auto& B = lvl(R);
     if (L < R) {
@@ -360,6 +409,7 @@ bool build_level(Oracle& o, int c) {
 
 void solve(Oracle& o) {
   o.status = ST_NOT_FOUND;
+  o.otf_level = 0;
   o.uniq.assign(o.max_cost + 1, 0);
   o.cand.assign(o.max_cost + 1, 0);
   o.level.assign(o.max_cost + 1, {});
@@ -389,6 +439,16 @@ void solve(Oracle& o) {
     if (it != o.index.end()) x[it->second] = 1;
     int c = o.c1;
     o.cand[c] += 1;
+    if (o.otf_level) {
+      if (misclassified(o, x) <= o.max_err) {
+        o.status = ST_OK;
+        o.answer_cost = c;
+        o.answer = {OP_CHAR, (int64_t)a, -1};
+        o.answer_text = std::string(1, o.sigma[a]);
+        return;
+      }
+      continue;
+    }
     if (o.seen.count(x)) continue;
     if (misclassified(o, x) <= o.max_err) {
       o.uniq[c] += 1;
@@ -398,7 +458,14 @@ void solve(Oracle& o) {
       o.answer_text = std::string(1, o.sigma[a]);
       return;
     }
-    if ((int64_t)o.cs.size() + 1 > o.row_cap) { o.status = ST_OUT_OF_MEMORY; return; }
+    if ((int64_t)o.cs.size() + 1 > o.row_cap) {
+      if (o.otf) {
+        o.otf_level = c;
+        continue;
+      }
+      o.status = ST_OUT_OF_MEMORY;
+      return;
+    }
     int64_t id = (int64_t)o.cs.size();
     o.seen.emplace(x, id);
     o.cs.push_back(x);
@@ -499,6 +566,8 @@ void* oracle_create(const char* alphabet, const char* const* pos, int npos, cons
   }
   return o;
 }
+
+void oracle_set_on_the_fly(void* h, int enable) { ((Oracle*)h)->otf = enable != 0; }
 
 int oracle_solve(void* h) {
   Oracle* o = (Oracle*)h;
