@@ -186,6 +186,17 @@ rei_status rei_set_chunk(rei_instance *inst, uint64_t max_candidates);
  * with every lower level kept, continues on rei_solve's path.  Results do not
  * depend on it. */
 rei_status rei_set_batch_level(rei_instance *inst, uint64_t max_candidates);
+/* OnTheFly mode (Sec. 3, "OnTheFly mode"), off by default.  When on, the
+ * first new language that does not fit the cache budget does not stop the
+ * search: from there on candidates are neither stored nor checked for
+ * uniqueness, only for precision, while every constructor block drawn on
+ * lies in complete (fully stored) levels.  The first block that needs the
+ * level where the cache filled, or a later one, ends the search with
+ * REI_OUT_OF_MEMORY (a block with a complete, empty operand level has no
+ * candidates and is skipped).  An answer found this way is the answer of a
+ * search without a cap.  unique_per_level counts stored languages only.
+ * Instances with it on are solved on rei_solve's path by rei_solve_batch. */
+rei_status rei_set_on_the_fly(rei_instance *inst, int enable);
 /* Misclassified examples allowed (REI with error, Sec. 7); 0 = precise. */
 rei_status rei_set_max_errors(rei_instance *inst, uint32_t max_errors);
 

@@ -172,6 +172,16 @@ __device__ __forceinline__ void table_rebuild_one(uint64_t* slots, uint64_t mask
     pos = (pos + 1) & mask;
 }
 
+// Examples a language misclassifies: positives it lacks, negatives it has.
+template <int W>
+__device__ __forceinline__ int misclassified(const uint64_t* pmask, const uint64_t* nmask,
+                                             const uint64_t (&key)[W]) {
+  int bad = 0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) bad += __popcll(pmask[k] & ~key[k]) + __popcll(nmask[k] & key[k]);
+  return bad;
+}
+
 // Where a generator probes: the cache rows and the dedup table, and the
 // precision masks.
 struct Probe {
@@ -211,14 +221,10 @@ __device__ __forceinline__ void filter_emit(const Probe& a, const Sink& o, bool 
   if (surv) {
     const uint32_t sid = base + (uint32_t)__popcll(m & ((1ull << lane) - 1));
     uint64_t* dst = o.skey + (uint64_t)sid * W;
-    int bad = 0;
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
-      dst[k] = key[k];
-      bad += __popcll(a.pmask[k] & ~key[k]) + __popcll(a.nmask[k] & key[k]);
-    }
+    for (int k = 0; k < W; ++k) dst[k] = key[k];
     o.se[sid] = e_rel;
-    if (bad <= (int)a.max_err) atomicMin(o.answer_e, e_rel);
+    if (misclassified<W>(a.pmask, a.nmask, key) <= (int)a.max_err) atomicMin(o.answer_e, e_rel);
   }
 }
 

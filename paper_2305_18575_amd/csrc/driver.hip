@@ -107,6 +107,11 @@ struct rei_instance {
   uint64_t known_rows = 0;
   // set when the batched solver handed the instance over at this level
   uint32_t resume_level = 0;
+  // OnTheFly mode (Sec. 3): allowed, level where the cache filled (0: not
+  // yet), and whether a level needed an incomplete one
+  bool otf_on = false;
+  uint32_t otf_level = 0;
+  bool otf_blocked = false;
   uint64_t pending = 0;
 
   // levels, indexed by cost
@@ -301,27 +306,44 @@ uint64_t level_n(const rei_instance* in, int64_t c) {
 
 bool mul_ok(uint64_t a, uint64_t b, uint64_t* out) { return !__builtin_mul_overflow(a, b, out); }
 
-// Constructor blocks of level c in enumeration order.
-bool make_blocks(const rei_instance* in, uint32_t c, std::vector<Block>* out) {
+// Constructor blocks of level c in enumeration order.  In OnTheFly mode the
+// list ends before the first block that needs an incomplete level (the one
+// where the cache filled, or a later one) and *blocked is set, unless a
+// complete operand level of that block is empty (it has no candidates).
+bool make_blocks(const rei_instance* in, uint32_t c, std::vector<Block>* out, bool* blocked = nullptr) {
   out->clear();
+  if (blocked) *blocked = false;
   const rei_costs& k = in->costs;
   if (c == k.c_char) {
     out->push_back({OP_CHAR, 0, 0, (uint64_t)in->st.sigma.size(), false});
     return true;
   }
   const int64_t cc = c;
+  const int64_t full = in->otf_level;
+  auto usable = [&](int64_t a, int64_t b) -> bool {
+    if (!full || a < (int64_t)k.c_char || (b >= 0 && b < (int64_t)k.c_char)) return true;
+    const bool ca = a < full, cb = b < 0 || b < full;
+    if (ca && cb) return true;
+    if ((ca && level_n(in, a) == 0) || (b >= 0 && cb && level_n(in, b) == 0)) return true;
+    if (blocked) *blocked = true;
+    return false;
+  };
+  if (!usable(cc - k.c_question, -1)) return true;
   if (level_n(in, cc - k.c_question))
     out->push_back({OP_QUESTION, (uint32_t)(cc - k.c_question), 0, level_n(in, cc - k.c_question), false});
+  if (!usable(cc - k.c_star, -1)) return true;
   if (level_n(in, cc - k.c_star))
     out->push_back({OP_STAR, (uint32_t)(cc - k.c_star), 0, level_n(in, cc - k.c_star), false});
   for (int64_t L = k.c_char; cc - (int64_t)k.c_concat - L >= (int64_t)k.c_char; ++L) {
     const int64_t R = cc - k.c_concat - L;
+    if (!usable(L, R)) return true;
     uint64_t n;
     if (!mul_ok(level_n(in, L), level_n(in, R), &n)) return false;
     if (n) out->push_back({OP_CONCAT, (uint32_t)L, (uint32_t)R, n, false});
   }
   for (int64_t L = k.c_char; L <= cc - (int64_t)k.c_union - L; ++L) {
     const int64_t R = cc - k.c_union - L;
+    if (!usable(L, R)) return true;
     const uint64_t a = level_n(in, L), b = level_n(in, R);
     uint64_t n;
     if (L < R) {
@@ -357,8 +379,10 @@ rei_status enqueue_chunk(rei_instance* in, hipStream_t s, uint32_t c, const Bloc
   rei_status r;
   auto worst_rows = [&] { return std::min(in->row_cap, in->known_rows + in->pending + len); };
   auto worst_entries = [&] { return in->known_rows + in->pending + len; };
-  if (worst_rows() > in->rows_alloc || 2 * worst_entries() > in->slots_cap || len > in->surv_cap ||
-      words > in->bitmap_cap) {
+  // a level enumerated in OnTheFly mode stores nothing: no buffer grows
+  const bool otf_level = in->otf_level != 0;
+  if (!otf_level && (worst_rows() > in->rows_alloc || 2 * worst_entries() > in->slots_cap ||
+                     len > in->surv_cap || words > in->bitmap_cap)) {
     if ((r = sync_state(in, s)) != REI_OK) return r;
     if (in->h_state->stop) {
       *stopped = true;
@@ -424,6 +448,10 @@ rei_status enqueue_chunk(rei_instance* in, hipStream_t s, uint32_t c, const Bloc
   ca.cost = c;
   ca.chunk_e0 = e_base + e0;
   ca.len = len;
+  if (otf_level) {
+    LAUNCH(in, s, REI_K_COMPACT, len, launch_account(ca, s));
+    return REI_OK;
+  }
   LAUNCH(in, s, REI_K_INSERT, len, launch_insert(W, ca, s));
   LAUNCH(in, s, REI_K_COMPACT, len, launch_finalize(W, ca, s));
   in->pending += len;
@@ -590,6 +618,8 @@ bool begin_solve(rei_instance* in, double t0) {
   in->h_aux_valid = false;
   in->tree.clear();
   in->resume_level = 0;
+  in->otf_level = 0;
+  in->otf_blocked = false;
   if (in->max_cost < c1) {
     fill_result(in, REI_NOT_FOUND, 0, 0, t0);
     return true;
@@ -630,7 +660,7 @@ rei_status finish_solve(rei_instance* in, double t0) {
   rei_status final_status = REI_NOT_FOUND;
   uint32_t cost = 0, last = in->max_cost;
   rei_status r;
-  if (in->h_state->stop == STOP_OOM) {
+  if (in->h_state->stop == STOP_OOM || (in->h_state->stop == STOP_NONE && in->otf_blocked)) {
     final_status = REI_OUT_OF_MEMORY;
     last = last_used;
   }
@@ -667,7 +697,9 @@ rei_status search_levels(rei_instance* in, hipStream_t s) {
   std::fill(in->lcount.begin(), in->lcount.end(), 0);
   const uint32_t c_from = in->resume_level;
   in->resume_level = 0;
-  LAUNCH(in, s, REI_K_OTHER, 1, launch_state_reset(in->d_ctrl, in->d_state, in->row_cap, s));
+  in->otf_level = 0;
+  in->otf_blocked = false;
+  LAUNCH(in, s, REI_K_OTHER, 1, launch_state_reset(in->d_ctrl, in->d_state, in->row_cap, in->otf_on, s));
   if (c_from > c1) {
     // The batched solver stored every level below c_from (rows and
     // back-pointers) and wrote its state and counters to the pinned mirrors:
@@ -705,7 +737,8 @@ rei_status search_levels(rei_instance* in, hipStream_t s) {
   bool stopped = false;
   for (uint32_t c = c_from > c1 ? c_from : c1; c <= in->max_cost && !stopped; ++c) {
     in->lstart[c] = in->known_rows;
-    if (!make_blocks(in, c, &blocks)) {
+    bool blocked = false;
+    if (!make_blocks(in, c, &blocks, &blocked)) {
       in->err = "candidate count overflows 64 bits";
       return REI_ERR_TOO_LARGE;
     }
@@ -723,6 +756,11 @@ rei_status search_levels(rei_instance* in, hipStream_t s) {
     if ((r = sync_state(in, s)) != REI_OK) return r;
     in->lcount[c] = in->h_levels[c];
     if (in->h_state->stop) stopped = true;
+    if (!stopped && blocked) {
+      in->otf_blocked = true;  // a block needs a level that is not stored
+      stopped = true;
+    }
+    if (in->h_state->otf && !in->otf_level) in->otf_level = c;
   }
   return REI_OK;
 }
@@ -747,7 +785,8 @@ uint64_t batch_rows(const rei_instance* in, uint64_t arena_bytes) {
 }
 
 bool batchable(const rei_instance* in) {
-  return in->st.W <= kBatchMaxW && in->max_cost <= kBatchMaxCost && in->st.gt_pair.size() <= kBatchMaxPairs;
+  return in->st.W <= kBatchMaxW && in->max_cost <= kBatchMaxCost && in->st.gt_pair.size() <= kBatchMaxPairs &&
+         !in->otf_on;
 }
 
 // ---- batched solving -------------------------------------------------------
@@ -1233,6 +1272,12 @@ rei_status rei_set_chunk(rei_instance* inst, uint64_t max_candidates) {
 rei_status rei_set_batch_level(rei_instance* inst, uint64_t max_candidates) {
   if (!inst) return REI_ERR_INVALID_ARG;
   inst->batch_level_max = max_candidates ? max_candidates : kBatchLevelMax;
+  return REI_OK;
+}
+
+rei_status rei_set_on_the_fly(rei_instance* inst, int enable) {
+  if (!inst) return REI_ERR_INVALID_ARG;
+  inst->otf_on = enable != 0;
   return REI_OK;
 }
 

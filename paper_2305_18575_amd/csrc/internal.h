@@ -74,7 +74,9 @@ struct DevState {
   uint32_t answer_cost;
   uint64_t answer_e;        // level enumeration index of the answer
   uint64_t resume_level;    // STOP_HANDOFF: the first level not searched
-  uint64_t pad[3];
+  uint32_t otf_on;          // OnTheFly mode allowed when the cache fills
+  uint32_t otf;             // OnTheFly mode active: no storage, precision only
+  uint64_t pad[2];
 };
 
 // Arguments shared by all generator kernels.
@@ -159,7 +161,10 @@ hipError_t launch_insert(int W, const ChunkArgs& a, hipStream_t s);
 // Winners, their ranks, the stored rows and the accounting of the chunk:
 // one workgroup when the chunk is small (LDS bitmap), else a grid pipeline.
 hipError_t launch_finalize(int W, const ChunkArgs& a, hipStream_t s);
-hipError_t launch_state_reset(Ctrl* c, DevState* st, uint64_t row_cap, hipStream_t s);
+// Accounting of a chunk without survivors (a level enumerated in OnTheFly
+// mode): the answer, if any, and the candidate count.
+hipError_t launch_account(const ChunkArgs& a, hipStream_t s);
+hipError_t launch_state_reset(Ctrl* c, DevState* st, uint64_t row_cap, bool otf_on, hipStream_t s);
 constexpr uint64_t kSmallChunk = 1ull << 14;   // candidates finalized by one workgroup
 
 const char* gen_kernel_name(int op);

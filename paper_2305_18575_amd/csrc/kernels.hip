@@ -26,9 +26,17 @@ namespace rei {
 namespace {
 
 // Probe the table and append survivors (see filter_emit in device_common.h).
+// In OnTheFly mode (Sec. 3) the cache is full: no probe and no survivors,
+// only the precision test (a known duplicate equals a stored language, which
+// is not precise, or the search would have stopped there).
 template <int W, bool kInl>
 __device__ __forceinline__ void filter_emit(const GenArgs& a, bool valid, bool known_dup,
                                             const uint64_t (&key)[W], uint32_t e_rel) {
+  if (a.st->otf) {
+    if (valid && !known_dup && misclassified<W>(a.pmask, a.nmask, key) <= (int)a.max_err)
+      atomicMin(&a.ctrl->answer_e, e_rel);
+    return;
+  }
   const Probe p{a.rows, a.slots, a.slot_mask, a.pmask, a.nmask, a.max_err};
   const Sink k{a.skey, a.se, &a.ctrl->n_surv, &a.ctrl->answer_e};
   filter_emit<W, kInl>(p, k, valid, known_dup, key, e_rel);
@@ -257,13 +265,16 @@ __device__ __forceinline__ void ctrl_clear(Ctrl* c) {
   c->overflow_e = ~0u;
 }
 
-__global__ void state_reset(Ctrl* c, DevState* st, uint64_t row_cap) {
+__global__ void state_reset(Ctrl* c, DevState* st, uint64_t row_cap, uint32_t otf_on) {
   ctrl_clear(c);
   st->total_rows = 0;
   st->row_cap = row_cap;
   st->stop = STOP_NONE;
   st->answer_cost = 0;
   st->answer_e = 0;
+  st->resume_level = 0;
+  st->otf_on = otf_on;
+  st->otf = 0;
 }
 
 template <int W, bool kInl>
@@ -294,14 +305,35 @@ __global__ __launch_bounds__(256) void insert_survivors(ChunkArgs a) {
 // Outcome of a chunk, in enumeration order: the answer (first precise
 // candidate) if its winners before it fit the row cap, else out of memory at
 // the first winner that does not fit; otherwise all winners are stored.
+// With OnTheFly allowed, the first winner that does not fit switches the
+// search to OnTheFly mode instead: the winners that fit are stored, and the
+// rest of the chunk (and of the search) is tested for precision only.
 __device__ void account_chunk(const ChunkArgs& a, uint32_t ans, uint32_t answer_rank, uint32_t winners,
                               uint32_t overflow_e) {
   DevState* st = a.st;
   const uint64_t room = st->row_cap > st->total_rows ? st->row_cap - st->total_rows : 0;
   const uint32_t c = a.cost;
   uint64_t stored;
-  if (ans != ~0u) {
-    if ((uint64_t)answer_rank > room) {
+  if (st->otf) {
+    stored = 0;
+    if (ans != ~0u) {
+      a.cand[c] += (uint64_t)ans + 1;
+      st->stop = STOP_ANSWER;
+      st->answer_cost = c;
+      st->answer_e = a.chunk_e0 + ans;
+    } else {
+      a.cand[c] += a.len;
+    }
+  } else if (ans != ~0u) {
+    if ((uint64_t)answer_rank > room && st->otf_on) {
+      // the cache filled before the answer, which is found on the fly
+      stored = room;
+      a.cand[c] += (uint64_t)ans + 1;
+      a.uniq[c] += room;
+      st->stop = STOP_ANSWER;
+      st->answer_cost = c;
+      st->answer_e = a.chunk_e0 + ans;
+    } else if ((uint64_t)answer_rank > room) {
       stored = room;
       a.cand[c] += (uint64_t)overflow_e + 1;
       a.uniq[c] += room;
@@ -314,6 +346,11 @@ __device__ void account_chunk(const ChunkArgs& a, uint32_t ans, uint32_t answer_
       st->answer_cost = c;
       st->answer_e = a.chunk_e0 + ans;
     }
+  } else if ((uint64_t)winners > room && st->otf_on) {
+    stored = room;
+    a.cand[c] += a.len;
+    a.uniq[c] += room;
+    st->otf = 1;
   } else if ((uint64_t)winners > room) {
     stored = room;
     a.cand[c] += (uint64_t)overflow_e + 1;
@@ -609,8 +646,8 @@ hipError_t launch_fill(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_state_reset(Ctrl* c, DevState* st, uint64_t row_cap, hipStream_t s) {
-  hipLaunchKernelGGL(state_reset, dim3(1), dim3(1), 0, s, c, st, row_cap);
+hipError_t launch_state_reset(Ctrl* c, DevState* st, uint64_t row_cap, bool otf_on, hipStream_t s) {
+  hipLaunchKernelGGL(state_reset, dim3(1), dim3(1), 0, s, c, st, row_cap, otf_on ? 1u : 0u);
   return hipGetLastError();
 }
 
@@ -651,6 +688,11 @@ hipError_t launch_finalize(int W, const ChunkArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(scan_top, dim3(1), dim3(1024), 0, s, a, nb);
   hipLaunchKernelGGL(scan_down, dim3(nb), dim3(256), 0, s, a);
   REI_DISPATCH_WI(W, a.inl, hipLaunchKernelGGL((compact_winners<kW, kI>), dim3(g), dim3(256), 0, s, a));
+  hipLaunchKernelGGL(account_large, dim3(1), dim3(1), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_account(const ChunkArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(account_large, dim3(1), dim3(1), 0, s, a);
   return hipGetLastError();
 }

@@ -310,3 +310,62 @@ def test_batch_handoff_resumes_exactly(rei, level_max):
         check_against_oracle(r, spec)
     for h in hs:
         h.close()
+
+
+# ---- OnTheFly mode (Sec. 3) ----
+
+def _otf_cases():
+    cases = []
+    for seed in (1, 3, 4, 6, 8):
+        it = instances.single_instance(seed, (1, 1, 1, 1, 1))
+        for costs in ((1, 1, 1, 1, 1), (1, 3, 3, 3, 3), (2, 5, 5, 5, 5), (1, 1, 5, 1, 2)):
+            full = oracle.solve(it.alphabet, it.pos, it.neg, costs, 40, 1 << 40, 0, 8)
+            total = sum(full.unique)
+            for frac in (0.3, 0.8):
+                cases.append((it, costs, max(1, int(total * frac))))
+    return cases
+
+
+@pytest.mark.parametrize("chunk", [0, 100])
+def test_on_the_fly_parity(rei, chunk):
+    """The cache fills mid-level (in a chunk of its own with chunk=100, inside
+    one large chunk otherwise); the rest of that level and the later levels
+    whose blocks use complete levels run on the fly.  Status, cost, regex and
+    per-level counts equal the oracle's OnTheFly search."""
+    n_ok = n_oom = 0
+    for it, costs, cap in _otf_cases():
+        h = rei.Instance(it.alphabet, it.pos, it.neg, costs, 40, 1 << 30)
+        probe = h.solve()
+        words = probe.cs_words
+        h.close()
+        cache = cap * (8 * words + 8)
+        print(f"\nOnTheFly seed-instance costs {costs} cap {cap} rows chunk {chunk}", flush=True)
+        h = rei.Instance(it.alphabet, it.pos, it.neg, costs, 40, cache)
+        h.set_on_the_fly(True)
+        if chunk:
+            h.set_chunk(chunk)
+        g = h.solve()
+        o = oracle.solve(it.alphabet, it.pos, it.neg, costs, 40, cap, 0, 8, on_the_fly=True)
+        assert (g.status, g.cost, g.regex) == (o.status, o.cost, o.regex), (costs, cap, g, o)
+        for c in range(41):
+            assert g.unique_at(c) == o.unique[c], (c, g.unique, o.unique)
+            assert g.candidates_at(c) == o.candidates[c], (c, g.candidates, o.candidates)
+        n_ok += g.status == "OK"
+        n_oom += g.status == "OUT_OF_MEMORY"
+        h.close()
+    assert n_ok > 5 and n_oom > 5
+
+
+def test_on_the_fly_in_a_batch_runs_on_the_grid(rei):
+    it = instances.single_instance(3, (1, 1, 1, 1, 1))
+    costs = (1, 3, 3, 3, 3)
+    full = oracle.solve(it.alphabet, it.pos, it.neg, costs, 40, 1 << 40, 0, 8)
+    cap = sum(full.unique) // 2
+    h = rei.Instance(it.alphabet, it.pos, it.neg, costs, 40, cap * (8 * 2 + 8))
+    h.set_on_the_fly(True)
+    other = rei.Instance(it.alphabet, it.pos, it.neg, (1, 1, 1, 1, 1), it.max_cost)
+    rb, _ = rei.solve_batch([h, other])
+    o = oracle.solve(it.alphabet, it.pos, it.neg, costs, 40, cap, 0, 8, on_the_fly=True)
+    assert (rb.status, rb.cost, rb.regex) == (o.status, o.cost, o.regex)
+    h.close()
+    other.close()
