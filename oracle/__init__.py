@@ -53,6 +53,8 @@ def _load():
     lib.oracle_solve.argtypes = [vp]
     lib.oracle_set_on_the_fly.argtypes = [vp, ip]
     lib.oracle_set_on_the_fly.restype = None
+    lib.oracle_set_char_costs.argtypes = [vp, ctypes.POINTER(ip), ip]
+    lib.oracle_set_char_costs.restype = ip
     lib.oracle_destroy.argtypes = [vp]
     for name in ("oracle_status", "oracle_cost", "oracle_ic_size", "oracle_max_cost"):
         getattr(lib, name).argtypes = [vp]
@@ -107,7 +109,7 @@ class Oracle:
     def __init__(self, alphabet: str, pos: Sequence[str], neg: Sequence[str],
                  costs=(1, 1, 1, 1, 1), max_cost: int = 30,
                  row_cap: int = 1 << 40, max_errors: int = 0, threads: int = 1,
-                 on_the_fly: bool = False):
+                 on_the_fly: bool = False, char_costs: Optional[Sequence[int]] = None):
         lib = _load()
         st = ctypes.c_int(0)
         c = (ctypes.c_int * 5)(*costs)
@@ -118,6 +120,10 @@ class Oracle:
             raise OracleError(st.value)
         lib.oracle_set_on_the_fly(self._h, 1 if on_the_fly else 0)
         self._lib = lib
+        if char_costs is not None:
+            arr = (ctypes.c_int * max(1, len(char_costs)))(*char_costs)
+            if lib.oracle_set_char_costs(self._h, arr, len(char_costs)) != 0:
+                raise OracleError(-1, "bad per-character costs")
         self.max_cost = int(max_cost)
 
     def __del__(self):
@@ -172,6 +178,6 @@ class Oracle:
 
 
 def solve(alphabet, pos, neg, costs=(1, 1, 1, 1, 1), max_cost=30, row_cap=1 << 40,
-          max_errors=0, threads=1, on_the_fly=False) -> OracleResult:
+          max_errors=0, threads=1, on_the_fly=False, char_costs=None) -> OracleResult:
     return Oracle(alphabet, pos, neg, costs, max_cost, row_cap, max_errors, threads,
-                  on_the_fly).solve()
+                  on_the_fly, char_costs).solve()

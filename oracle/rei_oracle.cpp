@@ -48,6 +48,12 @@
 // misclassified examples (REI with error, Sec. 7) these read: the empty
 // language if |P| <= k, else eps if it misclassifies at most k examples.
 //
+// Per-character costs (the cost-homomorphism definition allows a different
+// cost for each alphabet character): character a enters at level cost(a),
+// before every other block of that level, in alphabet order.  The smallest
+// character cost takes the place of c1 (first level, cost of the trivial
+// answers).  With equal character costs this is the order above.
+//
 // Row cap: at most row_cap languages are kept (all levels, base level
 // included); a new non-answer language beyond it stops the search with
 // status OUT_OF_MEMORY (the language cache is full).
@@ -99,6 +105,7 @@ struct Oracle {
   int64_t row_cap = 0;
   int max_err = 0;
   int threads = 1;
+  std::vector<int> char_cost;  // per alphabet character (empty: all c1)
   bool otf = false;   // OnTheFly mode allowed
   int otf_level = 0;  // level where the cache filled (0: not reached)
 
@@ -240,8 +247,16 @@ int misclassified(const Oracle& o, const std::string& x) {
   return bad;
 }
 
+std::string op_char(const Oracle& o, int64_t a) {
+  std::string r(o.ic.size(), 0);
+  auto it = o.index.find(std::string(1, o.sigma[a]));
+  if (it != o.index.end()) r[it->second] = 1;
+  return r;
+}
+
 std::string compute(const Oracle& o, const Cand& c) {
   switch (c.op) {
+    case OP_CHAR: return op_char(o, c.x);
     case OP_QUESTION: return op_question(o, o.cs[c.x]);
     case OP_STAR: return op_star(o, o.cs[c.x]);
     case OP_CONCAT: return op_concat(o, o.cs[c.x], o.cs[c.y]);
@@ -372,7 +387,11 @@ bool build_level(Oracle& o, int c) {
     o.status = ST_OUT_OF_MEMORY;
     return false;
   };
-  // Q, then S
+  // characters of this cost, then Q, then S
+  for (size_t a = 0; a < o.sigma.size(); ++a) {
+    const int ca = o.char_cost.empty() ? o.c1 : o.char_cost[a];
+    if (ca == c && push(OP_CHAR, (int64_t)a, -1)) return true;
+  }
   if (!usable(c - o.c2, -1)) return true;
   for (int64_t x : lvl(c - o.c2))
     if (push(OP_QUESTION, x, -1)) return true;
@@ -432,51 +451,7 @@ void solve(Oracle& o) {
       return;
     }
   }
-  // level c1: the alphabet characters
-  for (size_t a = 0; a < o.sigma.size(); ++a) {
-    std::string x(o.ic.size(), 0);
-    auto it = o.index.find(std::string(1, o.sigma[a]));
-    if (it != o.index.end()) x[it->second] = 1;
-    int c = o.c1;
-    o.cand[c] += 1;
-    if (o.otf_level) {
-      if (misclassified(o, x) <= o.max_err) {
-        o.status = ST_OK;
-        o.answer_cost = c;
-        o.answer = {OP_CHAR, (int64_t)a, -1};
-        o.answer_text = std::string(1, o.sigma[a]);
-        return;
-      }
-      continue;
-    }
-    if (o.seen.count(x)) continue;
-    if (misclassified(o, x) <= o.max_err) {
-      o.uniq[c] += 1;
-      o.status = ST_OK;
-      o.answer_cost = c;
-      o.answer = {OP_CHAR, (int64_t)a, -1};
-      o.answer_text = std::string(1, o.sigma[a]);
-      return;
-    }
-    if ((int64_t)o.cs.size() + 1 > o.row_cap) {
-      if (o.otf) {
-        o.otf_level = c;
-        continue;
-      }
-      o.status = ST_OUT_OF_MEMORY;
-      return;
-    }
-    int64_t id = (int64_t)o.cs.size();
-    o.seen.emplace(x, id);
-    o.cs.push_back(x);
-    o.op.push_back(OP_CHAR);
-    o.arg_a.push_back((int64_t)a);
-    o.arg_b.push_back(-1);
-    o.row_level.push_back(c);
-    o.level[c].push_back(id);
-    o.uniq[c] += 1;
-  }
-  for (int c = o.c1 + 1; c <= o.max_cost; ++c)
+  for (int c = o.c1; c <= o.max_cost; ++c)
     if (build_level(o, c)) return;
 }
 
@@ -568,6 +543,21 @@ void* oracle_create(const char* alphabet, const char* const* pos, int npos, cons
 }
 
 void oracle_set_on_the_fly(void* h, int enable) { ((Oracle*)h)->otf = enable != 0; }
+
+// Per-character costs, one per alphabet character in alphabet order (all at
+// least 1); the smallest becomes c1.  Returns 0, or -1 on a bad argument.
+int oracle_set_char_costs(void* h, const int* costs, int n) {
+  Oracle* o = (Oracle*)h;
+  if (n != (int)o->sigma.size()) return -1;
+  int lo = 0;
+  for (int i = 0; i < n; ++i) {
+    if (costs[i] < 1) return -1;
+    lo = i == 0 ? costs[i] : std::min(lo, costs[i]);
+  }
+  o->char_cost.assign(costs, costs + n);
+  if (n) o->c1 = lo;
+  return 0;
+}
 
 int oracle_solve(void* h) {
   Oracle* o = (Oracle*)h;

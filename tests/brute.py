@@ -154,8 +154,9 @@ def to_pyre(printed: str) -> str:
     return ''.join(out)
 
 
-def regex_cost(printed: str, costs=(1, 1, 1, 1, 1)) -> int:
-    """Cost of a printed expression under the cost homomorphism (c1..c5)."""
+def regex_cost(printed: str, costs=(1, 1, 1, 1, 1), char_costs=None) -> int:
+    """Cost of a printed expression under the cost homomorphism (c1..c5);
+    ``char_costs`` maps characters to their own costs (default c1)."""
     c1, c2, c3, c4, c5 = costs
     s = printed
     pos = 0
@@ -192,7 +193,7 @@ def regex_cost(printed: str, costs=(1, 1, 1, 1, 1)) -> int:
             pos += 1
             return v
         pos += 1
-        return c1
+        return char_costs.get(s[pos - 1], c1) if char_costs else c1
 
     v = union()
     assert pos == len(s), printed
@@ -200,7 +201,7 @@ def regex_cost(printed: str, costs=(1, 1, 1, 1, 1)) -> int:
 
 
 def brute_levels(sigma: str, pos: Sequence[str], neg: Sequence[str], costs, kmax: int,
-                 max_errors: int = 0):
+                 max_errors: int = 0, char_costs=None):
     """Enumerate every expression tree of cost <= kmax over sigma with ?, *,
     concatenation and union, evaluate it on the substrings of the examples,
     and return (number of distinct languages whose cheapest tree costs c, for
@@ -217,8 +218,7 @@ def brute_levels(sigma: str, pos: Sequence[str], neg: Sequence[str], costs, kmax
     cstar: Optional[int] = None
     for k in range(1, kmax + 1):
         lst = by[k]
-        if k == c1:
-            lst.extend(m.char(a) for a in sigma)
+        lst.extend(m.char(a) for a in sigma if (char_costs[a] if char_costs else c1) == k)
         if k - c2 >= 1:
             lst.extend(m.question(x) for x in by[k - c2])
         if k - c3 >= 1:

@@ -139,3 +139,36 @@ def test_row_cap_out_of_memory(oracle_mod):
     r = oracle_mod.solve("01", inst.pos, inst.neg, row_cap=cap)
     assert r.status == "OUT_OF_MEMORY"
     assert sum(r.unique) == cap
+
+
+@pytest.mark.parametrize("seed,sigma,char_costs,costs", [
+    (0, "01", {"0": 1, "1": 2}, (1, 1, 1, 1, 1)),
+    (1, "01", {"0": 3, "1": 1}, (1, 1, 1, 1, 1)),
+    (2, "01", {"0": 2, "1": 2}, (1, 1, 2, 1, 1)),
+    (3, "012", {"0": 1, "1": 2, "2": 3}, (1, 1, 1, 1, 1)),
+    (4, "012", {"0": 2, "1": 1, "2": 1}, (1, 2, 1, 1, 2)),
+])
+def test_per_character_costs_vs_brute_force(oracle_mod, seed, sigma, char_costs, costs):
+    """Per-character costs (the cost-homomorphism definition allows one cost
+    per character): brute force gives every character its own leaf cost."""
+    rng = random.Random(seed)
+    words = ["".join(rng.choice(sigma) for _ in range(rng.randint(0, 4))) for _ in range(8)]
+    words = list(dict.fromkeys(words))
+    P, N = words[: len(words) // 2], words[len(words) // 2:]
+    kmax = 8
+    counts, cstar = brute.brute_levels(sigma, P, N, costs, kmax, 0, char_costs)
+    r = oracle_mod.solve(sigma, P, N, costs=costs, max_cost=kmax,
+                         char_costs=[char_costs[a] for a in sigma])
+    lo = min(char_costs.values())
+    if not P:
+        assert (r.status, r.cost) == ("OK", lo)
+        return
+    if cstar is None:
+        assert r.status == "NOT_FOUND"
+        for c in range(1, kmax + 1):
+            assert r.unique[c] == counts.get(c, 0), (c, r.unique, counts)
+    else:
+        assert r.status == "OK" and r.cost == cstar, (r, cstar)
+        for c in range(1, cstar):
+            assert r.unique[c] == counts.get(c, 0), (c, r.unique, counts)
+        assert brute.regex_cost(r.regex, costs, char_costs) == cstar
