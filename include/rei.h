@@ -90,7 +90,7 @@ typedef struct {
   uint32_t cost;             /* minimal cost when REI_OK                        */
   const char *regex;         /* UTF-8; "∅" / "ε" only for the trivial
                                 specifications P = {} and P = {eps}             */
-  uint32_t first_level;      /* = c_char                                        */
+  uint32_t first_level;      /* = c_char (the smallest character cost)          */
   uint32_t n_levels;         /* levels first_level .. first_level+n_levels-1    */
   const uint64_t *unique_per_level;     /* new languages per level; the last
                                            level counts those up to the answer */
@@ -186,6 +186,15 @@ rei_status rei_set_chunk(rei_instance *inst, uint64_t max_candidates);
  * with every lower level kept, continues on rei_solve's path.  Results do not
  * depend on it. */
 rei_status rei_set_batch_level(rei_instance *inst, uint64_t max_candidates);
+/* Per-character costs (the cost-homomorphism definition allows a different
+ * cost for each alphabet character).  costs[a] >= 1 is the cost of the a-th
+ * character of the alphabet given to rei_create; n must equal the alphabet
+ * size.  Character a enters at level costs[a], before the other blocks of
+ * that level, in alphabet order; the smallest of them replaces c_char (the
+ * first level, and the cost of the trivial answers ∅ and ε).  Instances with
+ * unequal character costs are solved on rei_solve's path by
+ * rei_solve_batch.  REI_ERR_INVALID_ARG on a wrong n or a zero cost. */
+rei_status rei_set_char_costs(rei_instance *inst, const uint32_t *costs, size_t n);
 /* OnTheFly mode (Sec. 3, "OnTheFly mode"), off by default.  When on, the
  * first new language that does not fit the cache budget does not stop the
  * search: from there on candidates are neither stored nor checked for

@@ -29,7 +29,7 @@ KERNEL_CLASSES = ["gen_char", "gen_question", "gen_star", "gen_concat", "gen_uni
 EXPORTS = ["rei_create", "rei_solve", "rei_solve_batch", "rei_server_create", "rei_server_submit",
            "rei_server_poll", "rei_server_destroy", "rei_destroy", "rei_status_str", "rei_last_error",
            "rei_create_error", "rei_ic_word", "rei_level_size", "rei_row_bits",
-           "rei_row_regex", "rei_set_chunk", "rei_set_batch_level", "rei_set_on_the_fly", "rei_set_max_errors", "rei_set_profiling",
+           "rei_row_regex", "rei_set_chunk", "rei_set_batch_level", "rei_set_on_the_fly", "rei_set_char_costs", "rei_set_max_errors", "rei_set_profiling",
            "rei_kernel_stats", "rei_kernel_name"]
 
 
@@ -116,6 +116,8 @@ def load_library():
     lib.rei_set_batch_level.argtypes = [vp, u64]
     lib.rei_set_on_the_fly.restype = ctypes.c_int
     lib.rei_set_on_the_fly.argtypes = [vp, ctypes.c_int]
+    lib.rei_set_char_costs.restype = ctypes.c_int
+    lib.rei_set_char_costs.argtypes = [vp, ctypes.POINTER(u32), ctypes.c_size_t]
     lib.rei_set_max_errors.restype = ctypes.c_int
     lib.rei_set_max_errors.argtypes = [vp, u32]
     lib.rei_set_profiling.restype = ctypes.c_int
@@ -221,6 +223,11 @@ class Instance:
     # ---- tuning / measurement ----
     def set_chunk(self, max_candidates: int):
         self._check(self._lib.rei_set_chunk(self._h, int(max_candidates)))
+
+    def set_char_costs(self, costs: Sequence[int]):
+        """Per-character costs, one per alphabet character in alphabet order."""
+        arr = (ctypes.c_uint32 * max(1, len(costs)))(*costs)
+        self._check(self._lib.rei_set_char_costs(self._h, arr, len(costs)))
 
     def set_on_the_fly(self, enable: bool = True):
         """OnTheFly mode: keep searching, precision only, once the cache is full."""
@@ -337,9 +344,11 @@ class Server:
 
 
 def solve(alphabet, pos, neg, costs=(1, 1, 1, 1, 1), max_cost=30, cache_bytes=1 << 30,
-          max_errors=0, chunk=0, stream=-1, on_the_fly=False) -> Result:
+          max_errors=0, chunk=0, stream=-1, on_the_fly=False, char_costs=None) -> Result:
     inst = Instance(alphabet, pos, neg, costs, max_cost, cache_bytes)
     try:
+        if char_costs is not None:
+            inst.set_char_costs(char_costs)
         if max_errors:
             inst.set_max_errors(max_errors)
         if on_the_fly:

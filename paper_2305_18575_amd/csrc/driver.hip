@@ -67,7 +67,12 @@ struct rei_instance {
   uint32_t* d_len_off = nullptr;
   uint64_t* d_pmask = nullptr;
   uint64_t* d_nmask = nullptr;
-  int32_t* d_char_index = nullptr;
+  int32_t* d_char_index = nullptr;  // ic index of each character, in char_order
+  // per-character costs (empty: every character costs c_char, which is then
+  // the smallest character cost) and the characters ordered by (cost,
+  // alphabet position): level c's base block is a contiguous run of it
+  std::vector<uint32_t> char_cost;
+  std::vector<uint32_t> char_order;
 
   // language cache
   uint64_t* d_rows = nullptr;
@@ -299,6 +304,16 @@ rei_status ensure_chunk_buffers(rei_instance* in, uint64_t len) {
   return REI_OK;
 }
 
+// The characters of cost c: positions [*first, *first + *count) of char_order.
+void chars_at(const rei_instance* in, int64_t c, uint32_t* first, uint32_t* count) {
+  *first = *count = 0;
+  for (uint32_t a : in->char_order) {
+    const uint32_t ca = in->char_cost.empty() ? in->costs.c_char : in->char_cost[a];
+    if ((int64_t)ca < c) ++*first;
+    if ((int64_t)ca == c) ++*count;
+  }
+}
+
 uint64_t level_n(const rei_instance* in, int64_t c) {
   if (c < (int64_t)in->costs.c_char || c >= (int64_t)in->lcount.size()) return 0;
   return in->lcount[c];
@@ -314,10 +329,11 @@ bool make_blocks(const rei_instance* in, uint32_t c, std::vector<Block>* out, bo
   out->clear();
   if (blocked) *blocked = false;
   const rei_costs& k = in->costs;
-  if (c == k.c_char) {
-    out->push_back({OP_CHAR, 0, 0, (uint64_t)in->st.sigma.size(), false});
-    return true;
-  }
+  // the characters of this cost come first (all of them at c_char when the
+  // characters cost the same)
+  uint32_t ch_first = 0, ch_count = 0;
+  chars_at(in, c, &ch_first, &ch_count);
+  if (ch_count) out->push_back({OP_CHAR, c, 0, ch_count, false});
   const int64_t cc = c;
   const int64_t full = in->otf_level;
   auto usable = [&](int64_t a, int64_t b) -> bool {
@@ -412,6 +428,11 @@ rei_status enqueue_chunk(rei_instance* in, hipStream_t s, uint32_t c, const Bloc
   g.e0 = e0;
   g.e1 = e1;
   g.char_index = in->d_char_index;
+  if (b.op == OP_CHAR) {
+    uint32_t first = 0, count = 0;
+    chars_at(in, c, &first, &count);
+    g.char_index = in->d_char_index + first;
+  }
   g.st = in->d_state;
   g.inl = in->inl ? 1u : 0u;
   if (b.op != OP_CHAR) {
@@ -477,7 +498,9 @@ bool decode(const rei_instance* in, uint32_t c, uint64_t e, Node* out) {
     }
     out->op = b.op;
     if (b.op == OP_CHAR) {
-      out->a = e;
+      uint32_t first = 0, count = 0;
+      chars_at(in, c, &first, &count);
+      out->a = in->char_order[first + e];  // alphabet position
       out->b = 0;
     } else if (b.op == OP_QUESTION || b.op == OP_STAR) {
       out->a = in->lstart[b.L] + e;
@@ -785,8 +808,10 @@ uint64_t batch_rows(const rei_instance* in, uint64_t arena_bytes) {
 }
 
 bool batchable(const rei_instance* in) {
+  bool same_char_cost = true;
+  for (uint32_t ca : in->char_cost) same_char_cost = same_char_cost && ca == in->costs.c_char;
   return in->st.W <= kBatchMaxW && in->max_cost <= kBatchMaxCost && in->st.gt_pair.size() <= kBatchMaxPairs &&
-         !in->otf_on;
+         !in->otf_on && same_char_cost;
 }
 
 // ---- batched solving -------------------------------------------------------
@@ -1087,6 +1112,8 @@ rei_status create_device(rei_instance* in) {
   if ((r = upload(in, &in->d_len_off, in->st.len_off)) != REI_OK) return r;
   if ((r = upload(in, &in->d_pmask, in->st.pmask)) != REI_OK) return r;
   if ((r = upload(in, &in->d_nmask, in->st.nmask)) != REI_OK) return r;
+  in->char_order.resize(in->st.sigma.size());
+  for (uint32_t a = 0; a < in->char_order.size(); ++a) in->char_order[a] = a;
   if ((r = upload(in, &in->d_char_index, in->st.char_index)) != REI_OK) return r;
   HIP_OK(in, hipMalloc(&in->d_ctrl, sizeof(Ctrl)));
   HIP_OK(in, hipMalloc(&in->d_state, sizeof(DevState)));
@@ -1272,6 +1299,25 @@ rei_status rei_set_chunk(rei_instance* inst, uint64_t max_candidates) {
 rei_status rei_set_batch_level(rei_instance* inst, uint64_t max_candidates) {
   if (!inst) return REI_ERR_INVALID_ARG;
   inst->batch_level_max = max_candidates ? max_candidates : kBatchLevelMax;
+  return REI_OK;
+}
+
+rei_status rei_set_char_costs(rei_instance* inst, const uint32_t* costs, size_t n) {
+  if (!inst || (n && !costs) || n != inst->st.sigma.size() || n == 0) return REI_ERR_INVALID_ARG;
+  uint32_t lo = costs[0];
+  for (size_t a = 0; a < n; ++a) {
+    if (costs[a] < 1) return REI_ERR_INVALID_ARG;
+    lo = std::min(lo, costs[a]);
+  }
+  inst->char_cost.assign(costs, costs + n);
+  inst->costs.c_char = lo;
+  for (uint32_t a = 0; a < inst->char_order.size(); ++a) inst->char_order[a] = a;
+  std::stable_sort(inst->char_order.begin(), inst->char_order.end(),
+                   [&](uint32_t x, uint32_t y) { return inst->char_cost[x] < inst->char_cost[y]; });
+  std::vector<int32_t> idx(n);
+  for (size_t i = 0; i < n; ++i) idx[i] = inst->st.char_index[inst->char_order[i]];
+  HIP_OK(inst, hipSetDevice(inst->device));
+  HIP_OK(inst, hipMemcpy(inst->d_char_index, idx.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
   return REI_OK;
 }
 

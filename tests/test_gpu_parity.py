@@ -369,3 +369,44 @@ def test_on_the_fly_in_a_batch_runs_on_the_grid(rei):
     assert (rb.status, rb.cost, rb.regex) == (o.status, o.cost, o.regex)
     h.close()
     other.close()
+
+
+# ---- per-character costs ----
+
+def _char_cost_cases():
+    cases = []
+    for seed in range(6):
+        it = instances.single_instance(seed, (1, 1, 1, 1, 1))
+        for cc in ((1, 2), (3, 1), (2, 2)):
+            cases.append((it.alphabet, it.pos, it.neg, (1, 1, 1, 1, 1), cc))
+    for it in instances.batched_instances(7, 12):
+        k = len(it.alphabet)
+        cc = tuple(1 + (i * 2) % 3 for i in range(k))
+        cases.append((it.alphabet, it.pos, it.neg, (1, 1, 2, 1, 1), cc))
+    return cases
+
+
+def test_per_character_costs_parity(rei):
+    """Characters enter at the level of their own cost; results (status,
+    cost, regex, per-level counts) equal the oracle's, also inside a batched
+    call (such instances run on the per-chunk path there)."""
+    cases = _char_cost_cases()
+    hs = []
+    for a, p, n, costs, cc in cases:
+        print(f"\nper-character costs {cc} alphabet {a!r}", flush=True)
+        h = rei.Instance(a, p, n, costs, 30)
+        h.set_char_costs(cc)
+        hs.append(h)
+    single = [h.solve() for h in hs]
+    batched = rei.solve_batch(hs)
+    for (a, p, n, costs, cc), g, b in zip(cases, single, batched):
+        o = oracle.solve(a, p, n, costs, 30, 1 << 40, 0, 8, char_costs=list(cc))
+        assert (g.status, g.cost, g.regex) == (o.status, o.cost, o.regex), (cc, g, o)
+        assert g.first_level == min(cc)
+        for c in range(31):
+            assert g.unique_at(c) == o.unique[c], (c, g.unique, o.unique)
+            assert g.candidates_at(c) == o.candidates[c], (c, g.candidates, o.candidates)
+        assert (b.status, b.cost, b.regex, b.unique, b.candidates) == (g.status, g.cost, g.regex, g.unique,
+                                                                        g.candidates)
+    for h in hs:
+        h.close()
