@@ -58,6 +58,15 @@ def workload(name: str):
     if name == "plain":
         out = [instances.plain_instance(s) for s in range(200)]
         return out, "plain instance: alphabet {0,1}, target cost 1-8, 4+4 strings of length 1-5, seeds 0-199"
+    if name == "sweep":
+        out = []
+        for kind, seeds in (("type1", (0, 2)), ("type2", (1, 2))):
+            gen = instances.type1_instance if kind == "type1" else instances.type2_instance
+            for seed in seeds:
+                for costs in instances.PAPER_COST_FUNCTIONS:
+                    out.append(gen(seed, costs=costs, max_cost=1000))
+        return out, ("cost-function sweep: Type 1 seeds 0 and 2, Type 2 seeds 1 and 2 (paper's generators, "
+                     "alphabet {0,1}), each under the paper's 12 cost functions, 25 GB language cache")
     if name == "row1":
         t = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_examples.json")))["table1_row1"]
         inst = instances.Instance(t["alphabet"], t["pos"], t["neg"], "", 0, 0, "row1",
@@ -96,9 +105,14 @@ def main():
     assert torch.cuda.is_available(), "no GPU visible"
     torch.cuda.set_device(0)
     insts, desc = workload(args.workload)
+    # the sweep mirrors the paper's 25 GB memory restriction and is timed per
+    # solve (its instances are not batchable: costs up to 30 per constructor)
+    cache = (25 << 30) if args.workload == "sweep" else (64 << 30)
+    if args.workload == "sweep":
+        args.sequential = True
     handles = []
     for it in insts:
-        h = rei.Instance(it.alphabet, it.pos, it.neg, it.costs, it.max_cost, cache_bytes=64 << 30)
+        h = rei.Instance(it.alphabet, it.pos, it.neg, it.costs, it.max_cost, cache_bytes=cache)
         if args.max_errors:
             h.set_max_errors(args.max_errors)
         handles.append(h)
@@ -253,6 +267,20 @@ def main():
         "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3), "units": v["units"]}
                     for k, v in classes.items()},
     }
+    if args.workload == "sweep":
+        # per cost function, as in the paper's cost-function comparison
+        per = {}
+        for it, r in zip(insts, results[-1]):
+            d = per.setdefault(",".join(map(str, it.costs)), {"solves": 0, "ok": 0, "out_of_memory": 0,
+                                                               "seconds": 0.0, "candidates": 0})
+            d["solves"] += 1
+            d["ok"] += r.status == "OK"
+            d["out_of_memory"] += r.status == "OUT_OF_MEMORY"
+            d["seconds"] = round(d["seconds"] + r.seconds_solve, 4)
+            d["candidates"] += sum(r.candidates)
+        line["per_cost_function"] = per
+        tot_c = sum(sum(r.candidates) for r in results[-1])
+        line["candidates_per_sec"] = round(tot_c / (elapsed / args.steps), 1)
     print(json.dumps(line), flush=True)
     for h in handles:
         h.close()

@@ -280,6 +280,79 @@ def batched_instances(master_seed: int, count: int) -> List[Instance]:
     return out
 
 
+# The twelve cost functions (c1..c5) of the paper's measurements (Table 1 and
+# the cost-function comparison of Sec. 4).
+PAPER_COST_FUNCTIONS = [
+    (1, 1, 1, 1, 1), (10, 1, 1, 1, 1), (1, 10, 1, 1, 1), (1, 1, 10, 1, 1),
+    (1, 1, 1, 10, 1), (1, 1, 1, 1, 10), (10, 10, 10, 10, 1), (10, 10, 10, 1, 10),
+    (10, 10, 1, 10, 10), (10, 1, 10, 10, 10), (1, 10, 10, 10, 10), (20, 20, 20, 5, 30),
+]
+
+
+def type1_instance(seed: int, p: Optional[int] = None, n: Optional[int] = None,
+                   le: Optional[int] = None, sigma: str = "01",
+                   costs=(1, 1, 1, 1, 1), max_cost: int = 1000) -> Instance:
+    """Type 1 benchmark (Sec. 4, Benchmark Construction): P and N are drawn
+    uniformly among pairs of disjoint sets of p and n strings of length at
+    most le, i.e. p + n distinct strings drawn uniformly without replacement
+    from all such strings, the first p positive.  Most strings are long.
+    Unset parameters are drawn as in the paper's main benchmarks: p and n in
+    8..12, le in 0..7 (le is drawn again while fewer than p + n strings of
+    length <= le exist)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = int(rng.integers(8, 13)) if p is None else p
+    n = int(rng.integers(8, 13)) if n is None else n
+    fixed_le = le is not None
+    while True:
+        le_v = le if fixed_le else int(rng.integers(0, 8))
+        universe = words(sigma, 0, le_v)
+        if len(universe) >= p + n:
+            break
+        if fixed_le:
+            raise ValueError(f"only {len(universe)} strings of length <= {le_v}")
+    idx = rng.choice(len(universe), size=p + n, replace=False)
+    chosen = [universe[int(i)] for i in idx]
+    return Instance(sigma, sorted(chosen[:p]), sorted(chosen[p:]), "", 0, seed, "type1",
+                    tuple(costs), max_cost, {"p": p, "n": n, "le": le_v})
+
+
+def type2_instance(seed: int, p: Optional[int] = None, n: Optional[int] = None,
+                   le: Optional[int] = None, sigma: str = "01",
+                   costs=(1, 1, 1, 1, 1), max_cost: int = 1000) -> Instance:
+    """Type 2 benchmark (Sec. 4, Benchmark Construction): every length
+    0..le has the same chance of occurring.  Each example's length is drawn
+    uniformly from 0..le, then the string uniformly among the strings of that
+    length not drawn yet (a length with none left is drawn again); the p
+    positive examples first, then the n negative ones.  Short strings such as
+    the empty word are therefore common.  Unset parameters are drawn as in
+    the paper's main benchmarks: p and n in 7..14, le in 0..10 (le is drawn
+    again while fewer than p + n strings of length <= le exist)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = int(rng.integers(7, 15)) if p is None else p
+    n = int(rng.integers(7, 15)) if n is None else n
+    fixed_le = le is not None
+    while True:
+        le_v = le if fixed_le else int(rng.integers(0, 11))
+        if (len(sigma) ** (le_v + 1) - 1) // max(1, len(sigma) - 1) >= p + n or (
+                len(sigma) == 1 and le_v + 1 >= p + n):
+            break
+        if fixed_le:
+            raise ValueError(f"fewer than {p + n} strings of length <= {le_v}")
+    by_len = [words(sigma, k, k) for k in range(le_v + 1)]
+    used = set()
+    chosen = []
+    while len(chosen) < p + n:
+        k = int(rng.integers(0, le_v + 1))
+        free = [w for w in by_len[k] if w not in used]
+        if not free:
+            continue
+        w = free[int(rng.integers(len(free)))]
+        used.add(w)
+        chosen.append(w)
+    return Instance(sigma, sorted(chosen[:p]), sorted(chosen[p:]), "", 0, seed, "type2",
+                    tuple(costs), max_cost, {"p": p, "n": n, "le": le_v})
+
+
 def ast_cost(ast, costs) -> int:
     c1, c2, c3, c4, c5 = costs
     t = ast[0]
