@@ -125,6 +125,14 @@ def main():
         del src, dst
 
     def step_sequential():
+        if args.workload == "sweep":
+            # 48 solves with 25 GB caches do not fit HBM side by side: each
+            # instance frees its cache after its solve
+            out = []
+            for h in handles:
+                out.append(h.solve(stream))
+                h.trim()
+            return out
         return [h.solve(stream) for h in handles]
 
     def step_batch():

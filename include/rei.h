@@ -155,6 +155,13 @@ rei_status rei_server_poll(rei_server *srv, uint64_t ticket, int wait, int *done
 /* Finishes every submitted request, then frees the server. */
 void rei_server_destroy(rei_server *srv);
 
+/* Free the device memory of the instance's last search (language cache,
+ * dedup table, chunk buffers) but keep the staged specification and the
+ * last result (its regex and counts).  The next rei_solve allocates again.
+ * After it, the inspection calls below have no rows to read.  Waits for the
+ * device.  For callers that solve many large instances in turn. */
+rei_status rei_trim(rei_instance *inst);
+
 /* Free the instance and its device memory.  NULL is ignored. */
 void rei_destroy(rei_instance *inst);
 

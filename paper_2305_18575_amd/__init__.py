@@ -27,7 +27,7 @@ KERNEL_CLASSES = ["gen_char", "gen_question", "gen_star", "gen_concat", "gen_uni
 
 # exported symbols, as declared in include/rei.h
 EXPORTS = ["rei_create", "rei_solve", "rei_solve_batch", "rei_server_create", "rei_server_submit",
-           "rei_server_poll", "rei_server_destroy", "rei_destroy", "rei_status_str", "rei_last_error",
+           "rei_server_poll", "rei_server_destroy", "rei_trim", "rei_destroy", "rei_status_str", "rei_last_error",
            "rei_create_error", "rei_ic_word", "rei_level_size", "rei_row_bits",
            "rei_row_regex", "rei_set_chunk", "rei_set_batch_level", "rei_set_on_the_fly", "rei_set_char_costs", "rei_set_max_errors", "rei_set_profiling",
            "rei_kernel_stats", "rei_kernel_name"]
@@ -96,6 +96,8 @@ def load_library():
     lib.rei_server_destroy.argtypes = [vp]
     lib.rei_destroy.restype = None
     lib.rei_destroy.argtypes = [vp]
+    lib.rei_trim.restype = ctypes.c_int
+    lib.rei_trim.argtypes = [vp]
     lib.rei_status_str.restype = cp
     lib.rei_status_str.argtypes = [ctypes.c_int]
     lib.rei_last_error.restype = cp
@@ -223,6 +225,10 @@ class Instance:
     # ---- tuning / measurement ----
     def set_chunk(self, max_candidates: int):
         self._check(self._lib.rei_set_chunk(self._h, int(max_candidates)))
+
+    def trim(self):
+        """Free the device memory of the last search (``rei_trim``)."""
+        self._check(self._lib.rei_trim(self._h))
 
     def set_char_costs(self, costs: Sequence[int]):
         """Per-character costs, one per alphabet character in alphabet order."""

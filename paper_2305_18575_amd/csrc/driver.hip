@@ -1060,6 +1060,28 @@ rei_status batch_collect(BatchRun* run) {
   return REI_OK;
 }
 
+// Frees the language cache, the table and the chunk buffers (the staged
+// tables and the result stay).
+void free_search_buffers(rei_instance* in) {
+  (void)hipSetDevice(in->device);
+  dfree(in->d_rows);
+  dfree(in->d_aux);
+  dfree(in->d_slots);
+  dfree(in->d_sref);
+  dfree(in->d_skey);
+  dfree(in->d_se);
+  dfree(in->d_spos);
+  dfree(in->d_bitmap);
+  dfree(in->d_prefix);
+  dfree(in->d_bsums);
+  in->rows_alloc = 0;
+  in->slots_cap = 0;
+  in->surv_cap = 0;
+  in->bitmap_cap = 0;
+  in->known_rows = 0;
+  in->h_aux_valid = false;
+}
+
 void free_device(rei_instance* in) {
   (void)hipSetDevice(in->device);
   dfree(in->d_gt_off);
@@ -1299,6 +1321,18 @@ rei_status rei_set_chunk(rei_instance* inst, uint64_t max_candidates) {
 rei_status rei_set_batch_level(rei_instance* inst, uint64_t max_candidates) {
   if (!inst) return REI_ERR_INVALID_ARG;
   inst->batch_level_max = max_candidates ? max_candidates : kBatchLevelMax;
+  return REI_OK;
+}
+
+rei_status rei_trim(rei_instance* inst) {
+  if (!inst) return REI_ERR_INVALID_ARG;
+  HIP_OK(inst, hipSetDevice(inst->device));
+  HIP_OK(inst, hipDeviceSynchronize());
+  free_search_buffers(inst);
+  // no rows left to inspect (the result's counts live in uniq / cand)
+  std::fill(inst->lstart.begin(), inst->lstart.end(), 0);
+  std::fill(inst->lcount.begin(), inst->lcount.end(), 0);
+  inst->tree.clear();
   return REI_OK;
 }
 

@@ -410,3 +410,37 @@ def test_per_character_costs_parity(rei):
                                                                         g.candidates)
     for h in hs:
         h.close()
+
+
+# ---- the paper's benchmark generators under its twelve cost functions ----
+
+def test_paper_generators_all_cost_functions(rei):
+    """Small Type 1 and Type 2 instances (Sec. 4, Benchmark Construction)
+    under each of the twelve cost functions: the GPU equals the oracle."""
+    cases = [instances.type1_instance(s, p=5, n=5, le=4) for s in range(3)]
+    cases += [instances.type2_instance(s, p=6, n=6, le=5) for s in range(2)]
+    for it in cases:
+        for costs in instances.PAPER_COST_FUNCTIONS:
+            print(f"\n{it.kind} {it.meta} costs {costs}", flush=True)
+            g = rei.solve(it.alphabet, it.pos, it.neg, costs, max_cost=1000)
+            o = oracle.solve(it.alphabet, it.pos, it.neg, costs, 1000, 1 << 40, 0, 8)
+            assert (g.status, g.cost, g.regex) == (o.status, o.cost, o.regex), (costs, g, o)
+            for c in range(0, g.cost + 1):
+                assert g.unique_at(c) == o.unique[c] and g.candidates_at(c) == o.candidates[c], c
+
+
+def test_trim_frees_and_resolves(rei):
+    """rei_trim frees the last search's device memory; the result stays, the
+    rows are gone (inspection refuses), and the next solve is identical."""
+    it = instances.single_instance(3, (1, 1, 5, 1, 2))
+    h = rei.Instance(it.alphabet, it.pos, it.neg, it.costs, it.max_cost)
+    a = h.solve()
+    assert h.level_size(a.first_level) > 0
+    h.trim()
+    assert h.level_size(a.first_level) == 0
+    with pytest.raises(rei.ReiError):
+        h.row_bits(a.first_level, 0, a.cs_words)
+    b = h.solve()
+    assert (a.status, a.cost, a.regex, a.unique, a.candidates) == (b.status, b.cost, b.regex, b.unique,
+                                                                    b.candidates)
+    h.close()
