@@ -126,6 +126,20 @@ rei_status rei_solve(rei_instance *inst, void *hip_stream, rei_result *out);
 rei_status rei_solve_batch(rei_instance *const *insts, size_t n, void *hip_stream, uint64_t arena_bytes,
                            rei_result *out);
 
+/* Autotuner of rei_solve_batch's launch shape.  Solves the n instances once
+ * for each workgroup size (256, 512 and 1024 threads per instance; at most
+ * 512 with 8 words per language), times each word-width group's launch with
+ * events the launch records, and keeps for each group the fastest size for
+ * groups of this many instances (by power-of-two size class) in a table of
+ * the process that later rei_solve_batch calls on any thread use.  Without
+ * an entry, a group gets enough waves per instance to fill the device's wave
+ * slots.  Results do not depend on the shape.  threads_out (NULL or 5
+ * entries, for W = 1 with keys in the table slots, then W = 1, 2, 4, 8)
+ * receives the chosen sizes, 0 for groups without instances.  The instances
+ * end up solved, as by rei_solve_batch. */
+rei_status rei_tune_batch(rei_instance *const *insts, size_t n, void *hip_stream, uint64_t arena_bytes,
+                          uint32_t *threads_out);
+
 /* ---- serving: continuous batching ------------------------------------------
  * A server solves submitted instances asynchronously.  Requests are admitted
  * in arrival order while the device bytes they need fit hbm_budget; admitted

@@ -26,7 +26,7 @@ KERNEL_CLASSES = ["gen_char", "gen_question", "gen_star", "gen_concat", "gen_uni
                   "insert_survivors", "compact_winners", "other", "solve_batch"]
 
 # exported symbols, as declared in include/rei.h
-EXPORTS = ["rei_create", "rei_solve", "rei_solve_batch", "rei_server_create", "rei_server_submit",
+EXPORTS = ["rei_create", "rei_solve", "rei_solve_batch", "rei_tune_batch", "rei_server_create", "rei_server_submit",
            "rei_server_poll", "rei_server_destroy", "rei_trim", "rei_destroy", "rei_status_str", "rei_last_error",
            "rei_create_error", "rei_ic_word", "rei_level_size", "rei_row_bits",
            "rei_row_regex", "rei_set_chunk", "rei_set_batch_level", "rei_set_on_the_fly", "rei_set_char_costs", "rei_set_max_errors", "rei_set_profiling",
@@ -85,6 +85,8 @@ def load_library():
     lib.rei_solve_batch.restype = ctypes.c_int
     lib.rei_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, vp, u64,
                                     ctypes.POINTER(_Result)]
+    lib.rei_tune_batch.restype = ctypes.c_int
+    lib.rei_tune_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, vp, u64, ctypes.POINTER(u32)]
     lib.rei_server_create.restype = ctypes.c_int
     lib.rei_server_create.argtypes = [u64, u32, u32, u32, ctypes.POINTER(vp)]
     lib.rei_server_submit.restype = ctypes.c_int
@@ -206,8 +208,7 @@ class Instance:
     def _result(self, r) -> "Result":
         n = r.n_levels
         return Result(STATUS[r.status], r.cost, (r.regex or b"").decode("utf-8"), r.first_level,
-                      [r.unique_per_level[i] for i in range(n)],
-                      [r.candidates_per_level[i] for i in range(n)],
+                      r.unique_per_level[:n] if n else [], r.candidates_per_level[:n] if n else [],
                       r.total_unique, r.ic_size, r.cs_words, r.seconds_stage, r.seconds_solve)
 
     def _check(self, st):
@@ -294,6 +295,24 @@ def solve_batch(instances: Sequence["Instance"], stream: Optional[int] = -1,
         msg = "; ".join(sorted({lib.rei_last_error(i._h).decode() for i in instances} - {""}))
         raise ReiError(st, msg)
     return [inst._result(rs[k]) for k, inst in enumerate(instances)]
+
+
+def tune_batch(instances: Sequence["Instance"], stream: Optional[int] = -1,
+               arena_bytes: int = 0) -> dict:
+    """``rei_tune_batch``: pick and remember the fastest workgroup size per
+    word-width group for batches like this one; returns {group: threads}."""
+    lib = load_library()
+    if stream == -1:
+        stream = current_stream_handle()
+    n = len(instances)
+    hs = (ctypes.c_void_p * n)(*[i._h for i in instances])
+    out = (ctypes.c_uint32 * 5)()
+    st = lib.rei_tune_batch(hs, n, ctypes.c_void_p(stream or 0), int(arena_bytes), out)
+    if st != 0:
+        msg = "; ".join(sorted({lib.rei_last_error(i._h).decode() for i in instances} - {""}))
+        raise ReiError(st, msg)
+    names = ["W1-inline", "W1", "W2", "W4", "W8"]
+    return {names[k]: int(out[k]) for k in range(5) if out[k]}
 
 
 class Server:

@@ -121,14 +121,13 @@ __device__ __forceinline__ bool decode_index(const BatchDesc& d, const uint64_t*
   return false;
 }
 
-// Threads per instance: 16 waves, or 8 when a language has 8 words (the
-// per-wave operand tiles then stay within 32 KB of LDS).
-template <int W>
-constexpr uint32_t batch_threads() { return W <= 4 ? 1024u : 512u; }
-
-template <int W, bool kInl>
-__global__ __launch_bounds__(batch_threads<W>()) void solve_batch(const BatchDesc* descs, uint32_t n_inst) {
-  constexpr uint32_t kT = batch_threads<W>();
+// kT threads per instance (256, 512 or 1024; at most 512 when a language
+// has 8 words, so that the per-wave operand tiles stay within 32 KB of LDS):
+// many waves shorten one instance's search, few let more instances share a
+// CU.  The host picks kT per launch (tuned or from the batch size).
+template <int W, bool kInl, uint32_t kT>
+__global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32_t n_inst) {
+  static_assert(kT >= kBatchChunk / 32 && kT <= 1024 && kT % 64 == 0, "one scan value per thread");
   constexpr uint32_t kWaves = kT / 64;
   __shared__ uint64_t s_lstart[kBatchMaxCost + 2], s_lcount[kBatchMaxCost + 2];
   __shared__ uint64_t s_uniq[kBatchMaxCost + 2], s_cand[kBatchMaxCost + 2];
@@ -545,20 +544,33 @@ __global__ __launch_bounds__(batch_threads<W>()) void solve_batch(const BatchDes
 
 }  // namespace
 
-hipError_t launch_solve_batch(int W, bool inl, const BatchDesc* d_descs, uint32_t n, hipStream_t s) {
+hipError_t launch_solve_batch(int W, bool inl, uint32_t threads, const BatchDesc* d_descs, uint32_t n,
+                              hipStream_t s) {
   if (n == 0) return hipSuccess;
+#define REI_BATCH_T(WW, II)                                                                                  \
+  switch (threads) {                                                                                         \
+    case 256: launch_timed(solve_batch<WW, II, 256>, dim3(n), dim3(256), 0, s, d_descs, n); break;         \
+    case 512: launch_timed(solve_batch<WW, II, 512>, dim3(n), dim3(512), 0, s, d_descs, n); break;         \
+    case 1024:                                                                                               \
+      if (WW > 4) return hipErrorInvalidValue;                                                               \
+      launch_timed(solve_batch<WW, II, (WW > 4 ? 512u : 1024u)>, dim3(n), dim3(1024), 0, s, d_descs, n);   \
+      break;                                                                                                 \
+    default: return hipErrorInvalidValue;                                                                    \
+  }
   switch (W) {
     case 1:
-      if (inl)
-        launch_timed(solve_batch<1, true>, dim3(n), dim3(batch_threads<1>()), 0, s, d_descs, n);
-      else
-        launch_timed(solve_batch<1, false>, dim3(n), dim3(batch_threads<1>()), 0, s, d_descs, n);
+      if (inl) {
+        REI_BATCH_T(1, true)
+      } else {
+        REI_BATCH_T(1, false)
+      }
       break;
-    case 2: launch_timed(solve_batch<2, false>, dim3(n), dim3(batch_threads<2>()), 0, s, d_descs, n); break;
-    case 4: launch_timed(solve_batch<4, false>, dim3(n), dim3(batch_threads<4>()), 0, s, d_descs, n); break;
-    case 8: launch_timed(solve_batch<8, false>, dim3(n), dim3(batch_threads<8>()), 0, s, d_descs, n); break;
+    case 2: REI_BATCH_T(2, false) break;
+    case 4: REI_BATCH_T(4, false) break;
+    case 8: REI_BATCH_T(8, false) break;
     default: return hipErrorInvalidValue;
   }
+#undef REI_BATCH_T
   return hipGetLastError();
 }
 

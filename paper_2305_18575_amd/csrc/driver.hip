@@ -7,6 +7,7 @@
 #include <condition_variable>
 #include <deque>
 #include <list>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -870,6 +871,11 @@ rei_status side_acquire(rei_instance* in, SideStream* out) {
   return REI_OK;
 }
 
+rei_status event_acquire_timing(rei_instance* in, hipEvent_t* out) {
+  HIP_OK(in, hipEventCreateWithFlags(out, hipEventDisableSystemFence));
+  return REI_OK;
+}
+
 rei_status event_acquire(rei_instance* in, hipEvent_t* out) {
   {
     std::lock_guard<std::mutex> g(g_pool_mu);
@@ -900,7 +906,48 @@ struct BatchRun {
   rei_instance* pin = nullptr;  // holds the batched launches' timings
   size_t rec_first = 0;
   std::vector<int> rec_w;
+  // launch shape: threads per instance of each group (forced by the tuner,
+  // else tuned or from the batch size), and the tuner's per-group timing
+  uint32_t force_threads = 0;
+  uint32_t threads[kBatchMaxW + 1] = {0};
+  bool time_groups = false;
+  hipEvent_t gev[kBatchMaxW + 1][2] = {};
 };
+
+// ---- launch shape of the batched solver ---------------------------------
+// Threads per instance for a group of n instances of word width W: the
+// tuner's choice for this size class when there is one, else enough waves
+// per instance to fill the device's wave slots (32 per CU) with n instances.
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, uint32_t> g_tuned;  // (group, size class) -> threads
+int g_cus = 0;
+
+int size_class(size_t n) {
+  int k = 0;
+  while ((size_t(1) << k) < n) ++k;
+  return k;
+}
+
+uint32_t max_threads(int g) { return g > 4 ? 512u : 1024u; }
+
+uint32_t choose_threads(int g, size_t n) {
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find({g, size_class(n)});
+    if (it != g_tuned.end()) return it->second;
+    if (!g_cus) {
+      int dev = 0, cus = 0;
+      if (hipGetDevice(&dev) == hipSuccess &&
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        g_cus = cus;
+      else
+        g_cus = 256;
+    }
+  }
+  const uint64_t waves = (uint64_t)g_cus * 32 / std::max<size_t>(1, n);
+  uint32_t t = waves >= 16 ? 1024u : waves >= 8 ? 512u : 256u;
+  return std::min(t, max_threads(g));
+}
 
 BatchDesc make_desc(const rei_instance* in) {
   BatchDesc d{};
@@ -1000,11 +1047,25 @@ rei_status batch_launch(rei_instance* const* insts, size_t n, hipStream_t s, uin
       HIP_OK(in0, hipStreamWaitEvent(ss.s, run->fork, 0));
       gs = ss.s;
     }
-    hipEvent_t ev = nullptr, ev2 = nullptr;
-    if ((r = prof_begin(run->pin, gs, REI_K_BATCH, &ev, &ev2)) != REI_OK) return r;
-    HIP_OK(in0, launch_solve_batch(g ? g : 1, g == 0, db.d, (uint32_t)groups[g].size(), gs));
-    if ((r = prof_end(run->pin, gs, REI_K_BATCH, ev, ev2, 0)) != REI_OK) return r;
-    if (run->pin->prof) run->rec_w.push_back(g);
+    const uint32_t th = run->force_threads ? std::min(run->force_threads, max_threads(g))
+                                           : choose_threads(g, groups[g].size());
+    run->threads[g] = th;
+    if (run->time_groups) {
+      // the tuner's own timing, recorded by the launch itself
+      hipEvent_t a = nullptr, b = nullptr;
+      if ((r = event_acquire_timing(in0, &a)) != REI_OK || (r = event_acquire_timing(in0, &b)) != REI_OK)
+        return r;
+      run->gev[g][0] = a;
+      run->gev[g][1] = b;
+      g_kernel_timer = KernelTimer{a, b};
+      HIP_OK(in0, launch_solve_batch(g ? g : 1, g == 0, th, db.d, (uint32_t)groups[g].size(), gs));
+    } else {
+      hipEvent_t ev = nullptr, ev2 = nullptr;
+      if ((r = prof_begin(run->pin, gs, REI_K_BATCH, &ev, &ev2)) != REI_OK) return r;
+      HIP_OK(in0, launch_solve_batch(g ? g : 1, g == 0, th, db.d, (uint32_t)groups[g].size(), gs));
+      if ((r = prof_end(run->pin, gs, REI_K_BATCH, ev, ev2, 0)) != REI_OK) return r;
+      if (run->pin->prof) run->rec_w.push_back(g);
+    }
     if (!first) {
       HIP_OK(in0, hipEventRecord(run->sides.back().join, gs));
       HIP_OK(in0, hipStreamWaitEvent(s, run->sides.back().join, 0));
@@ -1248,6 +1309,67 @@ rei_status rei_solve_batch(rei_instance* const* insts, size_t n, void* hip_strea
     }
   } catch (const std::bad_alloc&) {
     return REI_ERR_HOST_ALLOC;
+  }
+  return REI_OK;
+}
+
+rei_status rei_tune_batch(rei_instance* const* insts, size_t n, void* hip_stream, uint64_t arena_bytes,
+                          uint32_t* threads_out) {
+  if (n == 0 || !insts) return REI_ERR_INVALID_ARG;
+  for (size_t i = 0; i < n; ++i)
+    if (!insts[i]) return REI_ERR_INVALID_ARG;
+  if (arena_bytes == 0) arena_bytes = kDefaultArena;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const uint32_t cand[3] = {256, 512, 1024};
+  double best_ms[kBatchMaxW + 1];
+  uint32_t best_t[kBatchMaxW + 1] = {0};
+  size_t group_n[kBatchMaxW + 1] = {0};
+  for (int g = 0; g <= kBatchMaxW; ++g) best_ms[g] = 1e300;
+  rei_status r;
+  try {
+    for (uint32_t c : cand) {
+      BatchRun run;
+      run.force_threads = c;
+      run.time_groups = true;
+      if ((r = batch_launch(insts, n, s, arena_bytes, &run)) == REI_OK) {
+        hipError_t se = hipStreamSynchronize(s);
+        if (se != hipSuccess) {
+          insts[0]->err = std::string("tuning launch: ") + hipGetErrorString(se);
+          r = REI_ERR_DEVICE;
+        }
+      }
+      for (int g = 0; g <= kBatchMaxW; ++g) {
+        if (!run.gev[g][0]) continue;
+        float ms = 0;
+        if (r == REI_OK && run.threads[g] == c && hipEventElapsedTime(&ms, run.gev[g][0], run.gev[g][1]) == hipSuccess &&
+            ms < best_ms[g]) {
+          best_ms[g] = ms;
+          best_t[g] = c;
+        }
+        group_n[g] = run.members[g].size();
+        (void)hipEventDestroy(run.gev[g][0]);
+        (void)hipEventDestroy(run.gev[g][1]);
+      }
+      if (r != REI_OK) {
+        (void)hipStreamSynchronize(s);
+        batch_release(&run);
+        return r;
+      }
+      if ((r = batch_collect(&run)) != REI_OK) return r;
+      for (rei_instance* in : run.grid) {
+        if ((r = search_levels(in, s)) != REI_OK) return r;
+        if ((r = finish_solve(in, run.t0)) != REI_OK) return r;
+      }
+    }
+  } catch (const std::bad_alloc&) {
+    return REI_ERR_HOST_ALLOC;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  static const int slot[kBatchMaxW + 1] = {0, 1, 2, -1, 3, -1, -1, -1, 4};
+  for (int g = 0; g <= kBatchMaxW; ++g) {
+    if (slot[g] < 0) continue;
+    if (best_t[g]) g_tuned[{g, size_class(group_n[g])}] = best_t[g];
+    if (threads_out) threads_out[slot[g]] = best_t[g];
   }
   return REI_OK;
 }

@@ -208,7 +208,9 @@ struct BatchDesc {
   uint64_t* htree;            // [node count, then per node: row (~0 = the answer), op, a, b]
 };
 
-// Launches one workgroup per descriptor (all with the same W).
-hipError_t launch_solve_batch(int W, bool inl, const BatchDesc* d_descs, uint32_t n, hipStream_t s);
+// Launches one workgroup of `threads` (256, 512 or 1024; at most 512 for
+// W = 8) per descriptor (all with the same W).
+hipError_t launch_solve_batch(int W, bool inl, uint32_t threads, const BatchDesc* d_descs, uint32_t n,
+                              hipStream_t s);
 
 }  // namespace rei

@@ -444,3 +444,35 @@ def test_trim_frees_and_resolves(rei):
     assert (a.status, a.cost, a.regex, a.unique, a.candidates) == (b.status, b.cost, b.regex, b.unique,
                                                                     b.candidates)
     h.close()
+
+
+def test_tuned_launch_shapes_give_identical_results(rei):
+    """Every workgroup size the tuner tries gives the same results; the
+    tuner returns one size per word-width group present."""
+    specs = batch_specs()[::2]
+    hs = [rei.Instance(a, p, n, c, m) for (a, p, n, c, m) in specs]
+    before = rei.solve_batch(hs)
+    tuned = rei.tune_batch(hs)
+    assert tuned and all(t in (256, 512, 1024) for t in tuned.values())
+    after = rei.solve_batch(hs)
+    key = lambda r: (r.status, r.cost, r.regex, r.unique, r.candidates)
+    assert [key(r) for r in before] == [key(r) for r in after]
+    for r, spec in zip(after, specs):
+        check_against_oracle(r, spec)
+    for h in hs:
+        h.close()
+
+
+def test_large_batch_equals_per_instance_solves(rei):
+    """2500 instances: the groups are large enough that the launch gives each
+    instance 256 or 512 threads; every result equals the instance's own
+    rei_solve (the per-chunk path, parity-tested against the oracle)."""
+    xs = instances.batched_instances(3, 2500)
+    print(f"\nbatch of {len(xs)} instances", flush=True)
+    hs = [rei.Instance(i.alphabet, i.pos, i.neg, i.costs, i.max_cost, 1 << 30) for i in xs]
+    batched = rei.solve_batch(hs)
+    key = lambda r: (r.status, r.cost, r.regex, r.unique, r.candidates)
+    for h, b in zip(hs, batched):
+        assert key(h.solve()) == key(b)
+    for h in hs:
+        h.close()
