@@ -40,7 +40,6 @@ PROBE_BYTES = 64
 # by (workload, kernel class).  Only valid for the kernels as they were
 # measured: an entry is removed when its kernel changes.
 TRAFFIC_BYTES = {
-    ("single", "solve_batch"): 137582646,
     ("row1", "gen_concat"): 303436323,
 }
 
@@ -270,7 +269,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "instances_per_step": len(insts),
                    "mode": "rei_solve per instance" if args.sequential else "rei_solve_batch",
-                   "batch_threads_per_instance": tuned},
+                   "batch_tuning": tuned},
         ("batched_value" if args.sequential else "sequential_value"):
             None if other_value is None else round(other_value, 3),
         "batched_over_sequential": None if other_value is None else

@@ -111,10 +111,13 @@ rei_status rei_solve(rei_instance *inst, void *hip_stream, rei_result *out);
  * and max_cost <= 63 run in one launch per word width (the launches run side
  * by side), one workgroup per instance executing the whole level loop on the
  * device (no host round trip per level or chunk; the answer's expression
- * tree is decoded there too); the others, and any instance that outgrows its
- * preallocated rows or reaches a level of more than 2^20 candidates, run
- * rei_solve's path afterwards.  Every result equals what rei_solve returns
- * for that instance.
+ * tree is decoded there too).  An instance whose next level has more
+ * candidates than the hand-off size (rei_set_batch_level; 2^16 by default)
+ * continues from that level on rei_solve's path with its lower levels kept;
+ * one that outgrows its preallocated rows starts again there; the others
+ * run there from the start.  Up to 8 such instances run at once, each on
+ * its own stream.  Every result equals what rei_solve returns for that
+ * instance.
  *   insts        n distinct instances (each used by this call only).
  *   arena_bytes  device bytes preallocated per batched instance for rows,
  *                back-pointers and table (0 = 16 MiB); capped by the
@@ -126,19 +129,23 @@ rei_status rei_solve(rei_instance *inst, void *hip_stream, rei_result *out);
 rei_status rei_solve_batch(rei_instance *const *insts, size_t n, void *hip_stream, uint64_t arena_bytes,
                            rei_result *out);
 
-/* Autotuner of rei_solve_batch's launch shape.  Solves the n instances once
- * for each workgroup size (256, 512 and 1024 threads per instance; at most
- * 512 with 8 words per language), times each word-width group's launch with
- * events the launch records, and keeps for each group the fastest size for
- * groups of this many instances (by power-of-two size class) in a table of
- * the process that later rei_solve_batch calls on any thread use.  Without
- * an entry, a group gets enough waves per instance to fill the device's wave
- * slots.  Results do not depend on the shape.  threads_out (NULL or 5
- * entries, for W = 1 with keys in the table slots, then W = 1, 2, 4, 8)
- * receives the chosen sizes, 0 for groups without instances.  The instances
- * end up solved, as by rei_solve_batch. */
+/* Autotuner of rei_solve_batch.  First the launch shape: solves the n
+ * instances once for each workgroup size (256, 512 and 1024 threads per
+ * instance; at most 512 with 8 words per language), times each word-width
+ * group's launch with events the launch records, and keeps for each group
+ * the fastest size for groups of this many instances (by power-of-two size
+ * class) in a table of the process that later rei_solve_batch calls on any
+ * thread use.  Without an entry, a group gets enough waves per instance to
+ * fill the device's wave slots.  Then the hand-off level size (for
+ * instances that did not set rei_set_batch_level): whole calls are timed for
+ * 2^13 .. 2^19 candidates and the fastest becomes the process default
+ * (2^16 until then).  Results do not depend on either choice.  threads_out
+ * (NULL or 5 entries, for W = 1 with keys in the table slots, then W = 1, 2,
+ * 4, 8) receives the chosen sizes, 0 for groups without instances;
+ * level_max_out (NULL or 1 entry) the level size.  The instances end up
+ * solved, as by rei_solve_batch. */
 rei_status rei_tune_batch(rei_instance *const *insts, size_t n, void *hip_stream, uint64_t arena_bytes,
-                          uint32_t *threads_out);
+                          uint32_t *threads_out, uint64_t *level_max_out);
 
 /* ---- serving: continuous batching ------------------------------------------
  * A server solves submitted instances asynchronously.  Requests are admitted
@@ -203,7 +210,8 @@ rei_status rei_row_regex(rei_instance *inst, uint32_t cost, uint64_t i, char *bu
  * do not depend on it; tests vary it to check that. */
 rei_status rei_set_chunk(rei_instance *inst, uint64_t max_candidates);
 /* Largest level, in candidates, that rei_solve_batch searches inside its
- * one-workgroup solver (0 = default 2^20).  At a larger level the instance,
+ * one-workgroup solver (0 = the process default: 2^16, or what
+ * rei_tune_batch chose).  At a larger level the instance,
  * with every lower level kept, continues on rei_solve's path.  Results do not
  * depend on it. */
 rei_status rei_set_batch_level(rei_instance *inst, uint64_t max_candidates);
@@ -244,9 +252,12 @@ typedef enum {
   REI_K_COUNT
 } rei_kernel_class;
 
-/* Record a HIP event pair around every kernel launch of the next solves
- * (for rei_solve_batch: around each batched launch, counted on insts[0]).
- * Turning profiling on clears the statistics; turning it off keeps them. */
+/* Time kernel launches of the next solves with HIP event pairs.  enable = 1:
+ * the generator classes and the batched solver, whose launches record the
+ * pair at the kernel's own start and end (for rei_solve_batch: each batched
+ * launch, counted on insts[0]); enable = 2: every class (the others with
+ * events on the stream around the launch); 0: off.  Turning profiling on
+ * clears the statistics; turning it off keeps them. */
 rei_status rei_set_profiling(rei_instance *inst, int enable);
 /* Launch count, total device milliseconds and work units (candidates for the
  * generator classes, survivors for REI_K_INSERT) of one kernel class,

@@ -86,7 +86,8 @@ def load_library():
     lib.rei_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, vp, u64,
                                     ctypes.POINTER(_Result)]
     lib.rei_tune_batch.restype = ctypes.c_int
-    lib.rei_tune_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, vp, u64, ctypes.POINTER(u32)]
+    lib.rei_tune_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, vp, u64, ctypes.POINTER(u32),
+                                   ctypes.POINTER(u64)]
     lib.rei_server_create.restype = ctypes.c_int
     lib.rei_server_create.argtypes = [u64, u32, u32, u32, ctypes.POINTER(vp)]
     lib.rei_server_submit.restype = ctypes.c_int
@@ -247,8 +248,9 @@ class Instance:
     def set_max_errors(self, k: int):
         self._check(self._lib.rei_set_max_errors(self._h, int(k)))
 
-    def set_profiling(self, on: bool):
-        self._check(self._lib.rei_set_profiling(self._h, 1 if on else 0))
+    def set_profiling(self, on, level: int = 1):
+        """Kernel timing: level 1 = generators and batched solver, 2 = all."""
+        self._check(self._lib.rei_set_profiling(self._h, level if on else 0))
 
     def kernel_stats(self, k: int):
         n, u = ctypes.c_uint64(), ctypes.c_uint64()
@@ -300,19 +302,22 @@ def solve_batch(instances: Sequence["Instance"], stream: Optional[int] = -1,
 def tune_batch(instances: Sequence["Instance"], stream: Optional[int] = -1,
                arena_bytes: int = 0) -> dict:
     """``rei_tune_batch``: pick and remember the fastest workgroup size per
-    word-width group for batches like this one; returns {group: threads}."""
+    word-width group for batches like this one, then the hand-off level size;
+    returns {"threads_per_instance": {group: threads}, "level_max": n}."""
     lib = load_library()
     if stream == -1:
         stream = current_stream_handle()
     n = len(instances)
     hs = (ctypes.c_void_p * n)(*[i._h for i in instances])
     out = (ctypes.c_uint32 * 5)()
-    st = lib.rei_tune_batch(hs, n, ctypes.c_void_p(stream or 0), int(arena_bytes), out)
+    lm = ctypes.c_uint64()
+    st = lib.rei_tune_batch(hs, n, ctypes.c_void_p(stream or 0), int(arena_bytes), out, ctypes.byref(lm))
     if st != 0:
         msg = "; ".join(sorted({lib.rei_last_error(i._h).decode() for i in instances} - {""}))
         raise ReiError(st, msg)
     names = ["W1-inline", "W1", "W2", "W4", "W8"]
-    return {names[k]: int(out[k]) for k in range(5) if out[k]}
+    shape = {names[k]: int(out[k]) for k in range(5) if out[k]}
+    return {"threads_per_instance": shape, "level_max": int(lm.value)}
 
 
 class Server:

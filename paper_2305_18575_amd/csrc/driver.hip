@@ -58,7 +58,7 @@ struct rei_instance {
   uint64_t row_cap = 0;
   uint32_t max_err = 0;
   uint64_t chunk_max = kDefaultChunk;
-  uint64_t batch_level_max = kBatchLevelMax;
+  uint64_t batch_level_max = 0;  // 0: the tuned value, else kBatchLevelMax
   int device = 0;
   double seconds_stage = 0;
 
@@ -133,7 +133,7 @@ struct rei_instance {
   std::string err;
 
   // profiling
-  bool prof = false;
+  int prof = 0;  // 0 off, 1 generators and batched solver, 2 every class
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
   uint64_t st_launch[REI_K_COUNT] = {0};
@@ -185,8 +185,10 @@ rei_status prof_event(rei_instance* in, hipEvent_t* ev) {
   return REI_OK;
 }
 
+bool profiled(const rei_instance* in, int k) { return in->prof == 2 || (in->prof == 1 && self_timed(k)); }
+
 rei_status prof_begin(rei_instance* in, hipStream_t s, int k, hipEvent_t* a, hipEvent_t* b) {
-  if (!in->prof) return REI_OK;
+  if (!profiled(in, k)) return REI_OK;
   rei_status r;
   if ((r = prof_event(in, a)) != REI_OK || (r = prof_event(in, b)) != REI_OK) return r;
   if (self_timed(k))
@@ -197,7 +199,7 @@ rei_status prof_begin(rei_instance* in, hipStream_t s, int k, hipEvent_t* a, hip
 }
 
 rei_status prof_end(rei_instance* in, hipStream_t s, int k, hipEvent_t a, hipEvent_t b, uint64_t units) {
-  if (!in->prof) return REI_OK;
+  if (!profiled(in, k)) return REI_OK;
   if (self_timed(k)) {
     if (g_kernel_timer.start) {  // the launcher launched nothing
       g_kernel_timer = KernelTimer{nullptr, nullptr};
@@ -922,6 +924,15 @@ std::mutex g_tune_mu;
 std::map<std::pair<int, int>, uint32_t> g_tuned;  // (group, size class) -> threads
 int g_cus = 0;
 
+// Hand-off level size of instances that leave it at the default: the
+// tuner's choice, else kBatchLevelMax.
+std::atomic<uint64_t> g_level_max{0};
+
+uint64_t tuned_level_max() {
+  const uint64_t v = g_level_max.load();
+  return v ? v : kBatchLevelMax;
+}
+
 int size_class(size_t n) {
   int k = 0;
   while ((size_t(1) << k) < n) ++k;
@@ -975,7 +986,7 @@ BatchDesc make_desc(const rei_instance* in) {
   d.slots = in->d_slots;
   d.sref = in->d_sref;
   d.inl = in->inl ? 1u : 0u;
-  d.level_max = in->batch_level_max;
+  d.level_max = in->batch_level_max ? in->batch_level_max : tuned_level_max();
   d.slot_mask = in->slots_cap - 1;
   d.skey = in->d_skey;
   d.se = in->d_se;
@@ -1118,6 +1129,61 @@ rei_status batch_collect(BatchRun* run) {
     run->finished.push_back(in);
   }
   if (run->pin && run->pin->prof && (r = prof_collect(run->pin)) != REI_OK) return r;
+  return REI_OK;
+}
+
+// The instances a batched call leaves to the per-chunk path (hand-offs,
+// instances that outgrew their rows, unbatchable ones): each is
+// latency-bound on its own, so up to 8 run at once, each on a pooled side
+// stream driven by its own host thread.
+rei_status solve_grid_instances(const std::vector<rei_instance*>& grid, hipStream_t s, double t0) {
+  if (grid.empty()) return REI_OK;
+  if (grid.size() == 1) {
+    rei_status r = search_levels(grid[0], s);
+    return r == REI_OK ? finish_solve(grid[0], t0) : r;
+  }
+  const size_t nt = std::min<size_t>(grid.size(), 8);
+  std::atomic<size_t> next{0};
+  std::vector<rei_status> st(nt, REI_OK);
+  std::vector<std::thread> pool;
+  for (size_t t = 0; t < nt; ++t)
+    pool.emplace_back([&, t] {
+      SideStream ss;
+      bool have = false;
+      for (size_t i; (i = next.fetch_add(1)) < grid.size();) {
+        rei_instance* in = grid[i];
+        rei_status r;
+        try {
+          if (hipSetDevice(in->device) != hipSuccess) {
+            st[t] = REI_ERR_DEVICE;
+            break;
+          }
+          if (!have) {
+            if ((r = side_acquire(in, &ss)) != REI_OK) {
+              st[t] = r;
+              break;
+            }
+            have = true;
+          }
+          r = search_levels(in, ss.s);
+          if (r == REI_OK) r = finish_solve(in, t0);
+        } catch (const std::bad_alloc&) {
+          r = REI_ERR_HOST_ALLOC;
+        }
+        if (r != REI_OK) {
+          st[t] = r;
+          break;
+        }
+      }
+      if (have) {
+        (void)hipStreamSynchronize(ss.s);
+        std::lock_guard<std::mutex> g(g_pool_mu);
+        g_side_free.push_back(ss);
+      }
+    });
+  for (auto& th : pool) th.join();
+  for (rei_status r : st)
+    if (r != REI_OK) return r;
   return REI_OK;
 }
 
@@ -1299,10 +1365,7 @@ rei_status rei_solve_batch(rei_instance* const* insts, size_t n, void* hip_strea
       return REI_ERR_DEVICE;
     }
     if ((r = batch_collect(&run)) != REI_OK) return r;
-    for (rei_instance* in : run.grid) {
-      if ((r = search_levels(in, s)) != REI_OK) return r;
-      if ((r = finish_solve(in, run.t0)) != REI_OK) return r;
-    }
+    if ((r = solve_grid_instances(run.grid, s, run.t0)) != REI_OK) return r;
     for (size_t i = 0; i < n; ++i) {
       insts[i]->res.seconds_solve = now_s() - run.t0;
       out[i] = insts[i]->res;
@@ -1314,7 +1377,7 @@ rei_status rei_solve_batch(rei_instance* const* insts, size_t n, void* hip_strea
 }
 
 rei_status rei_tune_batch(rei_instance* const* insts, size_t n, void* hip_stream, uint64_t arena_bytes,
-                          uint32_t* threads_out) {
+                          uint32_t* threads_out, uint64_t* level_max_out) {
   if (n == 0 || !insts) return REI_ERR_INVALID_ARG;
   for (size_t i = 0; i < n; ++i)
     if (!insts[i]) return REI_ERR_INVALID_ARG;
@@ -1356,21 +1419,40 @@ rei_status rei_tune_batch(rei_instance* const* insts, size_t n, void* hip_stream
         return r;
       }
       if ((r = batch_collect(&run)) != REI_OK) return r;
-      for (rei_instance* in : run.grid) {
-        if ((r = search_levels(in, s)) != REI_OK) return r;
-        if ((r = finish_solve(in, run.t0)) != REI_OK) return r;
-      }
+      if ((r = solve_grid_instances(run.grid, s, run.t0)) != REI_OK) return r;
     }
   } catch (const std::bad_alloc&) {
     return REI_ERR_HOST_ALLOC;
   }
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  static const int slot[kBatchMaxW + 1] = {0, 1, 2, -1, 3, -1, -1, -1, 4};
-  for (int g = 0; g <= kBatchMaxW; ++g) {
-    if (slot[g] < 0) continue;
-    if (best_t[g]) g_tuned[{g, size_class(group_n[g])}] = best_t[g];
-    if (threads_out) threads_out[slot[g]] = best_t[g];
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    static const int slot[kBatchMaxW + 1] = {0, 1, 2, -1, 3, -1, -1, -1, 4};
+    for (int g = 0; g <= kBatchMaxW; ++g) {
+      if (slot[g] < 0) continue;
+      if (best_t[g]) g_tuned[{g, size_class(group_n[g])}] = best_t[g];
+      if (threads_out) threads_out[slot[g]] = best_t[g];
+    }
   }
+  // Hand-off level size (instances left at the default): whole batched
+  // calls timed with the shapes just chosen, the shortest wins.
+  double best_s = 1e300;
+  uint64_t best_l = kBatchLevelMax;
+  std::vector<rei_result> res(n);
+  for (int k = 13; k <= 19; k += 1) {
+    g_level_max.store(1ull << k);
+    const double t = now_s();
+    if ((r = rei_solve_batch(insts, n, hip_stream, arena_bytes, res.data())) != REI_OK) {
+      g_level_max.store(0);
+      return r;
+    }
+    const double dt = now_s() - t;
+    if (dt < best_s) {
+      best_s = dt;
+      best_l = 1ull << k;
+    }
+  }
+  g_level_max.store(best_l);
+  if (level_max_out) *level_max_out = best_l;
   return REI_OK;
 }
 
@@ -1442,7 +1524,7 @@ rei_status rei_set_chunk(rei_instance* inst, uint64_t max_candidates) {
 
 rei_status rei_set_batch_level(rei_instance* inst, uint64_t max_candidates) {
   if (!inst) return REI_ERR_INVALID_ARG;
-  inst->batch_level_max = max_candidates ? max_candidates : kBatchLevelMax;
+  inst->batch_level_max = max_candidates;
   return REI_OK;
 }
 
@@ -1491,13 +1573,14 @@ rei_status rei_set_max_errors(rei_instance* inst, uint32_t max_errors) {
 
 rei_status rei_set_profiling(rei_instance* inst, int enable) {
   if (!inst) return REI_ERR_INVALID_ARG;
+  if (enable < 0 || enable > 2) return REI_ERR_INVALID_ARG;
   if (enable && !inst->prof)
     for (int k = 0; k < REI_K_COUNT; ++k) {
       inst->st_launch[k] = 0;
       inst->st_ms[k] = 0;
       inst->st_units[k] = 0;
     }
-  inst->prof = enable != 0;
+  inst->prof = enable;
   return REI_OK;
 }
 

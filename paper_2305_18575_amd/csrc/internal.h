@@ -64,8 +64,8 @@ struct Ctrl {
 enum StopCode : uint32_t { STOP_NONE = 0, STOP_ANSWER = 1, STOP_OOM = 2, STOP_CAPACITY = 3, STOP_HANDOFF = 4 };
 // STOP_CAPACITY: the batched solver ran out of its preallocated rows; the
 // instance is solved again, from the start, on the per-chunk path.
-// STOP_HANDOFF: the batched solver reached a level of more than
-// kBatchLevelMax candidates (resume_level) with every lower level stored;
+// STOP_HANDOFF: the batched solver reached a level of more than level_max
+// candidates (resume_level) with every lower level stored;
 // the per-chunk path continues from there.
 struct DevState {
   uint64_t total_rows;      // rows stored (all levels)
@@ -175,7 +175,7 @@ constexpr uint32_t kBatchMaxCost = 63;   // largest max_cost handled in a batch
 constexpr int kBatchMaxW = 8;            // largest words per language
 constexpr uint32_t kBatchMaxIc = 64 * kBatchMaxW;  // largest |ic|
 constexpr uint32_t kBatchMaxPairs = 6144;          // largest guide table (cuts), kept in LDS
-constexpr uint64_t kBatchLevelMax = 1ull << 20;  // default: candidates of one level a workgroup takes on
+constexpr uint64_t kBatchLevelMax = 1ull << 16;  // default: candidates of one level a workgroup takes on
 constexpr uint32_t kBatchTreeNodes = 64; // answer-tree nodes written back (cost <= 63 needs <= 63)
 
 struct BatchDesc {

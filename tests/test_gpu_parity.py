@@ -453,7 +453,9 @@ def test_tuned_launch_shapes_give_identical_results(rei):
     hs = [rei.Instance(a, p, n, c, m) for (a, p, n, c, m) in specs]
     before = rei.solve_batch(hs)
     tuned = rei.tune_batch(hs)
-    assert tuned and all(t in (256, 512, 1024) for t in tuned.values())
+    shape = tuned["threads_per_instance"]
+    assert shape and all(t in (256, 512, 1024) for t in shape.values())
+    assert 1 << 13 <= tuned["level_max"] <= 1 << 19
     after = rei.solve_batch(hs)
     key = lambda r: (r.status, r.cost, r.regex, r.unique, r.candidates)
     assert [key(r) for r in before] == [key(r) for r in after]
@@ -476,3 +478,26 @@ def test_large_batch_equals_per_instance_solves(rei):
         assert key(h.solve()) == key(b)
     for h in hs:
         h.close()
+
+
+def test_kernel_statistics(rei):
+    """Profiling level 1 times the generators (units = candidates, summing to
+    the result's candidate counts); level 2 adds the other classes; enabling
+    clears the statistics, disabling keeps them."""
+    it = instances.single_instance(6, (1, 1, 1, 1, 1))
+    h = rei.Instance(it.alphabet, it.pos, it.neg, it.costs, it.max_cost)
+    classes = rei.KERNEL_CLASSES
+    h.set_profiling(True, level=1)
+    r = h.solve()
+    h.set_profiling(False)
+    stats = {c: h.kernel_stats(k) for k, c in enumerate(classes)}
+    gen_units = sum(stats[c][2] for c in classes if c.startswith("gen_"))
+    assert gen_units >= sum(r.candidates)  # chunks enqueued past the answer count too
+    assert all(stats[c][1] > 0 for c in classes if c.startswith("gen_") and stats[c][0])
+    assert stats["insert_survivors"][0] == 0 and stats["compact_winners"][0] == 0
+    h.set_profiling(True, level=2)
+    h.solve()
+    stats2 = {c: h.kernel_stats(k) for k, c in enumerate(classes)}
+    assert stats2["insert_survivors"][0] > 0 and stats2["compact_winners"][0] > 0
+    assert sum(stats2[c][2] for c in classes if c.startswith("gen_")) == gen_units
+    h.close()
