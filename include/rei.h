@@ -133,12 +133,13 @@ rei_status rei_solve_batch(rei_instance *const *insts, size_t n, void *hip_strea
  * instances once for each workgroup size (256, 512 and 1024 threads per
  * instance; at most 512 with 8 words per language), times each word-width
  * group's launch with events the launch records, and keeps for each group
- * the fastest size for groups of this many instances (by power-of-two size
- * class) in a table of the process that later rei_solve_batch calls on any
+ * the fastest size (best of three runs) for groups of this many instances
+ * (by power-of-two size class) in a table of the process that later rei_solve_batch calls on any
  * thread use.  Without an entry, a group gets enough waves per instance to
  * fill the device's wave slots.  Then the hand-off level size (for
- * instances that did not set rei_set_batch_level): whole calls are timed for
- * 2^13 .. 2^19 candidates and the fastest becomes the process default
+ * instances that did not set rei_set_batch_level): whole calls are timed
+ * three times for each of 2^13 .. 2^19 candidates and the fastest becomes
+ * the process default
  * (2^16 until then).  Results do not depend on either choice.  threads_out
  * (NULL or 5 entries, for W = 1 with keys in the table slots, then W = 1, 2,
  * 4, 8) receives the chosen sizes, 0 for groups without instances;

@@ -390,10 +390,20 @@ rei_status sync_state(rei_instance* in, hipStream_t s) {
 // Enqueues one chunk (no host synchronisation unless a buffer may have to
 // grow: then the stream is drained first and the buffer grown for the worst
 // case of this chunk).
-rei_status enqueue_chunk(rei_instance* in, hipStream_t s, uint32_t c, const Block& b, uint64_t e_base,
-                         uint64_t e0, uint64_t e1, bool* stopped) {
+// A piece of a chunk: candidates [e0, e1) of one block, whose first
+// candidate has level index e_base.  The pieces of a chunk are consecutive
+// in level index, so small blocks share one insert and one finalize.
+struct Piece {
+  Block b;
+  uint64_t e_base, e0, e1;
+};
+
+rei_status enqueue_chunk(rei_instance* in, hipStream_t s, uint32_t c, const std::vector<Piece>& pieces,
+                         bool* stopped) {
   const int W = in->st.W;
-  const uint64_t len = e1 - e0;
+  uint64_t len = 0;
+  for (const Piece& p : pieces) len += p.e1 - p.e0;
+  const uint64_t chunk_e0 = pieces[0].e_base + pieces[0].e0;
   const uint64_t words = (len + 31) / 32;
   rei_status r;
   auto worst_rows = [&] { return std::min(in->row_cap, in->known_rows + in->pending + len); };
@@ -428,25 +438,30 @@ rei_status enqueue_chunk(rei_instance* in, hipStream_t s, uint32_t c, const Bloc
   g.max_len = in->st.max_len;
   g.n = in->st.n;
   g.n_pairs = (uint32_t)in->st.gt_pair.size();
-  g.e0 = e0;
-  g.e1 = e1;
-  g.char_index = in->d_char_index;
-  if (b.op == OP_CHAR) {
-    uint32_t first = 0, count = 0;
-    chars_at(in, c, &first, &count);
-    g.char_index = in->d_char_index + first;
-  }
   g.st = in->d_state;
   g.inl = in->inl ? 1u : 0u;
-  if (b.op != OP_CHAR) {
-    g.lstart = in->lstart[b.L];
-    g.lcount = in->lcount[b.L];
-    if (b.op == OP_CONCAT || b.op == OP_UNION) {
-      g.rstart = in->lstart[b.R];
-      g.rcount = in->lcount[b.R];
+  for (const Piece& p : pieces) {
+    const Block& b = p.b;
+    g.e0 = p.e0;
+    g.e1 = p.e1;
+    g.rel0 = (uint32_t)(p.e_base + p.e0 - chunk_e0);
+    g.char_index = in->d_char_index;
+    if (b.op == OP_CHAR) {
+      uint32_t first = 0, count = 0;
+      chars_at(in, c, &first, &count);
+      g.char_index = in->d_char_index + first;
     }
+    g.lstart = g.lcount = g.rstart = g.rcount = 0;
+    if (b.op != OP_CHAR) {
+      g.lstart = in->lstart[b.L];
+      g.lcount = in->lcount[b.L];
+      if (b.op == OP_CONCAT || b.op == OP_UNION) {
+        g.rstart = in->lstart[b.R];
+        g.rcount = in->lcount[b.R];
+      }
+    }
+    LAUNCH(in, s, REI_K_GEN_CHAR + b.op, p.e1 - p.e0, launch_gen(W, b.op, g, b.same, s));
   }
-  LAUNCH(in, s, REI_K_GEN_CHAR + b.op, len, launch_gen(W, b.op, g, b.same, s));
 
   ChunkArgs ca{};
   ca.rows = in->d_rows;
@@ -470,7 +485,7 @@ rei_status enqueue_chunk(rei_instance* in, hipStream_t s, uint32_t c, const Bloc
   ca.uniq = in->d_levels + L;
   ca.cand = in->d_levels + 2 * L;
   ca.cost = c;
-  ca.chunk_e0 = e_base + e0;
+  ca.chunk_e0 = chunk_e0;
   ca.len = len;
   if (otf_level) {
     LAUNCH(in, s, REI_K_COMPACT, len, launch_account(ca, s));
@@ -768,16 +783,26 @@ rei_status search_levels(rei_instance* in, hipStream_t s) {
       in->err = "candidate count overflows 64 bits";
       return REI_ERR_TOO_LARGE;
     }
-    uint64_t e_base = 0;
+    // chunks of chunk_max consecutive level indices: large blocks are split,
+    // small ones share a chunk
+    uint64_t e_base = 0, acc = 0;
+    std::vector<Piece> pieces;
     for (const Block& b : blocks) {
       for (uint64_t e0 = 0; e0 < b.count && !stopped;) {
-        const uint64_t e1 = std::min(b.count, e0 + in->chunk_max);
-        if ((r = enqueue_chunk(in, s, c, b, e_base, e0, e1, &stopped)) != REI_OK) return r;
+        const uint64_t e1 = std::min(b.count, e0 + (in->chunk_max - acc));
+        pieces.push_back({b, e_base, e0, e1});
+        acc += e1 - e0;
         e0 = e1;
+        if (acc == in->chunk_max) {
+          if ((r = enqueue_chunk(in, s, c, pieces, &stopped)) != REI_OK) return r;
+          pieces.clear();
+          acc = 0;
+        }
       }
       if (stopped) break;
       e_base += b.count;
     }
+    if (!stopped && !pieces.empty() && (r = enqueue_chunk(in, s, c, pieces, &stopped)) != REI_OK) return r;
     // level boundary: the next level's blocks depend on this level's size
     if ((r = sync_state(in, s)) != REI_OK) return r;
     in->lcount[c] = in->h_levels[c];
@@ -1390,7 +1415,8 @@ rei_status rei_tune_batch(rei_instance* const* insts, size_t n, void* hip_stream
   for (int g = 0; g <= kBatchMaxW; ++g) best_ms[g] = 1e300;
   rei_status r;
   try {
-    for (uint32_t c : cand) {
+    for (int rep = 0; rep < 3 * 3; ++rep) {  // each shape three times, best of three
+      const uint32_t c = cand[rep % 3];
       BatchRun run;
       run.force_threads = c;
       run.time_groups = true;
@@ -1438,7 +1464,8 @@ rei_status rei_tune_batch(rei_instance* const* insts, size_t n, void* hip_stream
   double best_s = 1e300;
   uint64_t best_l = kBatchLevelMax;
   std::vector<rei_result> res(n);
-  for (int k = 13; k <= 19; k += 1) {
+  for (int rep = 0; rep < 3 * 7; ++rep) {  // 2^13 .. 2^19, best of three each
+    const int k = 13 + rep % 7;
     g_level_max.store(1ull << k);
     const double t = now_s();
     if ((r = rei_solve_batch(insts, n, hip_stream, arena_bytes, res.data())) != REI_OK) {

@@ -103,6 +103,7 @@ struct GenArgs {
   uint32_t n_pairs;           // guide-table entries
   // block / chunk
   uint64_t e0, e1;            // chunk range inside the block
+  uint32_t rel0;              // chunk-relative index of the block's candidate e0
   uint64_t lstart, lcount;    // left operand level: first row, number of rows
   uint64_t rstart, rcount;    // right operand level
   const int32_t* char_index;  // base level only

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256) void gen_char(GenArgs a) {
   const int idx = valid ? a.char_index[e] : -1;
 #pragma unroll
   for (int k = 0; k < W; ++k) key[k] = (idx >= 0 && (idx >> 6) == k) ? (1ull << (idx & 63)) : 0ull;
-  filter_emit<W, kInl>(a, valid, false, key, (uint32_t)(e - a.e0));
+  filter_emit<W, kInl>(a, valid, false, key, (uint32_t)(e - a.e0) + a.rel0);
 }
 
 // r? = eps + r; eps is word 0 of ic (shortlex puts the empty word first).
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void gen_question(GenArgs a) {
   for (int k = 0; k < W; ++k) key[k] = valid ? src[k] : 0ull;
   const bool dup = (key[0] & 1ull) != 0;  // already contains eps: r? = r
   key[0] |= 1ull;
-  filter_emit<W, kInl>(a, valid, dup, key, (uint32_t)(e - a.e0));
+  filter_emit<W, kInl>(a, valid, dup, key, (uint32_t)(e - a.e0) + a.rel0);
 }
 
 // r* for 64 rows per workgroup, bit-sliced: Xt[w] / Yt[w] hold bit t = row t's
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) void gen_star(GenArgs a) {
 #pragma unroll
     for (int k = 0; k < W; ++k) key[k] = transpose64(Yt[64 * k + lane]);
     const uint64_t e = base + lane;
-    filter_emit<W, kInl>(a, e < a.e1, false, key, (uint32_t)(e - a.e0));
+    filter_emit<W, kInl>(a, e < a.e1, false, key, (uint32_t)(e - a.e0) + a.rel0);
   }
 }
 
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(256) void gen_concat(GenArgs a, uint32_t yt_per_wg,
       const uint64_t j = (t0 + tq) * 64 + lane;
       const uint64_t e = i * nR + j;
       const bool valid = (j < nR) && (e >= a.e0) && (e < a.e1);
-      filter_emit<W, kInl>(a, valid, false, key, (uint32_t)(e - a.e0));
+      filter_emit<W, kInl>(a, valid, false, key, (uint32_t)(e - a.e0) + a.rel0);
     }
   }
 }
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void gen_union(GenArgs a) {
     eqy = eqy && key[k] == yv;
   }
   // x+y equals x or y (one contains the other): that language is stored
-  filter_emit<W, kInl>(a, valid, eqx || eqy, key, (uint32_t)(e - a.e0));
+  filter_emit<W, kInl>(a, valid, eqx || eqy, key, (uint32_t)(e - a.e0) + a.rel0);
 }
 
 // ---- chunk pipeline ------------------------------------------------------
