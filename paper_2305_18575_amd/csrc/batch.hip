@@ -540,6 +540,13 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
     d.hlev[L + i] = s_uniq[i];
     d.hlev[2 * L + i] = s_cand[i];
   }
+  // Publish: every result above, and the rows and table in device memory,
+  // become visible to the host and to other kernels before the flag does,
+  // so the host may hand the instance to the per-chunk path while the rest
+  // of the launch still runs.
+  __threadfence_system();
+  __syncthreads();
+  if (tid == 0) __hip_atomic_store(&d.hst->done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 }  // namespace

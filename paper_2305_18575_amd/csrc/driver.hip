@@ -931,7 +931,7 @@ struct BatchRun {
   std::vector<SideStream> sides;
   hipEvent_t fork = nullptr;
   rei_instance* pin = nullptr;  // holds the batched launches' timings
-  size_t rec_first = 0;
+  std::vector<ProfRec> brecs;   // the batched launches' event pairs
   std::vector<int> rec_w;
   // launch shape: threads per instance of each group (forced by the tuner,
   // else tuned or from the batch size), and the tuner's per-group timing
@@ -1057,9 +1057,9 @@ rei_status batch_launch(rei_instance* const* insts, size_t n, hipStream_t s, uin
     const int g = in->inl ? 0 : in->st.W;
     groups[g].push_back(make_desc(in));
     run->members[g].push_back(in);
+    __atomic_store_n(&in->h_state->done, 0u, __ATOMIC_RELEASE);
   }
   run->pin = n ? insts[0] : nullptr;
-  run->rec_first = run->pin ? run->pin->recs.size() : 0;
   // One launch per word width; the first on s, the others on side streams
   // that start after s's earlier work and that s waits for, so the groups
   // run side by side.
@@ -1100,7 +1100,13 @@ rei_status batch_launch(rei_instance* const* insts, size_t n, hipStream_t s, uin
       if ((r = prof_begin(run->pin, gs, REI_K_BATCH, &ev, &ev2)) != REI_OK) return r;
       HIP_OK(in0, launch_solve_batch(g ? g : 1, g == 0, th, db.d, (uint32_t)groups[g].size(), gs));
       if ((r = prof_end(run->pin, gs, REI_K_BATCH, ev, ev2, 0)) != REI_OK) return r;
-      if (run->pin->prof) run->rec_w.push_back(g);
+      if (run->pin->prof) {
+        // kept apart from the instance's own records until the launch is
+        // known to have finished (the instance may continue on the grid)
+        run->brecs.push_back(run->pin->recs.back());
+        run->pin->recs.pop_back();
+        run->rec_w.push_back(g);
+      }
     }
     if (!first) {
       HIP_OK(in0, hipEventRecord(run->sides.back().join, gs));
@@ -1125,35 +1131,58 @@ void batch_release(BatchRun* run) {
 
 // After run->s has finished the launches: results of the batched instances;
 // those that outgrew their preallocated rows are appended to run->grid.
-rei_status batch_collect(BatchRun* run) {
+// Reads a batched instance's final state from its pinned buffers (the
+// kernel wrote them); true when it continues on the per-chunk path.
+bool batch_take_state(rei_instance* in) {
+  in->known_rows = in->h_state->total_rows;
+  in->pending = 0;
+  const uint64_t k = std::min<uint64_t>(in->h_tree[0], kBatchTreeNodes);
+  in->tree.assign(in->h_tree + 1, in->h_tree + 1 + 4 * k);
+  if (in->h_state->stop == STOP_CAPACITY || in->h_state->stop == STOP_HANDOFF) {
+    in->resume_level = in->h_state->stop == STOP_HANDOFF ? (uint32_t)in->h_state->resume_level : 0;
+    return true;
+  }
+  return false;
+}
+
+// The batched launches' event pairs go into the statistics of insts[0];
+// call once nothing else uses that instance.
+rei_status batch_fold_prof(BatchRun* run) {
+  if (!run->pin || run->brecs.empty()) return REI_OK;
+  uint64_t group_cand[kBatchMaxW + 1] = {0};
+  for (int g = 0; g <= kBatchMaxW; g = g ? 2 * g : 1)
+    for (rei_instance* in : run->members[g]) {
+      const uint64_t L = in->max_cost + 2;
+      for (uint64_t c = 0; c < L; ++c) group_cand[g] += in->h_levels[2 * L + c];
+    }
+  for (size_t q = 0; q < run->brecs.size(); ++q) run->brecs[q].units = group_cand[run->rec_w[q]];
+  run->pin->recs.insert(run->pin->recs.end(), run->brecs.begin(), run->brecs.end());
+  run->brecs.clear();
+  return prof_collect(run->pin);
+}
+
+// After run->s has finished the launches: results of the batched instances
+// (those already taken, listed in `taken`, are skipped); those that
+// continue on the per-chunk path are appended to run->grid.
+rei_status batch_collect(BatchRun* run, const std::vector<rei_instance*>* taken = nullptr,
+                         bool fold_prof = true) {
   rei_status r;
   if (run->pin) HIP_OK(run->pin, hipStreamSynchronize(run->s));
   batch_release(run);
-  uint64_t group_cand[kBatchMaxW + 1] = {0};
   std::vector<rei_instance*> done;
   for (int g = 0; g <= kBatchMaxW; g = g ? 2 * g : 1)
     for (rei_instance* in : run->members[g]) {
-      // the kernel wrote the state, the level counters and the answer tree
-      // into this instance's pinned buffers
-      in->known_rows = in->h_state->total_rows;
-      in->pending = 0;
-      const uint64_t L = in->max_cost + 2;
-      const uint64_t k = std::min<uint64_t>(in->h_tree[0], kBatchTreeNodes);
-      in->tree.assign(in->h_tree + 1, in->h_tree + 1 + 4 * k);
-      for (uint64_t c = 0; c < L; ++c) group_cand[g] += in->h_levels[2 * L + c];
-      if (in->h_state->stop == STOP_CAPACITY || in->h_state->stop == STOP_HANDOFF) {
-        in->resume_level = in->h_state->stop == STOP_HANDOFF ? (uint32_t)in->h_state->resume_level : 0;
+      if (taken && std::find(taken->begin(), taken->end(), in) != taken->end()) continue;
+      if (batch_take_state(in))
         run->grid.push_back(in);
-      } else {
+      else
         done.push_back(in);
-      }
     }
-  for (size_t q = 0; q < run->rec_w.size(); ++q) run->pin->recs[run->rec_first + q].units = group_cand[run->rec_w[q]];
   for (rei_instance* in : done) {
     if ((r = finish_solve(in, run->t0)) != REI_OK) return r;
     run->finished.push_back(in);
   }
-  if (run->pin && run->pin->prof && (r = prof_collect(run->pin)) != REI_OK) return r;
+  if (fold_prof && (r = batch_fold_prof(run)) != REI_OK) return r;
   return REI_OK;
 }
 
@@ -1211,6 +1240,80 @@ rei_status solve_grid_instances(const std::vector<rei_instance*>& grid, hipStrea
     if (r != REI_OK) return r;
   return REI_OK;
 }
+
+// Worker threads that run the per-chunk path for instances handed to them
+// while a batched launch still runs: up to 8 threads, each driving its own
+// pooled stream, started as instances arrive.
+class GridPool {
+ public:
+  explicit GridPool(double t0) : t0_(t0) {}
+  ~GridPool() { (void)join(); }
+  void submit(rei_instance* in) {
+    std::lock_guard<std::mutex> lk(mu_);
+    q_.push_back(in);
+    if (idle_ == 0 && threads_.size() < 8) threads_.emplace_back([this] { work(); });
+    cv_.notify_one();
+  }
+  // Waits for every submitted instance; the first error, if any.
+  rei_status join() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      closed_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : threads_)
+      if (t.joinable()) t.join();
+    threads_.clear();
+    return status_;
+  }
+
+ private:
+  void work() {
+    SideStream ss;
+    bool have = false;
+    for (;;) {
+      rei_instance* in = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        ++idle_;
+        cv_.wait(lk, [&] { return closed_ || !q_.empty(); });
+        --idle_;
+        if (q_.empty()) break;
+        in = q_.front();
+        q_.pop_front();
+      }
+      rei_status r = REI_OK;
+      try {
+        if (hipSetDevice(in->device) != hipSuccess) r = REI_ERR_DEVICE;
+        if (r == REI_OK && !have) {
+          r = side_acquire(in, &ss);
+          have = r == REI_OK;
+        }
+        if (r == REI_OK) r = search_levels(in, ss.s);
+        if (r == REI_OK) r = finish_solve(in, t0_);
+      } catch (const std::bad_alloc&) {
+        r = REI_ERR_HOST_ALLOC;
+      }
+      if (r != REI_OK) {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (status_ == REI_OK) status_ = r;
+      }
+    }
+    if (have) {
+      (void)hipStreamSynchronize(ss.s);
+      std::lock_guard<std::mutex> g(g_pool_mu);
+      g_side_free.push_back(ss);
+    }
+  }
+  double t0_;
+  std::mutex mu_;
+  std::condition_variable cv_;
+  std::deque<rei_instance*> q_;
+  std::vector<std::thread> threads_;
+  int idle_ = 0;
+  bool closed_ = false;
+  rei_status status_ = REI_OK;
+};
 
 // Frees the language cache, the table and the chunk buffers (the staged
 // tables and the result stay).
@@ -1293,7 +1396,9 @@ rei_status create_device(rei_instance* in) {
   HIP_OK(in, hipMalloc(&in->d_state, sizeof(DevState)));
   const uint64_t L = in->max_cost + 2;
   HIP_OK(in, hipMalloc(&in->d_levels, 3 * L * 8));
-  const unsigned fl = hipHostMallocMapped | hipHostMallocPortable;
+  // coherent (fine-grained): the batched solver's completion flag is read
+  // by the host while the launch still runs
+  const unsigned fl = hipHostMallocMapped | hipHostMallocPortable | hipHostMallocCoherent;
   HIP_OK(in, hipHostMalloc((void**)&in->h_state, sizeof(DevState), fl));
   HIP_OK(in, hipHostMalloc((void**)&in->h_levels, 3 * L * 8, fl));
   HIP_OK(in, hipHostMalloc((void**)&in->h_tree, (1 + 4 * kBatchTreeNodes) * 8, fl));
@@ -1383,14 +1488,58 @@ rei_status rei_solve_batch(rei_instance* const* insts, size_t n, void* hip_strea
       batch_release(&run);
       return r;
     }
+    // Instances that are not batched start on the per-chunk path at once;
+    // batched ones that hand off (or outgrow their rows) follow as soon as
+    // their completion flag shows, while the launches still run.
+    GridPool pool(run.t0);
+    for (rei_instance* in : run.grid) pool.submit(in);
+    run.grid.clear();
+    std::vector<rei_instance*> members, taken;
+    for (int g = 0; g <= kBatchMaxW; g = g ? 2 * g : 1)
+      members.insert(members.end(), run.members[g].begin(), run.members[g].end());
+    std::vector<char> seen(members.size(), 0);
+    size_t left = members.size();
+    bool launches_done = false;
+    while (left) {
+      bool progress = false;
+      for (size_t i = 0; i < members.size(); ++i) {
+        if (seen[i] || !__atomic_load_n(&members[i]->h_state->done, __ATOMIC_ACQUIRE)) continue;
+        seen[i] = 1;
+        --left;
+        progress = true;
+        if (batch_take_state(members[i])) {
+          taken.push_back(members[i]);
+          pool.submit(members[i]);
+        }
+      }
+      if (!left || progress) continue;
+      if (launches_done) break;  // every flag is final: collected below
+      const hipError_t q = hipStreamQuery(s);
+      if (q == hipSuccess) {
+        launches_done = true;  // one more pass sees every flag
+      } else if (q != hipErrorNotReady) {
+        for (size_t i = 0; i < n; ++i) insts[i]->err = std::string("batched launch: ") + hipGetErrorString(q);
+        (void)pool.join();
+        (void)hipStreamSynchronize(s);
+        batch_release(&run);
+        return REI_ERR_DEVICE;
+      } else {
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+      }
+    }
     hipError_t se = hipStreamSynchronize(s);
     if (se != hipSuccess) {
       for (size_t i = 0; i < n; ++i) insts[i]->err = std::string("batched launch: ") + hipGetErrorString(se);
+      (void)pool.join();
       batch_release(&run);
       return REI_ERR_DEVICE;
     }
-    if ((r = batch_collect(&run)) != REI_OK) return r;
-    if ((r = solve_grid_instances(run.grid, s, run.t0)) != REI_OK) return r;
+    r = batch_collect(&run, &taken, false);
+    for (rei_instance* in : run.grid) pool.submit(in);
+    const rei_status rp = pool.join();
+    if (r != REI_OK) return r;
+    if (rp != REI_OK) return rp;
+    if ((r = batch_fold_prof(&run)) != REI_OK) return r;
     for (size_t i = 0; i < n; ++i) {
       insts[i]->res.seconds_solve = now_s() - run.t0;
       out[i] = insts[i]->res;

@@ -76,7 +76,9 @@ struct DevState {
   uint64_t resume_level;    // STOP_HANDOFF: the first level not searched
   uint32_t otf_on;          // OnTheFly mode allowed when the cache fills
   uint32_t otf;             // OnTheFly mode active: no storage, precision only
-  uint64_t pad[2];
+  uint32_t done;            // batched solver: set last, once this state is final
+  uint32_t pad32;
+  uint64_t pad[1];
 };
 
 // Arguments shared by all generator kernels.
