@@ -250,6 +250,7 @@ typedef enum {
   REI_K_COMPACT,
   REI_K_OTHER,
   REI_K_BATCH,          /* the batched solver (rei_solve_batch), per word width */
+  REI_K_GEN_MIXED,      /* small blocks of several constructors in one launch */
   REI_K_COUNT
 } rei_kernel_class;
 

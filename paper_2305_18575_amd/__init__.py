@@ -23,7 +23,7 @@ STATUS = {0: "OK", 1: "NOT_FOUND", 2: "OUT_OF_MEMORY", -1: "INVALID_ARG",
           -6: "HOST_ALLOC"}
 
 KERNEL_CLASSES = ["gen_char", "gen_question", "gen_star", "gen_concat", "gen_union",
-                  "insert_survivors", "compact_winners", "other", "solve_batch"]
+                  "insert_survivors", "compact_winners", "other", "solve_batch", "gen_pieces"]
 
 # exported symbols, as declared in include/rei.h
 EXPORTS = ["rei_create", "rei_solve", "rei_solve_batch", "rei_tune_batch", "rei_server_create", "rei_server_submit",

@@ -26,10 +26,6 @@ struct BlockD {
 // (Agent scope would write back and invalidate the whole L2 at each phase.)
 __device__ __forceinline__ void phase_barrier() { __syncthreads(); }
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
 
 // Concatenation of 64 candidates that share one operand ("uniform") while the
 // other operand varies over the 64 bit positions of the transposed tile T.
@@ -352,12 +348,12 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
               for (int k = 0; k < W; ++k)
                 T[64 * k + lane] = transpose64(jr < nR ? d.rows[(rst + jr) * W + k] : 0ull);
               if (lane < (uint32_t)W) U[lane] = d.rows[(lst + i) * W + lane];
-              wave_sync();
+              wave_sync_lds();
               uint64_t key[W];
               concat_tile<W, false>(T, U, s_gto, s_gtp, d.n, key);
               const uint64_t e = i * nR + jr;
               filter_emit<W, kInl>(probe, sink, jr < nR && e >= e0 && e < e1, false, key, (uint32_t)(rel0 + e));
-              wave_sync();
+              wave_sync_lds();
             }
           } else {
             // left operands across the lanes (the right level is small)
@@ -372,12 +368,12 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
               for (int k = 0; k < W; ++k)
                 T[64 * k + lane] = transpose64(ir < nL ? d.rows[(lst + ir) * W + k] : 0ull);
               if (lane < (uint32_t)W) U[lane] = d.rows[(rst + j) * W + lane];
-              wave_sync();
+              wave_sync_lds();
               uint64_t key[W];
               concat_tile<W, true>(T, U, s_gto, s_gtp, d.n, key);
               const uint64_t e = ir * nR + j;
               filter_emit<W, kInl>(probe, sink, ir < nL && e >= e0 && e < e1, false, key, (uint32_t)(rel0 + e));
-              wave_sync();
+              wave_sync_lds();
             }
           }
         }

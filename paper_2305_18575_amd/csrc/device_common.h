@@ -228,6 +228,12 @@ __device__ __forceinline__ void filter_emit(const Probe& a, const Sink& o, bool 
   }
 }
 
+// Orders a wave's LDS writes before its later LDS reads by other lanes.
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Pairs (i, j) with i < j of an n-row level, row-major: index of the first
 // pair of row i is i*n - i*(i+1)/2.
 __device__ __forceinline__ void tri_decode(uint64_t e, uint64_t n, uint64_t* pi, uint64_t* pj) {

@@ -172,7 +172,7 @@ constexpr unsigned kTimingEvent = hipEventDisableSystemFence;
 // Generators and the batched solver are launched through launch_timed, which
 // records the pair at the kernel's own start and end; the other launchers
 // (several small kernels each) are bracketed by events on the stream.
-bool self_timed(int k) { return k <= REI_K_GEN_UNION || k == REI_K_BATCH; }
+bool self_timed(int k) { return k <= REI_K_GEN_UNION || k == REI_K_BATCH || k == REI_K_GEN_MIXED; }
 
 rei_status prof_event(rei_instance* in, hipEvent_t* ev) {
   if (in->pool.empty()) {
@@ -440,8 +440,62 @@ rei_status enqueue_chunk(rei_instance* in, hipStream_t s, uint32_t c, const std:
   g.n_pairs = (uint32_t)in->st.gt_pair.size();
   g.st = in->d_state;
   g.inl = in->inl ? 1u : 0u;
+  // small pieces (W <= kPiecesMaxW) share gen_pieces launches of up to
+  // kMaxPieces pieces; larger ones get their constructor's kernel
+  PieceArgs pa{};
+  auto flush_pieces = [&]() -> rei_status {
+    if (!pa.n) return REI_OK;
+    GenArgs gp = g;  // pieces carry their own ranges; characters index from the table's start
+    gp.char_index = in->d_char_index;
+    LAUNCH(in, s, REI_K_GEN_MIXED, pa.items_cand, launch_gen_pieces(W, gp, pa, s));
+    pa = PieceArgs{};
+    return REI_OK;
+  };
   for (const Piece& p : pieces) {
     const Block& b = p.b;
+    if (W <= kPiecesMaxW && p.e1 - p.e0 <= kSmallPiece) {
+      PieceD& d = pa.p[pa.n];
+      d = PieceD{};
+      d.op = (uint32_t)b.op;
+      d.same = b.same ? 1u : 0u;
+      d.e0 = p.e0;
+      d.e1 = p.e1;
+      d.rel0 = (uint32_t)(p.e_base + p.e0 - chunk_e0);
+      if (b.op == OP_CHAR) {
+        uint32_t first = 0, count = 0;
+        chars_at(in, c, &first, &count);
+        d.char_off = first;
+      } else {
+        d.lstart = in->lstart[b.L];
+        d.lcount = in->lcount[b.L];
+        if (b.op == OP_CONCAT || b.op == OP_UNION) {
+          d.rstart = in->lstart[b.R];
+          d.rcount = in->lcount[b.R];
+        }
+      }
+      d.item0 = pa.items;
+      uint64_t items;
+      if (b.op == OP_CONCAT) {
+        const uint64_t nR = d.rcount, nL = d.lcount;
+        const uint64_t i_lo = p.e0 / nR, i_hi = (p.e1 - 1) / nR;
+        d.left_lanes = (nR < 64 && nR < nL) ? 1u : 0u;
+        if (!d.left_lanes) {
+          d.t0 = i_lo;
+          d.nt = (nR + 63) / 64;
+          items = (i_hi - i_lo + 1) * d.nt;
+        } else {
+          d.t0 = i_lo / 64;
+          d.nt = nR;
+          items = (i_hi / 64 - i_lo / 64 + 1) * nR;
+        }
+      } else {
+        items = (p.e1 - p.e0 + 63) / 64;
+      }
+      pa.items += items;
+      pa.items_cand += p.e1 - p.e0;
+      if (++pa.n == kMaxPieces && (r = flush_pieces()) != REI_OK) return r;
+      continue;
+    }
     g.e0 = p.e0;
     g.e1 = p.e1;
     g.rel0 = (uint32_t)(p.e_base + p.e0 - chunk_e0);
@@ -462,6 +516,7 @@ rei_status enqueue_chunk(rei_instance* in, hipStream_t s, uint32_t c, const std:
     }
     LAUNCH(in, s, REI_K_GEN_CHAR + b.op, p.e1 - p.e0, launch_gen(W, b.op, g, b.same, s));
   }
+  if ((r = flush_pieces()) != REI_OK) return r;
 
   ChunkArgs ca{};
   ca.rows = in->d_rows;
@@ -1780,6 +1835,7 @@ const char* rei_kernel_name(rei_kernel_class k) {
     case REI_K_COMPACT: return "compact_winners";
     case REI_K_OTHER: return "other";
     case REI_K_BATCH: return "solve_batch";
+    case REI_K_GEN_MIXED: return "gen_pieces";
     default: return "?";
   }
 }

@@ -172,6 +172,30 @@ constexpr uint64_t kSmallChunk = 1ull << 14;   // candidates finalized by one wo
 
 const char* gen_kernel_name(int op);
 
+// Many small pieces of one chunk in one launch (gen_pieces): each wave takes
+// one item of 64 candidates of one piece.  Items: CHAR, QUESTION, STAR,
+// UNION: 64 consecutive candidates; CONCAT: one left row and a tile of 64
+// right rows (or, with left_lanes, one right row and a tile of 64 left
+// rows, when the right level is small).
+constexpr int kMaxPieces = 32;
+constexpr uint64_t kSmallPiece = 16384;  // pieces up to this size go to gen_pieces
+constexpr int kPiecesMaxW = 8;           // widest languages gen_pieces handles
+struct PieceD {
+  uint32_t op, same, left_lanes, char_off;
+  uint32_t rel0, pad;
+  uint64_t e0, e1;                    // block-local candidate range
+  uint64_t lstart, lcount, rstart, rcount;
+  uint64_t item0;                     // first item of this piece
+  uint64_t t0, nt;                    // CONCAT: first row of the uniform side's range, tiles per row
+};
+struct PieceArgs {
+  uint32_t n, pad;
+  uint64_t items;       // work items of all pieces
+  uint64_t items_cand;  // candidates of all pieces (host bookkeeping)
+  PieceD p[kMaxPieces];
+};
+hipError_t launch_gen_pieces(int W, const GenArgs& a, const PieceArgs& p, hipStream_t s);
+
 // ---- batched solver: one workgroup runs the whole search of one instance --
 constexpr uint32_t kBatchChunk = 8192;   // candidates per chunk
 constexpr uint32_t kBatchMaxCost = 63;   // largest max_cost handled in a batch

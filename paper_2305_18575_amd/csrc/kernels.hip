@@ -243,6 +243,129 @@ __global__ __launch_bounds__(256) void gen_union(GenArgs a) {
   filter_emit<W, kInl>(a, valid, eqx || eqy, key, (uint32_t)(e - a.e0) + a.rel0);
 }
 
+// Many small pieces of one chunk (see PieceArgs): one wave per item of 64
+// candidates, so a level's small constructor blocks cost one launch.  The
+// constructors are those of the kernels above, at wave scale; the guide
+// table is read through the caches.
+template <int W, bool kInl>
+__global__ __launch_bounds__(256) void gen_pieces(GenArgs a, PieceArgs pa) {
+  __shared__ uint64_t lds[4][2 * 64 * W + W];
+  if (a.st->stop) return;
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint64_t* X = lds[wave];       // star: X tile; concat: operand tile
+  uint64_t* Y = X + 64 * W;      // star: Y tile
+  uint64_t* U = Y + 64 * W;      // concat: the uniform operand
+  for (uint64_t it = (uint64_t)blockIdx.x * 4 + wave; it < pa.items; it += (uint64_t)gridDim.x * 4) {
+    uint32_t k = 0;
+    while (k + 1 < pa.n && pa.p[k + 1].item0 <= it) ++k;
+    const PieceD& p = pa.p[k];
+    const uint64_t li = it - p.item0;
+    uint64_t key[W];
+    bool valid = false, dup = false;
+    uint64_t e = 0;
+    if (p.op == OP_CHAR || p.op == OP_QUESTION || p.op == OP_UNION) {
+      e = p.e0 + 64 * li + lane;
+      valid = e < p.e1;
+      if (p.op == OP_CHAR) {
+        const int idx = valid ? a.char_index[p.char_off + e] : -1;
+#pragma unroll
+        for (int q = 0; q < W; ++q) key[q] = (idx >= 0 && (idx >> 6) == q) ? (1ull << (idx & 63)) : 0ull;
+      } else if (p.op == OP_QUESTION) {
+        const uint64_t* src = a.rows + (p.lstart + (valid ? e : 0)) * W;
+#pragma unroll
+        for (int q = 0; q < W; ++q) key[q] = valid ? src[q] : 0ull;
+        dup = (key[0] & 1ull) != 0;
+        key[0] |= 1ull;
+      } else {
+        uint64_t i = 0, j = 0;
+        if (valid) {
+          if (p.same) {
+            tri_decode(e, p.lcount, &i, &j);
+          } else {
+            i = e / p.rcount;
+            j = e - i * p.rcount;
+          }
+        }
+        const uint64_t* x = a.rows + (p.lstart + i) * W;
+        const uint64_t* y = a.rows + (p.rstart + j) * W;
+        bool eqx = true, eqy = true;
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+          const uint64_t xv = valid ? x[q] : 0ull, yv = valid ? y[q] : 0ull;
+          key[q] = xv | yv;
+          eqx = eqx && key[q] == xv;
+          eqy = eqy && key[q] == yv;
+        }
+        dup = eqx || eqy;
+      }
+    } else if (p.op == OP_STAR) {
+      // Y(eps) = 1; by increasing length, Y(w) = OR over cuts with a
+      // non-empty first factor of X(u) & Y(v)
+      e = p.e0 + 64 * li + lane;
+      valid = e < p.e1;
+#pragma unroll
+      for (int q = 0; q < W; ++q) {
+        X[64 * q + lane] = transpose64(valid ? a.rows[(p.lstart + e) * W + q] : 0ull);
+        Y[64 * q + lane] = (q == 0 && lane == 0) ? ~0ull : 0ull;
+      }
+      wave_sync_lds();
+      for (uint32_t l = 1; l <= a.max_len; ++l) {
+        const uint32_t lo = a.len_off[l], hi = a.len_off[l + 1];
+        for (uint32_t w = lo + lane; w < hi; w += 64) {
+          uint64_t acc = 0;
+          const uint32_t q1 = a.gt_off[w + 1];
+          for (uint32_t q = a.gt_off[w] + 1; q < q1; ++q) {
+            const uint32_t pr = a.gt_pair[q];
+            acc |= X[pr >> 16] & Y[pr & 0xFFFFu];
+          }
+          Y[w] = acc;
+        }
+        wave_sync_lds();
+      }
+#pragma unroll
+      for (int q = 0; q < W; ++q) key[q] = transpose64(Y[64 * q + lane]);
+    } else {  // OP_CONCAT
+      const uint64_t nR = p.rcount, nL = p.lcount;
+      uint64_t i, j;
+      if (!p.left_lanes) {  // right rows across the lanes, one left row
+        i = p.t0 + li / p.nt;
+        j = 64 * (li % p.nt) + lane;
+#pragma unroll
+        for (int q = 0; q < W; ++q) X[64 * q + lane] = transpose64(j < nR ? a.rows[(p.rstart + j) * W + q] : 0ull);
+        if (lane < (uint32_t)W) U[lane] = a.rows[(p.lstart + i) * W + lane];
+        valid = j < nR;
+      } else {  // left rows across the lanes, one right row
+        i = 64 * (p.t0 + li / p.nt) + lane;
+        j = li % p.nt;
+#pragma unroll
+        for (int q = 0; q < W; ++q) X[64 * q + lane] = transpose64(i < nL ? a.rows[(p.lstart + i) * W + q] : 0ull);
+        if (lane < (uint32_t)W) U[lane] = a.rows[(p.rstart + j) * W + lane];
+        valid = i < nL;
+      }
+      wave_sync_lds();
+#pragma unroll
+      for (int q = 0; q < W; ++q) {
+        const uint32_t w = 64u * q + lane;
+        uint64_t acc = 0;
+        if (w < a.n) {
+          const uint32_t q1 = a.gt_off[w + 1];
+          for (uint32_t c = a.gt_off[w]; c < q1; ++c) {
+            const uint32_t pr = a.gt_pair[c];
+            const uint32_t uu = p.left_lanes ? (pr & 0xFFFFu) : (pr >> 16);   // index into the uniform row
+            const uint32_t tt = p.left_lanes ? (pr >> 16) : (pr & 0xFFFFu);   // index into the tile
+            if ((U[uu >> 6] >> (uu & 63)) & 1ull) acc |= X[tt];
+          }
+        }
+        key[q] = transpose64(acc);
+      }
+      e = i * nR + j;
+      valid = valid && e >= p.e0 && e < p.e1;
+    }
+    filter_emit<W, kInl>(a, valid, dup, key, valid ? (uint32_t)(e - p.e0) + p.rel0 : 0u);
+    wave_sync_lds();  // the tiles are rewritten by the next item
+  }
+}
+
 // ---- chunk pipeline ------------------------------------------------------
 
 __global__ void fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
@@ -662,6 +785,35 @@ hipError_t launch_rehash(int W, bool inl, const uint64_t* rows, uint64_t nrows, 
 hipError_t launch_gen(int W, int op, const GenArgs& a, bool same_level, hipStream_t s) {
   if (a.e1 <= a.e0) return hipSuccess;
   REI_DISPATCH_WI(W, a.inl, return (launch_gen_w<kW, kI>(op, a, same_level, s)));
+  return hipGetLastError();
+}
+
+hipError_t launch_gen_pieces(int W, const GenArgs& a, const PieceArgs& p, hipStream_t s) {
+  if (p.items == 0) return hipSuccess;
+  if (W > kPiecesMaxW || p.n > (uint32_t)kMaxPieces) return hipErrorInvalidValue;
+  // every table a piece reads must be there, and every range non-empty
+  if (!a.char_index || !a.gt_off || !a.gt_pair || !a.len_off || !a.st || !a.ctrl) return hipErrorInvalidValue;
+  for (uint32_t k = 0; k < p.n; ++k) {
+    const PieceD& d = p.p[k];
+    if (d.op != OP_CHAR && !a.rows) return hipErrorInvalidValue;  // (no rows yet: only characters)
+    if (d.e1 <= d.e0 || (k && d.item0 < p.p[k - 1].item0) || d.item0 >= p.items) return hipErrorInvalidValue;
+    if (d.op == OP_CONCAT && (d.rcount == 0 || d.lcount == 0 || d.nt == 0)) return hipErrorInvalidValue;
+    if ((d.op == OP_UNION && !d.same && d.rcount == 0) || (d.op != OP_CHAR && d.lcount == 0))
+      return hipErrorInvalidValue;
+  }
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((p.items + 3) / 4, 4096);
+  switch (W) {
+    case 1:
+      if (a.inl)
+        launch_timed(gen_pieces<1, true>, dim3(grid), dim3(256), 0, s, a, p);
+      else
+        launch_timed(gen_pieces<1, false>, dim3(grid), dim3(256), 0, s, a, p);
+      break;
+    case 2: launch_timed(gen_pieces<2, false>, dim3(grid), dim3(256), 0, s, a, p); break;
+    case 4: launch_timed(gen_pieces<4, false>, dim3(grid), dim3(256), 0, s, a, p); break;
+    case 8: launch_timed(gen_pieces<8, false>, dim3(grid), dim3(256), 0, s, a, p); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
