@@ -92,6 +92,8 @@ def main():
                     help="requests per serving run (0 = skip the serving measurement)")
     ap.add_argument("--sequential", action="store_true",
                     help="time rei_solve per instance as the step instead of rei_solve_batch")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the batched solver's tuning (profiling runs: every launch the same kind)")
     ap.add_argument("--no-compare", action="store_true",
                     help="do not also time the other mode (batched vs sequential)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -154,7 +156,7 @@ def main():
     for _ in range(args.warmup):
         step()
     tuned = None
-    if not args.sequential and args.warmup:
+    if not args.sequential and args.warmup and not args.no_tune:
         # launch shape of the batched solver, chosen by measurement (untimed)
         tuned = rei.tune_batch(handles, stream)
     # Python's cyclic collector scans every object torch created at import;

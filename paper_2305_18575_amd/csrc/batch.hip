@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
   __shared__ uint32_t s_nsurv, s_ans, s_rank, s_over, s_stop, s_resume;
   __shared__ uint64_t s_total;
   __shared__ uint32_t s_bm[kWords], s_pre[kWords];
-  __shared__ uint32_t s_sc[kT];
+  __shared__ uint32_t s_winners;
   __shared__ uint64_t s_tile[kWaves][64 * W];
   __shared__ uint64_t s_uni[kWaves][W];
   __shared__ uint32_t s_gto[kBatchMaxIc + 1], s_gtp[kBatchMaxPairs], s_lo[kBatchMaxIc + 2];
@@ -401,18 +401,12 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
             atomicOr(&s_bm[e >> 5], 1u << (e & 31));
         }
         __syncthreads();
-        const uint32_t v = (tid < words) ? (uint32_t)__popc(s_bm[tid]) : 0u;
-        s_sc[tid] = v;
-        __syncthreads();
-        for (uint32_t off = 1; off < kT; off <<= 1) {
-          const uint32_t x = (tid >= off) ? s_sc[tid - off] : 0u;
-          __syncthreads();
-          s_sc[tid] += x;
-          __syncthreads();
+        if (wave == 0) {
+          const uint32_t t = wave_popc_scan<kWords / 64>(s_bm, s_pre, words);
+          if (lane == 0) s_winners = t;
         }
-        if (tid < words) s_pre[tid] = s_sc[tid] - v;
-        const uint32_t winners = s_sc[kT - 1];
         __syncthreads();
+        const uint32_t winners = s_winners;
         const uint64_t total = s_total;
         const uint64_t room = d.row_cap > total ? d.row_cap - total : 0;
         const uint64_t alloc_room = d.rows_alloc > total ? d.rows_alloc - total : 0;

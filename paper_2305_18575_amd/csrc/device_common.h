@@ -228,6 +228,37 @@ __device__ __forceinline__ void filter_emit(const Probe& a, const Sink& o, bool 
   }
 }
 
+// Exclusive prefix sums of the popcounts of bm[0, words) into pre[], by one
+// wave (all 64 lanes call it; words <= 64 * kPer); returns the total.  Lane
+// l takes words l*kPer .. l*kPer + kPer - 1, so one shuffle scan over the
+// lanes replaces a workgroup-wide scan with a barrier per step.
+template <int kPer>
+__device__ __forceinline__ uint32_t wave_popc_scan(const uint32_t* bm, uint32_t* pre, uint32_t words) {
+  const uint32_t lane = lane_id();
+  uint32_t c[kPer];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const uint32_t idx = lane * kPer + k;
+    c[k] = idx < words ? (uint32_t)__popc(bm[idx]) : 0u;
+    sum += c[k];
+  }
+  uint32_t incl = sum;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t v = (uint32_t)__shfl_up((int)incl, off, kWave);
+    if ((int)lane >= off) incl += v;
+  }
+  uint32_t run = incl - sum;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const uint32_t idx = lane * kPer + k;
+    if (idx < words) pre[idx] = run;
+    run += c[k];
+  }
+  return (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+}
+
 // Orders a wave's LDS writes before its later LDS reads by other lanes.
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");

@@ -509,8 +509,7 @@ template <int W, bool kInl>
 __global__ __launch_bounds__(1024) void finalize_small(ChunkArgs a) {
   __shared__ uint32_t bm[kSmallWords];
   __shared__ uint32_t pre[kSmallWords];
-  __shared__ uint32_t sc[1024];
-  __shared__ uint32_t s_rank, s_over;
+  __shared__ uint32_t s_rank, s_over, s_total;
   if (a.st->stop) return;
   const uint32_t t = threadIdx.x;
   const uint32_t ns = a.ctrl->n_surv, ans = a.ctrl->answer_e;
@@ -527,18 +526,12 @@ __global__ __launch_bounds__(1024) void finalize_small(ChunkArgs a) {
       atomicOr(&bm[e >> 5], 1u << (e & 31));
   }
   __syncthreads();
-  const uint32_t v = (t < words) ? (uint32_t)__popc(bm[t]) : 0u;
-  sc[t] = v;
-  __syncthreads();
-  for (uint32_t off = 1; off < 1024; off <<= 1) {
-    const uint32_t x = (t >= off) ? sc[t - off] : 0u;
-    __syncthreads();
-    sc[t] += x;
-    __syncthreads();
+  if (t < 64) {
+    const uint32_t tot = wave_popc_scan<kSmallWords / 64>(bm, pre, words);
+    if (t == 0) s_total = tot;
   }
-  if (t < words) pre[t] = sc[t] - v;
-  const uint32_t total = sc[1023];
   __syncthreads();
+  const uint32_t total = s_total;
   const uint64_t row_base = a.st->total_rows;
   const uint64_t room = a.st->row_cap > row_base ? a.st->row_cap - row_base : 0;
   for (uint32_t sid = t; sid < ns; sid += 1024) {
