@@ -203,10 +203,15 @@ def main():
     bytes_per_launch = PROBE_BYTES * d["units"] / max(1, d["launches"])
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     traffic = TRAFFIC_BYTES.get((args.workload, dom)) if not args.max_errors else None
+    # the events a launch records also span its dispatch and completion; an
+    # empty kernel launched the same way shows how much (context for
+    # comparing with a kernel trace; achieved keeps the raw events)
+    overhead_us = rei.timing_overhead_us()
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
                 "algorithmic_bytes_per_launch": round(bytes_per_launch),
-                "avg_launch_us": round(avg_ms * 1e3, 3), "launches": d["launches"],
+                "avg_launch_us": round(avg_ms * 1e3, 3), "event_overhead_us": round(overhead_us, 3),
+                "launches": d["launches"],
                 "candidates_per_launch": round(d["units"] / max(1, d["launches"]), 1)}
 
     serving_out = None

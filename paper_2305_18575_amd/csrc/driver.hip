@@ -1815,6 +1815,38 @@ rei_status rei_set_profiling(rei_instance* inst, int enable) {
   return REI_OK;
 }
 
+rei_status rei_timing_overhead(double* us) {
+  if (!us) return REI_ERR_INVALID_ARG;
+  *us = 0;
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return REI_ERR_DEVICE;
+  constexpr int kRuns = 64;
+  std::vector<hipEvent_t> ev(2 * kRuns, nullptr);
+  rei_status st = REI_OK;
+  for (auto& e : ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) st = REI_ERR_DEVICE;
+  for (int k = 0; st == REI_OK && k < kRuns; ++k) {
+    g_kernel_timer = KernelTimer{ev[2 * k], ev[2 * k + 1]};
+    if (launch_noop_timed(s) != hipSuccess) st = REI_ERR_DEVICE;
+  }
+  g_kernel_timer = KernelTimer{nullptr, nullptr};
+  if (st == REI_OK && hipStreamSynchronize(s) != hipSuccess) st = REI_ERR_DEVICE;
+  std::vector<float> ms;
+  for (int k = 8; st == REI_OK && k < kRuns; ++k) {  // the first launches warm up
+    float m = 0;
+    if (hipEventElapsedTime(&m, ev[2 * k], ev[2 * k + 1]) != hipSuccess) st = REI_ERR_DEVICE;
+    ms.push_back(m);
+  }
+  if (st == REI_OK) {
+    std::sort(ms.begin(), ms.end());
+    *us = 1e3 * ms[ms.size() / 2];
+  }
+  for (auto e : ev)
+    if (e) (void)hipEventDestroy(e);
+  (void)hipStreamDestroy(s);
+  return st;
+}
+
 rei_status rei_kernel_stats(const rei_instance* inst, rei_kernel_class k, uint64_t* launches, double* ms,
                             uint64_t* units) {
   if (!inst || k < 0 || k >= REI_K_COUNT) return REI_ERR_INVALID_ARG;

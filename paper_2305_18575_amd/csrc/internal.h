@@ -167,6 +167,8 @@ hipError_t launch_finalize(int W, const ChunkArgs& a, hipStream_t s);
 // Accounting of a chunk without survivors (a level enumerated in OnTheFly
 // mode): the answer, if any, and the candidate count.
 hipError_t launch_account(const ChunkArgs& a, hipStream_t s);
+// An empty kernel through launch_timed (calibrates the timing events).
+hipError_t launch_noop_timed(hipStream_t s);
 hipError_t launch_state_reset(Ctrl* c, DevState* st, uint64_t row_cap, bool otf_on, hipStream_t s);
 constexpr uint64_t kSmallChunk = 1ull << 14;   // candidates finalized by one workgroup
 

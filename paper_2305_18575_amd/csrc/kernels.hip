@@ -837,6 +837,15 @@ hipError_t launch_finalize(int W, const ChunkArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+namespace {
+__global__ void noop_kernel() {}
+}
+
+hipError_t launch_noop_timed(hipStream_t s) {
+  launch_timed(noop_kernel, dim3(1), dim3(64), 0, s);
+  return hipGetLastError();
+}
+
 hipError_t launch_account(const ChunkArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(account_large, dim3(1), dim3(1), 0, s, a);
   return hipGetLastError();

@@ -501,3 +501,8 @@ def test_kernel_statistics(rei):
     assert stats2["insert_survivors"][0] > 0 and stats2["compact_winners"][0] > 0
     assert sum(stats2[c][2] for c in classes if c.startswith("gen_")) == gen_units
     h.close()
+
+
+def test_timing_overhead_is_measured(rei):
+    us = rei.timing_overhead_us()
+    assert 0.0 < us < 1000.0
