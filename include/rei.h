@@ -266,7 +266,7 @@ rei_status rei_set_profiling(rei_instance *inst, int enable);
  * accumulated over the solves since profiling was enabled. */
 rei_status rei_kernel_stats(const rei_instance *inst, rei_kernel_class k, uint64_t *launches,
                             double *ms, uint64_t *units);
-/* Median time the timing events read for an empty kernel launched the same
+/* Shortest time the timing events read for an empty kernel launched the same
  * way (the events a launch records include the dispatch and completion of
  * the launch, which an external kernel trace leaves out), in microseconds.
  * Creates and destroys a stream of its own.  For reading the statistics. */

@@ -143,8 +143,8 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // The dedup table starts small and grows (cleared and rebuilt from the
   // stored rows) while rows accumulate, up to the arena's slot_mask: a
-  // small instance clears a few hundred KB instead of its whole arena.
-  uint64_t tmask = min(d.slot_mask, (uint64_t)(4 * kBatchChunk) - 1);
+  // small instance clears a few KB instead of its whole arena.
+  uint64_t tmask = min(d.slot_mask, (uint64_t)1023);
   Probe probe{d.rows, d.slots, tmask, d.pmask, d.nmask, d.max_err};
   const Sink sink{d.skey, d.se, &s_nsurv, &s_ans};
 
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
         const uint64_t total = s_total;
         if (2 * (total + len) > tmask + 1) {
           uint64_t cap = tmask + 1;
-          while (cap < 4 * (total + kBatchChunk) && cap <= d.slot_mask) cap *= 2;
+          while (cap < 4 * (total + len) && cap <= d.slot_mask) cap *= 2;
           tmask = min(d.slot_mask, cap - 1);
           for (uint64_t i = tid; i <= tmask; i += kT) {
             d.slots[i] = kEmpty;
