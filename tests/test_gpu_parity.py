@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 
 def run_both(rei, alphabet, pos, neg, costs=(1, 1, 1, 1, 1), max_cost=30, cache_bytes=1 << 30,
-             max_errors=0, chunk=0, rows=False):
+             max_errors=0, chunk=0, rows=False, row_limit=None):
     print(f"\ncase: sigma={alphabet} |P|={len(pos)} |N|={len(neg)} costs={costs} "
           f"max_cost={max_cost} cache={cache_bytes} err={max_errors} chunk={chunk}", flush=True)
     inst = rei.Instance(alphabet, pos, neg, costs, max_cost, cache_bytes)
@@ -35,7 +35,7 @@ def run_both(rei, alphabet, pos, neg, costs=(1, 1, 1, 1, 1), max_cost=30, cache_
         assert g.unique_at(c) == o.unique[c], (c, g.unique, o.unique)
         assert g.candidates_at(c) == o.candidates[c], (c, g.candidates, o.candidates)
     if rows:
-        compare_rows(inst, o_inst, g)
+        compare_rows(inst, o_inst, g, row_limit)
     inst.close()
     return g, o
 
@@ -91,6 +91,18 @@ def test_large_config_partial(rei):
     for seed in (0, 1):
         inst = instances.large_instance(seed)
         run_both(rei, inst.alphabet, inst.pos, inst.neg, inst.costs, 8, rows=True)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_large_config_full_size(rei, seed):
+    """The large configuration at its full size: ternary alphabet, 20+20
+    strings of length 0..10, 474-700 infixes (8-16 words per language),
+    searched to the target's cost with a 64 GB cache, as bench.py's large
+    instances run; all counts and the answer exact, and up to 64 rows of
+    every level compared bit by bit."""
+    inst = instances.large_instance(seed)
+    run_both(rei, inst.alphabet, inst.pos, inst.neg, inst.costs, inst.max_cost, 64 << 30,
+             rows=True, row_limit=64)
 
 
 @pytest.mark.parametrize("chunk", [1, 7, 64, 1000])
