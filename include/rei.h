@@ -266,6 +266,12 @@ rei_status rei_set_profiling(rei_instance *inst, int enable);
  * accumulated over the solves since profiling was enabled. */
 rei_status rei_kernel_stats(const rei_instance *inst, rei_kernel_class k, uint64_t *launches,
                             double *ms, uint64_t *units);
+/* Testing: keep only the low `bits` bits of every language hash (0 = all 64)
+ * on the current device.  Forces table collisions, equal fingerprints (so
+ * every probe compares whole languages) and long probe sequences; results
+ * do not change, searches get slower.  Process-wide: call only while no
+ * search runs. */
+rei_status rei_set_hash_bits(uint32_t bits);
 /* Shortest time the timing events read for an empty kernel launched the same
  * way (the events a launch records include the dispatch and completion of
  * the launch, which an external kernel trace leaves out), in microseconds.

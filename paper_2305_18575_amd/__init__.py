@@ -30,7 +30,7 @@ EXPORTS = ["rei_create", "rei_solve", "rei_solve_batch", "rei_tune_batch", "rei_
            "rei_server_poll", "rei_server_destroy", "rei_trim", "rei_destroy", "rei_status_str", "rei_last_error",
            "rei_create_error", "rei_ic_word", "rei_level_size", "rei_row_bits",
            "rei_row_regex", "rei_set_chunk", "rei_set_batch_level", "rei_set_on_the_fly", "rei_set_char_costs", "rei_set_max_errors", "rei_set_profiling",
-           "rei_kernel_stats", "rei_timing_overhead", "rei_kernel_name"]
+           "rei_kernel_stats", "rei_timing_overhead", "rei_set_hash_bits", "rei_kernel_name"]
 
 
 class ReiError(RuntimeError):
@@ -130,6 +130,8 @@ def load_library():
     lib.rei_kernel_stats.restype = ctypes.c_int
     lib.rei_kernel_stats.argtypes = [vp, ctypes.c_int, ctypes.POINTER(u64),
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64)]
+    lib.rei_set_hash_bits.restype = ctypes.c_int
+    lib.rei_set_hash_bits.argtypes = [u32]
     lib.rei_timing_overhead.restype = ctypes.c_int
     lib.rei_timing_overhead.argtypes = [ctypes.POINTER(ctypes.c_double)]
     lib.rei_kernel_name.restype = cp
@@ -320,6 +322,13 @@ def tune_batch(instances: Sequence["Instance"], stream: Optional[int] = -1,
     names = ["W1-inline", "W1", "W2", "W4", "W8"]
     shape = {names[k]: int(out[k]) for k in range(5) if out[k]}
     return {"threads_per_instance": shape, "level_max": int(lm.value)}
+
+
+def set_hash_bits(bits: int):
+    """``rei_set_hash_bits`` (testing): keep only the low bits of the hash."""
+    st = load_library().rei_set_hash_bits(int(bits))
+    if st != 0:
+        raise ReiError(st, "rei_set_hash_bits")
 
 
 def timing_overhead_us() -> float:

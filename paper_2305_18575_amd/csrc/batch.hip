@@ -541,6 +541,10 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
 
 }  // namespace
 
+hipError_t set_hash_mask_batch(uint64_t mask) {
+  return hipMemcpyToSymbol(HIP_SYMBOL(g_hash_mask), &mask, sizeof(mask));
+}
+
 hipError_t launch_solve_batch(int W, bool inl, uint32_t threads, const BatchDesc* d_descs, uint32_t n,
                               hipStream_t s) {
   if (n == 0) return hipSuccess;

@@ -19,12 +19,17 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
   return x;
 }
 
+// Bits of the language hash that are kept: all, unless a test narrows them
+// to force collisions, equal fingerprints and long probe sequences (results
+// must not change).  Each translation unit has its own copy (set_hash_mask).
+__device__ uint64_t g_hash_mask = ~0ull;
+
 template <int W>
 __device__ __forceinline__ uint64_t hash_key(const uint64_t (&k)[W]) {
   uint64_t h = mix64(k[0] ^ 0x9e3779b97f4a7c15ull);
 #pragma unroll
   for (int i = 1; i < W; ++i) h = mix64(h ^ k[i]);
-  return h;
+  return h & g_hash_mask;
 }
 
 __device__ __forceinline__ uint64_t fingerprint(uint64_t h) { return (h >> 40) & 0xFFFFFFull; }

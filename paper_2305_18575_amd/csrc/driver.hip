@@ -1815,6 +1815,12 @@ rei_status rei_set_profiling(rei_instance* inst, int enable) {
   return REI_OK;
 }
 
+rei_status rei_set_hash_bits(uint32_t bits) {
+  const uint64_t mask = (bits == 0 || bits >= 64) ? ~0ull : ((1ull << bits) - 1);
+  if (set_hash_mask_kernels(mask) != hipSuccess || set_hash_mask_batch(mask) != hipSuccess) return REI_ERR_DEVICE;
+  return REI_OK;
+}
+
 rei_status rei_timing_overhead(double* us) {
   if (!us) return REI_ERR_INVALID_ARG;
   *us = 0;

@@ -174,6 +174,10 @@ constexpr uint64_t kSmallChunk = 1ull << 14;   // candidates finalized by one wo
 
 const char* gen_kernel_name(int op);
 
+// The hash bits kept by the kernels of kernels.hip and of batch.hip.
+hipError_t set_hash_mask_kernels(uint64_t mask);
+hipError_t set_hash_mask_batch(uint64_t mask);
+
 // Many small pieces of one chunk in one launch (gen_pieces): each wave takes
 // one item of 64 candidates of one piece.  Items: CHAR, QUESTION, STAR,
 // UNION: 64 consecutive candidates; CONCAT: one left row and a tile of 64

@@ -841,6 +841,10 @@ namespace {
 __global__ void noop_kernel() {}
 }
 
+hipError_t set_hash_mask_kernels(uint64_t mask) {
+  return hipMemcpyToSymbol(HIP_SYMBOL(g_hash_mask), &mask, sizeof(mask));
+}
+
 hipError_t launch_noop_timed(hipStream_t s) {
   launch_timed(noop_kernel, dim3(1), dim3(64), 0, s);
   return hipGetLastError();

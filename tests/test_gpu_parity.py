@@ -518,3 +518,28 @@ def test_kernel_statistics(rei):
 def test_timing_overhead_is_measured(rei):
     us = rei.timing_overhead_us()
     assert 0.0 < us < 1000.0
+
+
+@pytest.mark.parametrize("bits", [6, 12])
+def test_weak_hash_gives_identical_results(rei, bits):
+    """With only the low bits of the hash kept, languages collide in the
+    table, every fingerprint is equal (each probe compares whole languages)
+    and probe sequences grow long; the results still equal the oracle's on
+    the per-chunk path, in the batched solver and with OnTheFly mode."""
+    rei.set_hash_bits(bits)
+    try:
+        print(f"\nhash bits {bits}", flush=True)
+        for seed in range(0, 200, 25):
+            inst = instances.plain_instance(seed)
+            run_both(rei, inst.alphabet, inst.pos, inst.neg, inst.costs, inst.max_cost, chunk=50)
+        if bits >= 12:  # 124 K rows: with 64 start positions the probes would walk them all
+            inst = instances.single_instance(6, (1, 1, 1, 1, 1))
+            run_both(rei, inst.alphabet, inst.pos, inst.neg, inst.costs, inst.max_cost, rows=True, row_limit=32)
+        specs = batch_specs()[:40]
+        hs = [rei.Instance(a, p, n, c, m) for (a, p, n, c, m) in specs]
+        for r, spec in zip(rei.solve_batch(hs), specs):
+            check_against_oracle(r, spec)
+        for h in hs:
+            h.close()
+    finally:
+        rei.set_hash_bits(0)
