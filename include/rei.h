@@ -154,8 +154,9 @@ rei_status rei_tune_batch(rei_instance *const *insts, size_t n, void *hip_stream
  * requests that can be batched (as in rei_solve_batch) are launched together
  * on a free stream from a pool of n_streams, so requests arriving while others
  * run are started at once and their work overlaps on the device; the others
- * (and batched ones that outgrow their preallocated rows) run rei_solve's path
- * on one of n_workers worker threads, each with its own stream.  Each result
+ * (and batched ones that hand off or outgrow their preallocated rows) run
+ * rei_solve's path on one of n_workers worker threads, each with its own
+ * stream (0 = defaults: 64 per batch, 4 streams, 4 workers).  Each result
  * equals rei_solve's for that instance.  The budget counts the device bytes
  * of requests in flight (an estimate made at submit: the batched arena, or
  * the cache budget plus its table for the per-chunk path); a finished

@@ -345,7 +345,7 @@ class Server:
     """Continuous-batching server (``rei_server_*``): submit staged instances,
     poll or wait for their results."""
 
-    def __init__(self, hbm_budget: int, max_batch: int = 64, n_streams: int = 4, n_workers: int = 2):
+    def __init__(self, hbm_budget: int, max_batch: int = 64, n_streams: int = 4, n_workers: int = 4):
         lib = load_library()
         self._lib = lib
         h = ctypes.c_void_p()

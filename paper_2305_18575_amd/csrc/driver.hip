@@ -2076,7 +2076,7 @@ rei_status rei_server_create(uint64_t hbm_budget, uint32_t max_batch, uint32_t n
     sv->streams.push_back(s);
     sv->stream_busy.push_back(false);
   }
-  const uint32_t nw = n_workers ? n_workers : 2;
+  const uint32_t nw = n_workers ? n_workers : 4;
   for (uint32_t k = 0; k < nw; ++k) {
     hipStream_t s;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) break;

@@ -53,7 +53,7 @@ def percentiles(lat: Sequence[float]):
 
 
 def run_served(rei, handles, arrivals, budget: int, max_batch: int = 64, n_streams: int = 4,
-               n_workers: int = 2):
+               n_workers: int = 4):
     """Submits handles[i] at arrivals[i] seconds; returns results, latencies and
     instances per second (requests / time from first arrival to last completion)."""
     srv = rei.Server(budget, max_batch, n_streams, n_workers)
