@@ -172,7 +172,6 @@ hipError_t launch_noop_timed(hipStream_t s);
 hipError_t launch_state_reset(Ctrl* c, DevState* st, uint64_t row_cap, bool otf_on, hipStream_t s);
 constexpr uint64_t kSmallChunk = 1ull << 14;   // candidates finalized by one workgroup
 
-const char* gen_kernel_name(int op);
 
 // The hash bits kept by the kernels of kernels.hip and of batch.hip.
 hipError_t set_hash_mask_kernels(uint64_t mask);

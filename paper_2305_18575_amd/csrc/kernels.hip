@@ -1,7 +1,7 @@
 // Device kernels of the REI search for CDNA4 (gfx950), wave64.
 //
-// One chunk of candidates (a contiguous range of enumeration indices inside
-// one constructor block of a cost level) goes through:
+// One chunk of candidates (a contiguous range of level indices, spanning one
+// or more constructor blocks of a cost level) goes through:
 //   gen_*     build each candidate's language (characteristic sequence over
 //             ic, W 64-bit words) and probe the dedup table read-only; a
 //             candidate whose language is not yet stored is a survivor and
@@ -15,8 +15,8 @@
 //   scan      exclusive prefix of the bitmap popcounts = rank of each winner
 //             in enumeration order;
 //   compact   winners before the answer are appended to the level in rank
-//             order ("new languages go to temporary storage, only unique
-//             ones are copied into the cache", Sec. 3, GPU language cache).
+//             order (new languages wait in temporary storage and only the
+//             unique ones enter the cache: Sec. 3, GPU language cache).
 #include <algorithm>
 
 #include "device_common.h"
@@ -855,15 +855,5 @@ hipError_t launch_account(const ChunkArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-const char* gen_kernel_name(int op) {
-  switch (op) {
-    case OP_CHAR: return "gen_char";
-    case OP_QUESTION: return "gen_question";
-    case OP_STAR: return "gen_star";
-    case OP_CONCAT: return "gen_concat";
-    case OP_UNION: return "gen_union";
-  }
-  return "?";
-}
 
 }  // namespace rei
