@@ -185,6 +185,20 @@ void rei_server_destroy(rei_server *srv);
  * device.  For callers that solve many large instances in turn. */
 rei_status rei_trim(rei_instance *inst);
 
+/* Route the device memory of instances created from now on through the
+ * caller's allocator, for a framework that owns the device memory (a caching
+ * allocator, say) and hands it out.  alloc(bytes,
+ * ctx) returns device memory of the current device or NULL on failure (the
+ * call then fails with REI_ERR_DEVICE); free_(ptr, ctx) takes back a pointer
+ * alloc returned.  An instance keeps the pair it was created with for all its
+ * allocations and frees, so the pair and ctx must stay valid until every such
+ * instance is destroyed.  The library drains the device after each alloc and
+ * before each free_, so the allocator may reuse memory in the order of any
+ * stream.  Both NULL restores hipMalloc / hipFree; exactly one NULL is
+ * REI_ERR_INVALID_ARG.  Process-wide; thread-safe. */
+rei_status rei_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
+                             void (*free_)(void *ptr, void *ctx), void *ctx);
+
 /* Free the instance and its device memory.  NULL is ignored. */
 void rei_destroy(rei_instance *inst);
 

@@ -13,7 +13,7 @@ from __future__ import annotations
 import ctypes
 import os
 from dataclasses import dataclass
-from typing import List, Optional, Sequence
+from typing import Callable, List, Optional, Sequence
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librei.so")
@@ -27,7 +27,7 @@ KERNEL_CLASSES = ["gen_char", "gen_question", "gen_star", "gen_concat", "gen_uni
 
 # exported symbols, as declared in include/rei.h
 EXPORTS = ["rei_create", "rei_solve", "rei_solve_batch", "rei_tune_batch", "rei_server_create", "rei_server_submit",
-           "rei_server_poll", "rei_server_destroy", "rei_trim", "rei_destroy", "rei_status_str", "rei_last_error",
+           "rei_server_poll", "rei_server_destroy", "rei_set_allocator", "rei_trim", "rei_destroy", "rei_status_str", "rei_last_error",
            "rei_create_error", "rei_ic_word", "rei_level_size", "rei_row_bits",
            "rei_row_regex", "rei_set_chunk", "rei_set_batch_level", "rei_set_on_the_fly", "rei_set_char_costs", "rei_set_max_errors", "rei_set_profiling",
            "rei_kernel_stats", "rei_timing_overhead", "rei_set_hash_bits", "rei_kernel_name"]
@@ -135,6 +135,8 @@ def load_library():
     lib.rei_timing_overhead.restype = ctypes.c_int
     lib.rei_timing_overhead.argtypes = [ctypes.POINTER(ctypes.c_double)]
     lib.rei_kernel_name.restype = cp
+    lib.rei_set_allocator.restype = ctypes.c_int
+    lib.rei_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, vp]
     lib.rei_kernel_name.argtypes = [ctypes.c_int]
     _lib = lib
     return lib
@@ -322,6 +324,49 @@ def tune_batch(instances: Sequence["Instance"], stream: Optional[int] = -1,
     names = ["W1-inline", "W1", "W2", "W4", "W8"]
     shape = {names[k]: int(out[k]) for k in range(5) if out[k]}
     return {"threads_per_instance": shape, "level_max": int(lm.value)}
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_allocator_refs = []  # every pair ever registered: instances keep theirs until destroyed
+
+
+def set_allocator(alloc: Optional[Callable[[int], int]], free: Optional[Callable[[int], None]]):
+    """``rei_set_allocator``: instances created from now on take their device
+    memory from ``alloc(bytes) -> address`` (0 on failure) and give it back
+    with ``free(address)``; ``None, None`` restores hipMalloc / hipFree."""
+    lib = load_library()
+    if alloc is None and free is None:
+        st = lib.rei_set_allocator(_ALLOC_FN(), _FREE_FN(), None)
+    elif alloc is None or free is None:
+        raise ValueError("set_allocator needs both functions or neither")
+    else:
+        def c_alloc(nbytes, _ctx):
+            try:
+                return int(alloc(int(nbytes))) or None
+            except Exception:  # an exception cannot cross the C boundary: report failure
+                return None
+
+        def c_free(ptr, _ctx):
+            try:
+                free(int(ptr))
+            except Exception:
+                pass
+
+        pair = (_ALLOC_FN(c_alloc), _FREE_FN(c_free))
+        _allocator_refs.append(pair)
+        st = lib.rei_set_allocator(pair[0], pair[1], None)
+    if st != 0:
+        raise ReiError(st, "rei_set_allocator")
+
+
+def use_torch_allocator(device: Optional[int] = None):
+    """Route the device memory of new instances through torch's caching
+    allocator on ``device`` (default: the current device)."""
+    import torch
+    dev = torch.cuda.current_device() if device is None else int(device)
+    set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n, dev),
+                  torch.cuda.caching_allocator_delete)
 
 
 def set_hash_bits(bits: int):

@@ -38,6 +38,16 @@ struct Block {
   bool same;         // union of a level with itself (pairs x before y)
 };
 
+// Device memory of an instance: hipMalloc / hipFree, or the caller's pair
+// (rei_set_allocator) captured when the instance is created.
+struct DevAlloc {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*free_)(void*, void*) = nullptr;
+  void* ctx = nullptr;
+};
+std::mutex g_alloc_mu;
+DevAlloc g_alloc;
+
 struct ProfRec {
   int k;
   hipEvent_t a, b;
@@ -60,6 +70,7 @@ struct rei_instance {
   uint64_t chunk_max = kDefaultChunk;
   uint64_t batch_level_max = 0;  // 0: the tuned value, else kBatchLevelMax
   int device = 0;
+  DevAlloc alloc;  // how this instance's device memory is obtained and released
   double seconds_stage = 0;
 
   // staged tables on the device
@@ -152,9 +163,30 @@ namespace {
     }                                                                                  \
   } while (0)
 
+// A caller's allocator may order its reuse of memory by some stream of its
+// own, which the library's streams do not follow: the device is drained after
+// taking memory from it and before handing memory back, as hipMalloc and
+// hipFree would do by themselves.
 template <class T>
-void dfree(T*& p) {
-  if (p) (void)hipFree(p);
+hipError_t dev_alloc(const rei_instance* in, T** p, size_t bytes) {
+  if (in->alloc.alloc) {
+    *p = (T*)in->alloc.alloc(bytes, in->alloc.ctx);
+    if (!*p) return hipErrorOutOfMemory;
+    return hipDeviceSynchronize();
+  }
+  return hipMalloc(p, bytes);
+}
+
+template <class T>
+void dfree(const rei_instance* in, T*& p) {
+  if (p) {
+    if (in->alloc.free_) {
+      (void)hipDeviceSynchronize();
+      in->alloc.free_((void*)p, in->alloc.ctx);
+    } else {
+      (void)hipFree(p);
+    }
+  }
   p = nullptr;
 }
 
@@ -244,9 +276,9 @@ rei_status ensure_rows(rei_instance* in, uint64_t need, hipStream_t s) {
   const int W = in->st.W;
   uint64_t* nr = nullptr;
   uint64_t* na = nullptr;
-  HIP_OK(in, hipMalloc(&nr, cap * W * 8));
-  if (hipMalloc(&na, cap * 8) != hipSuccess) {
-    (void)hipFree(nr);
+  HIP_OK(in, dev_alloc(in, &nr, cap * W * 8));
+  if (dev_alloc(in, &na, cap * 8) != hipSuccess) {
+    dfree(in, nr);
     in->err = "hipMalloc of the back-pointer array failed";
     return REI_ERR_DEVICE;
   }
@@ -255,8 +287,8 @@ rei_status ensure_rows(rei_instance* in, uint64_t need, hipStream_t s) {
     HIP_OK(in, hipMemcpyAsync(na, in->d_aux, in->known_rows * 8, hipMemcpyDeviceToDevice, s));
   }
   HIP_OK(in, hipStreamSynchronize(s));
-  dfree(in->d_rows);
-  dfree(in->d_aux);
+  dfree(in, in->d_rows);
+  dfree(in, in->d_aux);
   in->d_rows = nr;
   in->d_aux = na;
   in->rows_alloc = cap;
@@ -269,11 +301,11 @@ rei_status ensure_table(rei_instance* in, uint64_t entries, hipStream_t s, bool 
   uint64_t cap = std::max<uint64_t>(4096, pow2_at_least(4 * entries));
   if (force && in->slots_cap >= cap) cap = in->slots_cap;
   if (cap != in->slots_cap) {
-    dfree(in->d_slots);
-    dfree(in->d_sref);
+    dfree(in, in->d_slots);
+    dfree(in, in->d_sref);
     in->slots_cap = 0;
-    HIP_OK(in, hipMalloc(&in->d_slots, cap * 8));
-    if (in->inl) HIP_OK(in, hipMalloc(&in->d_sref, cap * 8));
+    HIP_OK(in, dev_alloc(in, &in->d_slots, cap * 8));
+    if (in->inl) HIP_OK(in, dev_alloc(in, &in->d_sref, cap * 8));
     in->slots_cap = cap;
   }
   LAUNCH(in, s, REI_K_OTHER, cap, launch_fill(in->d_slots, cap, kEmpty, s));
@@ -286,22 +318,22 @@ rei_status ensure_table(rei_instance* in, uint64_t entries, hipStream_t s, bool 
 rei_status ensure_chunk_buffers(rei_instance* in, uint64_t len) {
   const int W = in->st.W;
   if (len > in->surv_cap) {
-    dfree(in->d_skey);
-    dfree(in->d_se);
-    dfree(in->d_spos);
-    HIP_OK(in, hipMalloc(&in->d_skey, len * W * 8));
-    HIP_OK(in, hipMalloc(&in->d_se, len * 4));
-    HIP_OK(in, hipMalloc(&in->d_spos, len * 8));
+    dfree(in, in->d_skey);
+    dfree(in, in->d_se);
+    dfree(in, in->d_spos);
+    HIP_OK(in, dev_alloc(in, &in->d_skey, len * W * 8));
+    HIP_OK(in, dev_alloc(in, &in->d_se, len * 4));
+    HIP_OK(in, dev_alloc(in, &in->d_spos, len * 8));
     in->surv_cap = len;
   }
   const uint64_t words = (len + 31) / 32;
   if (words > in->bitmap_cap) {
-    dfree(in->d_bitmap);
-    dfree(in->d_prefix);
-    dfree(in->d_bsums);
-    HIP_OK(in, hipMalloc(&in->d_bitmap, words * 4));
-    HIP_OK(in, hipMalloc(&in->d_prefix, words * 4));
-    HIP_OK(in, hipMalloc(&in->d_bsums, ((words + 1023) / 1024 + 1) * 4));
+    dfree(in, in->d_bitmap);
+    dfree(in, in->d_prefix);
+    dfree(in, in->d_bsums);
+    HIP_OK(in, dev_alloc(in, &in->d_bitmap, words * 4));
+    HIP_OK(in, dev_alloc(in, &in->d_prefix, words * 4));
+    HIP_OK(in, dev_alloc(in, &in->d_bsums, ((words + 1023) / 1024 + 1) * 4));
     in->bitmap_cap = words;
   }
   return REI_OK;
@@ -1374,16 +1406,16 @@ class GridPool {
 // tables and the result stay).
 void free_search_buffers(rei_instance* in) {
   (void)hipSetDevice(in->device);
-  dfree(in->d_rows);
-  dfree(in->d_aux);
-  dfree(in->d_slots);
-  dfree(in->d_sref);
-  dfree(in->d_skey);
-  dfree(in->d_se);
-  dfree(in->d_spos);
-  dfree(in->d_bitmap);
-  dfree(in->d_prefix);
-  dfree(in->d_bsums);
+  dfree(in, in->d_rows);
+  dfree(in, in->d_aux);
+  dfree(in, in->d_slots);
+  dfree(in, in->d_sref);
+  dfree(in, in->d_skey);
+  dfree(in, in->d_se);
+  dfree(in, in->d_spos);
+  dfree(in, in->d_bitmap);
+  dfree(in, in->d_prefix);
+  dfree(in, in->d_bsums);
   in->rows_alloc = 0;
   in->slots_cap = 0;
   in->surv_cap = 0;
@@ -1394,25 +1426,25 @@ void free_search_buffers(rei_instance* in) {
 
 void free_device(rei_instance* in) {
   (void)hipSetDevice(in->device);
-  dfree(in->d_gt_off);
-  dfree(in->d_gt_pair);
-  dfree(in->d_len_off);
-  dfree(in->d_pmask);
-  dfree(in->d_nmask);
-  dfree(in->d_char_index);
-  dfree(in->d_rows);
-  dfree(in->d_aux);
-  dfree(in->d_slots);
-  dfree(in->d_sref);
-  dfree(in->d_skey);
-  dfree(in->d_se);
-  dfree(in->d_spos);
-  dfree(in->d_bitmap);
-  dfree(in->d_prefix);
-  dfree(in->d_bsums);
-  dfree(in->d_ctrl);
-  dfree(in->d_state);
-  dfree(in->d_levels);
+  dfree(in, in->d_gt_off);
+  dfree(in, in->d_gt_pair);
+  dfree(in, in->d_len_off);
+  dfree(in, in->d_pmask);
+  dfree(in, in->d_nmask);
+  dfree(in, in->d_char_index);
+  dfree(in, in->d_rows);
+  dfree(in, in->d_aux);
+  dfree(in, in->d_slots);
+  dfree(in, in->d_sref);
+  dfree(in, in->d_skey);
+  dfree(in, in->d_se);
+  dfree(in, in->d_spos);
+  dfree(in, in->d_bitmap);
+  dfree(in, in->d_prefix);
+  dfree(in, in->d_bsums);
+  dfree(in, in->d_ctrl);
+  dfree(in, in->d_state);
+  dfree(in, in->d_levels);
   if (in->h_state) (void)hipHostFree(in->h_state);
   if (in->h_levels) (void)hipHostFree(in->h_levels);
   if (in->h_tree) (void)hipHostFree(in->h_tree);
@@ -1431,7 +1463,7 @@ void free_device(rei_instance* in) {
 template <class T>
 rei_status upload(rei_instance* in, T** dst, const std::vector<T>& src) {
   const size_t bytes = std::max<size_t>(1, src.size()) * sizeof(T);
-  HIP_OK(in, hipMalloc(dst, bytes));
+  HIP_OK(in, dev_alloc(in, dst, bytes));
   if (!src.empty()) HIP_OK(in, hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
   return REI_OK;
 }
@@ -1447,10 +1479,10 @@ rei_status create_device(rei_instance* in) {
   in->char_order.resize(in->st.sigma.size());
   for (uint32_t a = 0; a < in->char_order.size(); ++a) in->char_order[a] = a;
   if ((r = upload(in, &in->d_char_index, in->st.char_index)) != REI_OK) return r;
-  HIP_OK(in, hipMalloc(&in->d_ctrl, sizeof(Ctrl)));
-  HIP_OK(in, hipMalloc(&in->d_state, sizeof(DevState)));
+  HIP_OK(in, dev_alloc(in, &in->d_ctrl, sizeof(Ctrl)));
+  HIP_OK(in, dev_alloc(in, &in->d_state, sizeof(DevState)));
   const uint64_t L = in->max_cost + 2;
-  HIP_OK(in, hipMalloc(&in->d_levels, 3 * L * 8));
+  HIP_OK(in, dev_alloc(in, &in->d_levels, 3 * L * 8));
   // coherent (fine-grained): the batched solver's completion flag is read
   // by the host while the launch still runs
   const unsigned fl = hipHostMallocMapped | hipHostMallocPortable | hipHostMallocCoherent;
@@ -1489,6 +1521,10 @@ rei_status rei_create(const char* alphabet, const char* const* pos, size_t n_pos
   }
   rei_instance* in = new (std::nothrow) rei_instance();
   if (!in) return REI_ERR_HOST_ALLOC;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    in->alloc = g_alloc;
+  }
   rei_status st;
   try {
     st = stage(alphabet, pos, n_pos, neg, n_neg, &in->st, &g_create_error);
@@ -1756,6 +1792,15 @@ rei_status rei_set_chunk(rei_instance* inst, uint64_t max_candidates) {
 rei_status rei_set_batch_level(rei_instance* inst, uint64_t max_candidates) {
   if (!inst) return REI_ERR_INVALID_ARG;
   inst->batch_level_max = max_candidates;
+  return REI_OK;
+}
+
+rei_status rei_set_allocator(void* (*alloc)(size_t, void*), void (*free_)(void*, void*), void* ctx) {
+  if ((alloc == nullptr) != (free_ == nullptr)) return REI_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc.alloc = alloc;
+  g_alloc.free_ = free_;
+  g_alloc.ctx = alloc ? ctx : nullptr;
   return REI_OK;
 }
 

@@ -65,3 +65,16 @@ def test_row_cap_formula_matches_header():
     assert instances.row_cap(1 << 20, 65) == (1 << 20) // 24
     assert instances.row_cap(1 << 20, 200) == (1 << 20) // 40
     assert instances.row_cap(1 << 20, 2048) == (1 << 20) // 264
+
+
+def test_set_allocator_argument_checks():
+    """rei_set_allocator takes both functions or neither; it touches no device."""
+    lib = rei.load_library()
+    alloc = rei._ALLOC_FN(lambda n, ctx: None)
+    free = rei._FREE_FN(lambda p, ctx: None)
+    assert lib.rei_set_allocator(alloc, rei._FREE_FN(), None) == -1
+    assert lib.rei_set_allocator(rei._ALLOC_FN(), free, None) == -1
+    assert lib.rei_set_allocator(alloc, free, None) == 0
+    assert lib.rei_set_allocator(rei._ALLOC_FN(), rei._FREE_FN(), None) == 0
+    with pytest.raises(ValueError):
+        rei.set_allocator(None, lambda p: None)

@@ -543,3 +543,47 @@ def test_weak_hash_gives_identical_results(rei, bits):
             h.close()
     finally:
         rei.set_hash_bits(0)
+
+
+def test_caller_allocator_gives_identical_results(rei):
+    """rei_set_allocator: with device memory from torch's caching allocator the
+    per-chunk path, a batch and its hand-offs (allocating from worker threads)
+    give the results of hipMalloc'd memory, and every allocation comes back."""
+    import torch
+    specs = batch_specs()[::4]
+    key = lambda r: (r.status, r.cost, r.regex, r.unique, r.candidates)
+
+    def run():
+        hs = [rei.Instance(a, p, n, c, m) for (a, p, n, c, m) in specs]
+        single = [key(h.solve()) for h in hs]
+        for h in hs:
+            h.set_batch_level(300)
+        batch = [key(r) for r in rei.solve_batch(hs)]
+        for h in hs:
+            h.close()
+        return single, batch
+
+    ref = run()
+    live, calls = {}, [0, 0]
+
+    def alloc(n):
+        p = torch.cuda.caching_allocator_alloc(n, 0)
+        calls[0] += 1
+        live[p] = n
+        return p
+
+    def free(p):
+        calls[1] += 1
+        del live[p]
+        torch.cuda.caching_allocator_delete(p)
+
+    print(f"\n{len(specs)} instances, torch caching allocator", flush=True)
+    rei.set_allocator(alloc, free)
+    try:
+        got = run()
+    finally:
+        rei.set_allocator(None, None)
+    assert got == ref
+    assert calls[0] > len(specs) and calls[0] == calls[1] and not live
+    with pytest.raises(ValueError):
+        rei.set_allocator(alloc, None)
