@@ -112,7 +112,9 @@ rei_status rei_solve(rei_instance *inst, void *hip_stream, rei_result *out);
  * by side), one workgroup per instance executing the whole level loop on the
  * device (no host round trip per level or chunk; the answer's expression
  * tree is decoded there too).  An instance whose next level has more
- * candidates than the hand-off size (rei_set_batch_level; 2^16 by default)
+ * candidates than the hand-off size (rei_set_batch_level; 2^16 by default),
+ * or more than 4096 after its workgroup has run for the hand-off time
+ * (rei_set_batch_time; 500 us by default),
  * continues from that level on rei_solve's path with its lower levels kept;
  * one that outgrows its preallocated rows starts again there; the others
  * run there from the start.  Up to 8 such instances run at once, each on
@@ -123,7 +125,9 @@ rei_status rei_solve(rei_instance *inst, void *hip_stream, rei_result *out);
  *                back-pointers and table (0 = 16 MiB); capped by the
  *                instance's cache budget.
  *   out          n results; out[i] belongs to insts[i] (owned by it, as for
- *                rei_solve).  seconds_solve is the wall time of the call.
+ *                rei_solve).  seconds_solve is the time from the start
+ *                of the call until that result was known (the launch's
+ *                completion flag, or the end of its per-chunk levels).
  * Returns REI_OK when every instance was searched (each out[i].status tells
  * its outcome), or the first error. */
 rei_status rei_solve_batch(rei_instance *const *insts, size_t n, void *hip_stream, uint64_t arena_bytes,
@@ -231,6 +235,13 @@ rei_status rei_set_chunk(rei_instance *inst, uint64_t max_candidates);
  * with every lower level kept, continues on rei_solve's path.  Results do not
  * depend on it. */
 rei_status rei_set_batch_level(rei_instance *inst, uint64_t max_candidates);
+/* Hand-off time of rei_solve_batch: once the instance's workgroup has run
+ * this many microseconds, its next level moves to rei_solve's path if it has
+ * more than 4096 candidates, so that the deep searches of a batch use the
+ * device beside the workgroups of the others.  -1 = the default (500), 0 =
+ * never on time (only rei_set_batch_level's size).  The hand-off level then
+ * depends on timing; results do not. */
+rei_status rei_set_batch_time(rei_instance *inst, int64_t microseconds);
 /* Per-character costs (the cost-homomorphism definition allows a different
  * cost for each alphabet character).  costs[a] >= 1 is the cost of the a-th
  * character of the alphabet given to rei_create; n must equal the alphabet

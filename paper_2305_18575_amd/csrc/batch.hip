@@ -173,6 +173,7 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
 
   uint32_t ans_cost = 0;
   uint64_t ans_e = 0;
+  const long long t_start = wall_clock64();
   for (uint32_t c = d.c1; c <= d.max_cost && s_stop == STOP_NONE; ++c) {
     if (tid == 0) {
       s_lstart[c] = s_total;
@@ -201,8 +202,12 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
       s_bstart[0] = 0;
       for (uint32_t b = 0; b < nb; ++b) s_bstart[b + 1] = s_bstart[b] + s_blk[b].count;
       // a level this large is work for the whole device: hand the instance,
-      // with its lower levels stored, to the per-chunk path
-      if (s_bstart[nb] > d.level_max) {
+      // with its lower levels stored, to the per-chunk path; so is a
+      // mid-sized level of an instance that has kept its workgroup long
+      // (the deep searches of a batch), while the device has room beside it
+      const bool late = d.time_ticks && s_bstart[nb] > kBatchTimeMinLevel &&
+                        (uint64_t)(wall_clock64() - t_start) > d.time_ticks;
+      if (s_bstart[nb] > d.level_max || late) {
         s_stop = STOP_HANDOFF;
         s_resume = c;
       }

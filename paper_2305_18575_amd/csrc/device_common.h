@@ -22,7 +22,7 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
 // Bits of the language hash that are kept: all, unless a test narrows them
 // to force collisions, equal fingerprints and long probe sequences (results
 // must not change).  Each translation unit has its own copy (set_hash_mask).
-__device__ uint64_t g_hash_mask = ~0ull;
+__constant__ uint64_t g_hash_mask = ~0ull;
 
 template <int W>
 __device__ __forceinline__ uint64_t hash_key(const uint64_t (&k)[W]) {

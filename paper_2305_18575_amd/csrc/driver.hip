@@ -69,8 +69,10 @@ struct rei_instance {
   uint32_t max_err = 0;
   uint64_t chunk_max = kDefaultChunk;
   uint64_t batch_level_max = 0;  // 0: the tuned value, else kBatchLevelMax
+  int64_t batch_time_us = -1;    // -1: kBatchTimeUs; 0: no hand-off on time
   int device = 0;
   DevAlloc alloc;  // how this instance's device memory is obtained and released
+  double t_seen = -1;  // seconds into a batched call when its completion flag showed
   double seconds_stage = 0;
 
   // staged tables on the device
@@ -813,6 +815,45 @@ rei_status finish_solve(rei_instance* in, double t0) {
   return REI_OK;
 }
 
+// The answer's expression tree from the device (decode_tree): in->tree then
+// answers the printer's back-pointer reads.  Left empty (the printer reads
+// back-pointers itself) in OnTheFly mode, whose levels are not all stored,
+// or past the kernel's limits.
+rei_status device_tree(rei_instance* in, hipStream_t s) {
+  in->tree.clear();
+  if (in->otf_on || in->max_cost + 2 > kTreeMaxLevels || in->char_order.size() > kTreeMaxChars) return REI_OK;
+  TreeArgs t{};
+  t.levels = in->d_levels;
+  t.aux = in->d_aux;
+  t.st = in->d_state;
+  t.out = in->v_tree;
+  t.c1 = in->costs.c_char;
+  t.c2 = in->costs.c_question;
+  t.c3 = in->costs.c_star;
+  t.c4 = in->costs.c_concat;
+  t.c5 = in->costs.c_union;
+  t.nsigma = (uint32_t)in->char_order.size();
+  t.max_nodes = kBatchTreeNodes;
+  for (size_t k = 0; k < in->char_order.size(); ++k) {
+    const uint32_t a = in->char_order[k];
+    t.ccost[k] = in->char_cost.empty() ? in->costs.c_char : in->char_cost[a];
+  }
+  in->h_tree[0] = 0;
+  LAUNCH(in, s, REI_K_OTHER, 1, launch_decode_tree(t, s));
+  HIP_OK(in, hipStreamSynchronize(s));
+  const uint64_t k = std::min<uint64_t>(in->h_tree[0], kBatchTreeNodes);
+  in->tree.assign(in->h_tree + 1, in->h_tree + 1 + 4 * k);
+  for (size_t q = 0; q + 3 < in->tree.size(); q += 4)
+    if (in->tree[q + 1] == OP_CHAR) {
+      if (in->tree[q + 2] >= in->char_order.size()) {
+        in->tree.clear();  // not a character position: leave it to the printer
+        break;
+      }
+      in->tree[q + 2] = in->char_order[in->tree[q + 2]];  // enumeration -> alphabet position
+    }
+  return REI_OK;
+}
+
 // The per-chunk search on the grid: chunks are enqueued without waiting,
 // with one wait per cost level.
 rei_status search_levels(rei_instance* in, hipStream_t s) {
@@ -900,6 +941,7 @@ rei_status search_levels(rei_instance* in, hipStream_t s) {
     }
     if (in->h_state->otf && !in->otf_level) in->otf_level = c;
   }
+  if (in->h_state->stop == STOP_ANSWER) return device_tree(in, s);
   return REI_OK;
 }
 
@@ -1072,6 +1114,22 @@ uint32_t choose_threads(int g, size_t n) {
   return std::min(t, max_threads(g));
 }
 
+// Wall-clock counter ticks per microsecond of a device (its counter runs at a
+// fixed rate, independent of the shader clock).
+uint64_t wall_ticks_per_us(int device) {
+  static std::mutex mu;
+  static std::map<int, uint64_t> rate;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = rate.find(device);
+  if (it != rate.end()) return it->second;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || khz <= 0)
+    khz = 100000;  // the usual 100 MHz
+  const uint64_t t = std::max<uint64_t>(1, (uint64_t)khz / 1000);
+  rate[device] = t;
+  return t;
+}
+
 BatchDesc make_desc(const rei_instance* in) {
   BatchDesc d{};
   d.gt_off = in->d_gt_off;
@@ -1099,6 +1157,8 @@ BatchDesc make_desc(const rei_instance* in) {
   d.sref = in->d_sref;
   d.inl = in->inl ? 1u : 0u;
   d.level_max = in->batch_level_max ? in->batch_level_max : tuned_level_max();
+  const int64_t us = in->batch_time_us < 0 ? kBatchTimeUs : in->batch_time_us;
+  d.time_ticks = us ? (uint64_t)us * wall_ticks_per_us(in->device) : 0;
   d.slot_mask = in->slots_cap - 1;
   d.skey = in->d_skey;
   d.se = in->d_se;
@@ -1267,6 +1327,9 @@ rei_status batch_collect(BatchRun* run, const std::vector<rei_instance*>* taken 
     }
   for (rei_instance* in : done) {
     if ((r = finish_solve(in, run->t0)) != REI_OK) return r;
+    // latency of an instance the launch finished: when its flag showed
+    if (in->t_seen >= 0) in->res.seconds_solve = in->t_seen;
+    in->t_seen = -1;
     run->finished.push_back(in);
   }
   if (fold_prof && (r = batch_fold_prof(run)) != REI_OK) return r;
@@ -1596,6 +1659,7 @@ rei_status rei_solve_batch(rei_instance* const* insts, size_t n, void* hip_strea
       for (size_t i = 0; i < members.size(); ++i) {
         if (seen[i] || !__atomic_load_n(&members[i]->h_state->done, __ATOMIC_ACQUIRE)) continue;
         seen[i] = 1;
+        members[i]->t_seen = now_s() - run.t0;
         --left;
         progress = true;
         if (batch_take_state(members[i])) {
@@ -1631,10 +1695,9 @@ rei_status rei_solve_batch(rei_instance* const* insts, size_t n, void* hip_strea
     if (r != REI_OK) return r;
     if (rp != REI_OK) return rp;
     if ((r = batch_fold_prof(&run)) != REI_OK) return r;
-    for (size_t i = 0; i < n; ++i) {
-      insts[i]->res.seconds_solve = now_s() - run.t0;
-      out[i] = insts[i]->res;
-    }
+    // seconds_solve: when each result was known (its flag, or the end of
+    // its per-chunk levels), counted from the start of the call
+    for (size_t i = 0; i < n; ++i) out[i] = insts[i]->res;
   } catch (const std::bad_alloc&) {
     return REI_ERR_HOST_ALLOC;
   }
@@ -1792,6 +1855,12 @@ rei_status rei_set_chunk(rei_instance* inst, uint64_t max_candidates) {
 rei_status rei_set_batch_level(rei_instance* inst, uint64_t max_candidates) {
   if (!inst) return REI_ERR_INVALID_ARG;
   inst->batch_level_max = max_candidates;
+  return REI_OK;
+}
+
+rei_status rei_set_batch_time(rei_instance* inst, int64_t microseconds) {
+  if (!inst || microseconds < -1) return REI_ERR_INVALID_ARG;
+  inst->batch_time_us = microseconds;
   return REI_OK;
 }
 

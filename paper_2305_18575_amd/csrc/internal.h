@@ -169,6 +169,22 @@ hipError_t launch_finalize(int W, const ChunkArgs& a, hipStream_t s);
 hipError_t launch_account(const ChunkArgs& a, hipStream_t s);
 // An empty kernel through launch_timed (calibrates the timing events).
 hipError_t launch_noop_timed(hipStream_t s);
+
+// The answer's expression tree of a per-chunk search, decoded on the device
+// (one thread) from the stored back-pointers, so that the host reads a few
+// hundred bytes instead of the back-pointer array.
+constexpr uint32_t kTreeMaxLevels = 1024;  // max_cost + 2 at most
+constexpr uint32_t kTreeMaxChars = 64;     // alphabet size at most
+struct TreeArgs {
+  const uint64_t* levels;  // stored rows per cost level (device)
+  const uint64_t* aux;     // back-pointers (level index of each stored row)
+  const DevState* st;      // answer cost and level index
+  uint64_t* out;           // host-visible: [nodes k (0 = not decoded), then k x (row, op, a, b)];
+                           // row ~0 is the answer, a of a character is its position in ccost
+  uint32_t c1, c2, c3, c4, c5, nsigma, max_nodes, pad;
+  uint32_t ccost[kTreeMaxChars];  // character costs in enumeration order
+};
+hipError_t launch_decode_tree(const TreeArgs& t, hipStream_t s);
 hipError_t launch_state_reset(Ctrl* c, DevState* st, uint64_t row_cap, bool otf_on, hipStream_t s);
 constexpr uint64_t kSmallChunk = 1ull << 14;   // candidates finalized by one workgroup
 
@@ -207,6 +223,8 @@ constexpr uint32_t kBatchMaxCost = 63;   // largest max_cost handled in a batch
 constexpr int kBatchMaxW = 8;            // largest words per language
 constexpr uint32_t kBatchMaxIc = 64 * kBatchMaxW;  // largest |ic|
 constexpr uint32_t kBatchMaxPairs = 6144;          // largest guide table (cuts), kept in LDS
+constexpr uint64_t kBatchTimeMinLevel = 4096;  // smaller levels stay on the workgroup whatever the time
+constexpr uint32_t kBatchTimeUs = 500;         // default workgroup time before larger levels move
 constexpr uint64_t kBatchLevelMax = 1ull << 16;  // default: candidates of one level a workgroup takes on
 constexpr uint32_t kBatchTreeNodes = 64; // answer-tree nodes written back (cost <= 63 needs <= 63)
 
@@ -231,6 +249,8 @@ struct BatchDesc {
                               // (the kernel uses a growing prefix of it)
   uint32_t inl, pad2;
   uint64_t level_max;         // larger levels are handed to the per-chunk path
+  uint64_t time_ticks;        // wall-clock ticks after which a level of more than
+                              // kBatchTimeMinLevel candidates is handed over too (0: never)
   uint64_t* skey;             // kBatchChunk survivors
   uint32_t* se;
   uint64_t* spos;

@@ -841,6 +841,129 @@ namespace {
 __global__ void noop_kernel() {}
 }
 
+namespace {
+// Decodes level index e of level c: the characters of cost c, then r? over
+// c - c2, r* over c - c3, concatenations by left cost and unions by left cost
+// (Sec. 3 enumeration order; the counts of the levels below c are final).
+__device__ bool tree_decode_index(const TreeArgs& t, const uint64_t* lstart, const uint64_t* lcount, uint32_t c,
+                                  uint64_t e, uint32_t* op, uint64_t* a, uint64_t* b) {
+  const int64_t c1 = t.c1, cc = c;
+  auto lc = [&](int64_t k) -> uint64_t { return (k >= c1 && k < cc) ? lcount[k] : 0ull; };
+  *b = 0;
+  uint32_t first = 0, cnt = 0;
+  for (uint32_t k = 0; k < t.nsigma; ++k) {
+    first += t.ccost[k] < c;
+    cnt += t.ccost[k] == c;
+  }
+  if (e < cnt) {
+    *op = OP_CHAR;
+    *a = first + e;
+    return true;
+  }
+  e -= cnt;
+  uint64_t n = lc(cc - t.c2);
+  if (e < n) {
+    *op = OP_QUESTION;
+    *a = lstart[cc - t.c2] + e;
+    return true;
+  }
+  e -= n;
+  n = lc(cc - t.c3);
+  if (e < n) {
+    *op = OP_STAR;
+    *a = lstart[cc - t.c3] + e;
+    return true;
+  }
+  e -= n;
+  for (int64_t L = c1; cc - (int64_t)t.c4 - L >= c1; ++L) {
+    const int64_t R = cc - t.c4 - L;
+    n = lc(L) * lc(R);
+    if (e < n) {
+      *op = OP_CONCAT;
+      *a = lstart[L] + e / lc(R);
+      *b = lstart[R] + e % lc(R);
+      return true;
+    }
+    e -= n;
+  }
+  for (int64_t L = c1; L <= cc - (int64_t)t.c5 - L; ++L) {
+    const int64_t R = cc - t.c5 - L;
+    const uint64_t x = lc(L), y = lc(R);
+    n = (L < R) ? x * y : (x ? x * (x - 1) / 2 : 0);
+    if (e < n) {
+      *op = OP_UNION;
+      if (L == R) {
+        uint64_t i = 0, j = 0;
+        tri_decode(e, x, &i, &j);
+        *a = lstart[L] + i;
+        *b = lstart[L] + j;
+      } else {
+        *a = lstart[L] + e / y;
+        *b = lstart[R] + e % y;
+      }
+      return true;
+    }
+    e -= n;
+  }
+  return false;
+}
+
+__global__ __launch_bounds__(64) void decode_tree(TreeArgs t) {
+  __shared__ uint64_t lstart[kTreeMaxLevels], lcount[kTreeMaxLevels];
+  __shared__ uint64_t stk[64];
+  if (threadIdx.x != 0) return;
+  const uint32_t ans_c = t.st->answer_cost;
+  const uint64_t ans_e = t.st->answer_e;
+  if (t.st->stop != STOP_ANSWER || ans_c >= kTreeMaxLevels || ans_c < t.c1) {
+    t.out[0] = 0;
+    return;
+  }
+  uint64_t start = 0;
+  for (uint32_t c = 0; c <= ans_c; ++c) {
+    lstart[c] = start;
+    lcount[c] = c >= t.c1 ? t.levels[c] : 0ull;
+    start += lcount[c];
+  }
+  uint32_t k = 0, sp = 0;
+  bool ok = true;
+  auto node = [&](uint64_t row, uint32_t c, uint64_t e) {
+    uint32_t op = 0;
+    uint64_t a = 0, b = 0;
+    if (k >= t.max_nodes || sp + 2 > 64 || !tree_decode_index(t, lstart, lcount, c, e, &op, &a, &b)) {
+      ok = false;
+      return;
+    }
+    uint64_t* o = t.out + 1 + 4 * k++;
+    o[0] = row;
+    o[1] = op;
+    o[2] = a;
+    o[3] = b;
+    if (op != OP_CHAR) stk[sp++] = a;
+    if (op == OP_CONCAT || op == OP_UNION) stk[sp++] = b;
+  };
+  node(~0ull, ans_c, ans_e);
+  while (ok && sp) {
+    const uint64_t row = stk[--sp];
+    uint32_t rc = 0;
+    for (uint32_t c = t.c1; c < ans_c; ++c)
+      if (row >= lstart[c] && row < lstart[c] + lcount[c]) rc = c;
+    if (!rc) {
+      ok = false;
+      break;
+    }
+    node(row, rc, t.aux[row]);
+  }
+  t.out[0] = ok ? k : 0;
+}
+}  // namespace
+
+hipError_t launch_decode_tree(const TreeArgs& t, hipStream_t s) {
+  if (!t.levels || !t.aux || !t.st || !t.out || t.nsigma > kTreeMaxChars || t.max_nodes == 0)
+    return hipErrorInvalidValue;
+  launch_timed(decode_tree, dim3(1), dim3(64), 0, s, t);
+  return hipGetLastError();
+}
+
 hipError_t set_hash_mask_kernels(uint64_t mask) {
   return hipMemcpyToSymbol(HIP_SYMBOL(g_hash_mask), &mask, sizeof(mask));
 }

@@ -324,6 +324,26 @@ def test_batch_handoff_resumes_exactly(rei, level_max):
         h.close()
 
 
+@pytest.mark.parametrize("us", [0, 1, 200])
+def test_batch_time_handoff_is_exact(rei, us):
+    """Hand-off on time (rei_set_batch_time): 1 us moves every instance at its
+    first level above 4096 candidates, 0 never on time, 200 wherever the
+    clock says; the results equal the oracle's whatever the hand-off level."""
+    specs = batch_specs()[::3]
+    for seed in (3, 6, 9):
+        i = instances.single_instance(seed, (1, 1, 5, 1, 2))
+        specs.append((i.alphabet, i.pos, i.neg, i.costs, i.max_cost))
+    print(f"\nbatch of {len(specs)} instances, hand-off after {us} us", flush=True)
+    hs = [rei.Instance(a, p, n, c, m) for (a, p, n, c, m) in specs]
+    for h in hs:
+        h.set_batch_time(us)
+    res = rei.solve_batch(hs)
+    for r, spec in zip(res, specs):
+        check_against_oracle(r, spec)
+    for h in hs:
+        h.close()
+
+
 # ---- OnTheFly mode (Sec. 3) ----
 
 def _otf_cases():
