@@ -29,6 +29,7 @@ namespace {
 thread_local std::string g_create_error;
 
 constexpr uint64_t kDefaultChunk = 1ull << 24;
+constexpr uint64_t kFirstChunk = 1ull << 16;  // first chunk of a level; each next one doubles
 constexpr uint64_t kDefaultArena = 16ull << 20;  // bytes per batched instance
 
 struct Block {
@@ -911,20 +912,25 @@ rei_status search_levels(rei_instance* in, hipStream_t s) {
       in->err = "candidate count overflows 64 bits";
       return REI_ERR_TOO_LARGE;
     }
-    // chunks of chunk_max consecutive level indices: large blocks are split,
-    // small ones share a chunk
+    // chunks of consecutive level indices: large blocks are split, small
+    // ones share a chunk.  Chunks grow from kFirstChunk to chunk_max within a
+    // level: an answer early in a large level ends it after a few small
+    // chunks (later chunks see the stop flag and exit at once), while a level
+    // without one costs a handful of extra launches.
     uint64_t e_base = 0, acc = 0;
+    uint64_t cur = std::min(in->chunk_max, kFirstChunk);
     std::vector<Piece> pieces;
     for (const Block& b : blocks) {
       for (uint64_t e0 = 0; e0 < b.count && !stopped;) {
-        const uint64_t e1 = std::min(b.count, e0 + (in->chunk_max - acc));
+        const uint64_t e1 = std::min(b.count, e0 + (cur - acc));
         pieces.push_back({b, e_base, e0, e1});
         acc += e1 - e0;
         e0 = e1;
-        if (acc == in->chunk_max) {
+        if (acc == cur) {
           if ((r = enqueue_chunk(in, s, c, pieces, &stopped)) != REI_OK) return r;
           pieces.clear();
           acc = 0;
+          cur = std::min(in->chunk_max, 2 * cur);
         }
       }
       if (stopped) break;
