@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes per work unit of each kernel class (see DESIGN.md):
+# Algorithmic bytes per work unit of each kernel class:
 # a generator must probe the dedup table once per candidate; a probe is a
 # random access, and the smallest HBM transaction is 64 bytes.
 PROBE_BYTES = 64
@@ -40,8 +40,13 @@ PROBE_BYTES = 64
 # by (workload, kernel class).  Only valid for the kernels as they were
 # measured: an entry is removed when its kernel changes.
 TRAFFIC_BYTES = {
-    ("row1", "gen_concat"): 300432828,
-    ("batched", "solve_batch"): 543574200,
+    ("row1", "gen_concat"): 295079584,
+    ("single", "solve_batch"): 42687952,
+    ("single", "gen_pieces"): 4220904,
+    ("single", "gen_concat"): 3651415,
+    ("batched", "solve_batch"): 543456868,
+    ("batched", "gen_pieces"): 3831180,
+    ("batched", "gen_concat"): 2344834,
 }
 
 
@@ -165,8 +170,31 @@ def main():
     # belong to no step.  Objects made so far are moved out of its reach.
     gc.collect()
     gc.freeze()
+
+    def kernel_classes():
+        out = {}
+        for k, name in enumerate(rei.KERNEL_CLASSES):
+            n = ms = units = 0
+            for h in handles:
+                a, b, c = h.kernel_stats(k)
+                n += a
+                ms += b
+                units += c
+            out[name] = {"launches": n, "ms": ms, "units": units}
+        return out
+
+    # One untimed step with the generator classes and the batched solver
+    # timed names the dominant kernel; the timed steps then record events on
+    # its launches only (events on a launch cost it a few microseconds).
     for h in handles:
         h.set_profiling(True)
+    step()
+    torch.cuda.synchronize()
+    classes = kernel_classes()
+    gen = {k: v for k, v in classes.items() if k.startswith("gen_") or k == "solve_batch"}
+    dom = max(gen, key=lambda k: gen[k]["ms"])
+    for h in handles:
+        h.set_profiling_class(dom)
     results, elapsed = timed(step, args.steps)
     for h in handles:
         h.set_profiling(False)
@@ -187,19 +215,8 @@ def main():
     def pct(p):
         return solve_ms[min(len(solve_ms) - 1, int(p * len(solve_ms)))]
 
-    # kernel statistics from the library's HIP events
-    classes = {}
-    for k, name in enumerate(rei.KERNEL_CLASSES):
-        n = ms = units = 0
-        for h in handles:
-            a, b, c = h.kernel_stats(k)
-            n += a
-            ms += b
-            units += c
-        classes[name] = {"launches": n, "ms": ms, "units": units}
-    gen = {k: v for k, v in classes.items() if k.startswith("gen_") or k == "solve_batch"}
-    dom = max(gen, key=lambda k: gen[k]["ms"])
-    d = classes[dom]
+    # the dominant kernel's launches over the timed steps (HIP events)
+    d = kernel_classes()[dom]
     avg_ms = d["ms"] / max(1, d["launches"])
     bytes_per_launch = PROBE_BYTES * d["units"] / max(1, d["launches"])
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
@@ -289,8 +306,10 @@ def main():
         "roofline": roofline,
         "serving": serving_out,
         "cpu_baseline": cpu,
-        "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3), "units": v["units"]}
-                    for k, v in classes.items()},
+        # every generator class and the batched solver, from the untimed
+        # profiled step before the timed ones
+        "kernels_profiled_step": {k: {"launches": v["launches"], "ms": round(v["ms"], 3), "units": v["units"]}
+                                  for k, v in classes.items()},
     }
     if args.workload == "sweep":
         # per cost function, as in the paper's cost-function comparison

@@ -133,22 +133,22 @@ rei_status rei_solve(rei_instance *inst, void *hip_stream, rei_result *out);
 rei_status rei_solve_batch(rei_instance *const *insts, size_t n, void *hip_stream, uint64_t arena_bytes,
                            rei_result *out);
 
-/* Autotuner of rei_solve_batch.  First the launch shape: solves the n
- * instances once for each workgroup size (256, 512 and 1024 threads per
- * instance; at most 512 with 8 words per language), times each word-width
- * group's launch with events the launch records, and keeps for each group
- * the fastest size (best of three runs) for groups of this many instances
- * (by power-of-two size class) in a table of the process that later rei_solve_batch calls on any
- * thread use.  Without an entry, a group gets enough waves per instance to
- * fill the device's wave slots.  Then the hand-off level size (for
- * instances that did not set rei_set_batch_level): whole calls are timed
- * three times for each of 2^13 .. 2^19 candidates and the fastest becomes
- * the process default
- * (2^16 until then).  Results do not depend on either choice.  threads_out
- * (NULL or 5 entries, for W = 1 with keys in the table slots, then W = 1, 2,
- * 4, 8) receives the chosen sizes, 0 for groups without instances;
- * level_max_out (NULL or 1 entry) the level size.  The instances end up
- * solved, as by rei_solve_batch. */
+/* Autotuner of rei_solve_batch, by whole calls (what the caller waits for,
+ * hand-offs included), each setting timed as the shortest of five calls.
+ * First the launch shape: every word-width group at 256, 512, then 1024
+ * threads per instance (at most 512 with 8 words per language); the fastest
+ * is kept, for each group present, for groups of its size (by power-of-two
+ * size class) in a table of the process that later rei_solve_batch calls on
+ * any thread use.  Without an entry, a group gets enough waves per instance
+ * to fill the device's wave slots.  Then the hand-off level size (for
+ * instances that did not set rei_set_batch_level): 2^13 .. 2^19 candidates,
+ * the fastest becomes the process default (2^16 until then).  Other
+ * rei_solve_batch calls running meanwhile also take the shape being timed.
+ * Results do not depend on either choice.  threads_out (NULL or 5 entries,
+ * for W = 1 with keys in the table slots, then W = 1, 2, 4, 8) receives the
+ * chosen sizes, 0 for groups without instances; level_max_out (NULL or 1
+ * entry) the level size.  The instances end up solved, as by
+ * rei_solve_batch. */
 rei_status rei_tune_batch(rei_instance *const *insts, size_t n, void *hip_stream, uint64_t arena_bytes,
                           uint32_t *threads_out, uint64_t *level_max_out);
 
@@ -238,9 +238,11 @@ rei_status rei_set_batch_level(rei_instance *inst, uint64_t max_candidates);
 /* Hand-off time of rei_solve_batch: once the instance's workgroup has run
  * this many microseconds, its next level moves to rei_solve's path if it has
  * more than 4096 candidates, so that the deep searches of a batch use the
- * device beside the workgroups of the others.  -1 = the default (500), 0 =
- * never on time (only rei_set_batch_level's size).  The hand-off level then
- * depends on timing; results do not. */
+ * device beside the workgroups of the others; only in batches with fewer
+ * instances than the device has compute units (a larger batch leaves none
+ * idle).  -1 = the default (500), 0 = never on time (only
+ * rei_set_batch_level's size).  The hand-off level then depends on timing;
+ * results do not. */
 rei_status rei_set_batch_time(rei_instance *inst, int64_t microseconds);
 /* Per-character costs (the cost-homomorphism definition allows a different
  * cost for each alphabet character).  costs[a] >= 1 is the cost of the a-th
@@ -287,6 +289,11 @@ typedef enum {
  * events on the stream around the launch); 0: off.  Turning profiling on
  * clears the statistics; turning it off keeps them. */
 rei_status rei_set_profiling(rei_instance *inst, int enable);
+/* As rei_set_profiling, for the launches of one kernel class only: a caller
+ * that needs one class's average launch time leaves every other launch
+ * untouched by events.  Clears the statistics; rei_set_profiling(inst, 0)
+ * turns it off. */
+rei_status rei_set_profiling_class(rei_instance *inst, rei_kernel_class k);
 /* Launch count, total device milliseconds and work units (candidates for the
  * generator classes, survivors for REI_K_INSERT) of one kernel class,
  * accumulated over the solves since profiling was enabled. */

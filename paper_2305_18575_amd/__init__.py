@@ -29,7 +29,7 @@ KERNEL_CLASSES = ["gen_char", "gen_question", "gen_star", "gen_concat", "gen_uni
 EXPORTS = ["rei_create", "rei_solve", "rei_solve_batch", "rei_tune_batch", "rei_server_create", "rei_server_submit",
            "rei_server_poll", "rei_server_destroy", "rei_set_allocator", "rei_trim", "rei_destroy", "rei_status_str", "rei_last_error",
            "rei_create_error", "rei_ic_word", "rei_level_size", "rei_row_bits",
-           "rei_row_regex", "rei_set_chunk", "rei_set_batch_level", "rei_set_batch_time", "rei_set_on_the_fly", "rei_set_char_costs", "rei_set_max_errors", "rei_set_profiling",
+           "rei_row_regex", "rei_set_chunk", "rei_set_batch_level", "rei_set_batch_time", "rei_set_on_the_fly", "rei_set_char_costs", "rei_set_max_errors", "rei_set_profiling", "rei_set_profiling_class",
            "rei_kernel_stats", "rei_timing_overhead", "rei_set_hash_bits", "rei_kernel_name"]
 
 
@@ -135,6 +135,8 @@ def load_library():
     lib.rei_timing_overhead.restype = ctypes.c_int
     lib.rei_timing_overhead.argtypes = [ctypes.POINTER(ctypes.c_double)]
     lib.rei_kernel_name.restype = cp
+    lib.rei_set_profiling_class.restype = ctypes.c_int
+    lib.rei_set_profiling_class.argtypes = [vp, ctypes.c_int]
     lib.rei_set_batch_time.restype = ctypes.c_int
     lib.rei_set_batch_time.argtypes = [vp, ctypes.c_int64]
     lib.rei_set_allocator.restype = ctypes.c_int
@@ -264,6 +266,11 @@ class Instance:
     def set_profiling(self, on, level: int = 1):
         """Kernel timing: level 1 = generators and batched solver, 2 = all."""
         self._check(self._lib.rei_set_profiling(self._h, level if on else 0))
+
+    def set_profiling_class(self, k):
+        """Kernel timing for one class only (index or name in KERNEL_CLASSES)."""
+        k = KERNEL_CLASSES.index(k) if isinstance(k, str) else int(k)
+        self._check(self._lib.rei_set_profiling_class(self._h, k))
 
     def kernel_stats(self, k: int):
         n, u = ctypes.c_uint64(), ctypes.c_uint64()

@@ -147,7 +147,8 @@ struct rei_instance {
   std::string err;
 
   // profiling
-  int prof = 0;  // 0 off, 1 generators and batched solver, 2 every class
+  int prof = 0;  // 0 off, 1 generators and batched solver, 2 every class, 3 prof_class only
+  int prof_class = 0;
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
   uint64_t st_launch[REI_K_COUNT] = {0};
@@ -220,7 +221,9 @@ rei_status prof_event(rei_instance* in, hipEvent_t* ev) {
   return REI_OK;
 }
 
-bool profiled(const rei_instance* in, int k) { return in->prof == 2 || (in->prof == 1 && self_timed(k)); }
+bool profiled(const rei_instance* in, int k) {
+  return in->prof == 2 || (in->prof == 1 && self_timed(k)) || (in->prof == 3 && k == in->prof_class);
+}
 
 rei_status prof_begin(rei_instance* in, hipStream_t s, int k, hipEvent_t* a, hipEvent_t* b) {
   if (!profiled(in, k)) return REI_OK;
@@ -1033,11 +1036,6 @@ rei_status side_acquire(rei_instance* in, SideStream* out) {
   return REI_OK;
 }
 
-rei_status event_acquire_timing(rei_instance* in, hipEvent_t* out) {
-  HIP_OK(in, hipEventCreateWithFlags(out, hipEventDisableSystemFence));
-  return REI_OK;
-}
-
 rei_status event_acquire(rei_instance* in, hipEvent_t* out) {
   {
     std::lock_guard<std::mutex> g(g_pool_mu);
@@ -1069,11 +1067,8 @@ struct BatchRun {
   std::vector<ProfRec> brecs;   // the batched launches' event pairs
   std::vector<int> rec_w;
   // launch shape: threads per instance of each group (forced by the tuner,
-  // else tuned or from the batch size), and the tuner's per-group timing
-  uint32_t force_threads = 0;
+  // else tuned or from the batch size)
   uint32_t threads[kBatchMaxW + 1] = {0};
-  bool time_groups = false;
-  hipEvent_t gev[kBatchMaxW + 1][2] = {};
 };
 
 // ---- launch shape of the batched solver ---------------------------------
@@ -1087,6 +1082,8 @@ int g_cus = 0;
 // Hand-off level size of instances that leave it at the default: the
 // tuner's choice, else kBatchLevelMax.
 std::atomic<uint64_t> g_level_max{0};
+// Threads per instance forced on every group while the tuner times a shape.
+std::atomic<uint32_t> g_force_threads{0};
 
 uint64_t tuned_level_max() {
   const uint64_t v = g_level_max.load();
@@ -1134,6 +1131,19 @@ uint64_t wall_ticks_per_us(int device) {
   const uint64_t t = std::max<uint64_t>(1, (uint64_t)khz / 1000);
   rate[device] = t;
   return t;
+}
+
+// Compute units of a device.
+uint32_t device_cus(int device) {
+  static std::mutex mu;
+  static std::map<int, uint32_t> cus;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cus.find(device);
+  if (it != cus.end()) return it->second;
+  int n = 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n <= 0) n = 256;
+  cus[device] = (uint32_t)n;
+  return (uint32_t)n;
 }
 
 BatchDesc make_desc(const rei_instance* in) {
@@ -1213,6 +1223,13 @@ rei_status batch_launch(rei_instance* const* insts, size_t n, hipStream_t s, uin
     __atomic_store_n(&in->h_state->done, 0u, __ATOMIC_RELEASE);
   }
   run->pin = n ? insts[0] : nullptr;
+  // Hand-off on time moves deep searches onto compute units the batch leaves
+  // idle; a batch with a workgroup for every compute unit leaves none.
+  size_t batched = 0;
+  for (int g = 0; g <= kBatchMaxW; g = g ? 2 * g : 1) batched += groups[g].size();
+  if (n && batched >= device_cus(insts[0]->device))
+    for (int g = 0; g <= kBatchMaxW; g = g ? 2 * g : 1)
+      for (BatchDesc& d : groups[g]) d.time_ticks = 0;
   // One launch per word width; the first on s, the others on side streams
   // that start after s's earlier work and that s waits for, so the groups
   // run side by side.
@@ -1236,30 +1253,19 @@ rei_status batch_launch(rei_instance* const* insts, size_t n, hipStream_t s, uin
       HIP_OK(in0, hipStreamWaitEvent(ss.s, run->fork, 0));
       gs = ss.s;
     }
-    const uint32_t th = run->force_threads ? std::min(run->force_threads, max_threads(g))
-                                           : choose_threads(g, groups[g].size());
+    const uint32_t forced = g_force_threads.load();
+    const uint32_t th = forced ? std::min(forced, max_threads(g)) : choose_threads(g, groups[g].size());
     run->threads[g] = th;
-    if (run->time_groups) {
-      // the tuner's own timing, recorded by the launch itself
-      hipEvent_t a = nullptr, b = nullptr;
-      if ((r = event_acquire_timing(in0, &a)) != REI_OK || (r = event_acquire_timing(in0, &b)) != REI_OK)
-        return r;
-      run->gev[g][0] = a;
-      run->gev[g][1] = b;
-      g_kernel_timer = KernelTimer{a, b};
-      HIP_OK(in0, launch_solve_batch(g ? g : 1, g == 0, th, db.d, (uint32_t)groups[g].size(), gs));
-    } else {
-      hipEvent_t ev = nullptr, ev2 = nullptr;
-      if ((r = prof_begin(run->pin, gs, REI_K_BATCH, &ev, &ev2)) != REI_OK) return r;
-      HIP_OK(in0, launch_solve_batch(g ? g : 1, g == 0, th, db.d, (uint32_t)groups[g].size(), gs));
-      if ((r = prof_end(run->pin, gs, REI_K_BATCH, ev, ev2, 0)) != REI_OK) return r;
-      if (run->pin->prof) {
-        // kept apart from the instance's own records until the launch is
-        // known to have finished (the instance may continue on the grid)
-        run->brecs.push_back(run->pin->recs.back());
-        run->pin->recs.pop_back();
-        run->rec_w.push_back(g);
-      }
+    hipEvent_t ev = nullptr, ev2 = nullptr;
+    if ((r = prof_begin(run->pin, gs, REI_K_BATCH, &ev, &ev2)) != REI_OK) return r;
+    HIP_OK(in0, launch_solve_batch(g ? g : 1, g == 0, th, db.d, (uint32_t)groups[g].size(), gs));
+    if ((r = prof_end(run->pin, gs, REI_K_BATCH, ev, ev2, 0)) != REI_OK) return r;
+    if (profiled(run->pin, REI_K_BATCH)) {
+      // kept apart from the instance's own records until the launch is
+      // known to have finished (the instance may continue on the grid)
+      run->brecs.push_back(run->pin->recs.back());
+      run->pin->recs.pop_back();
+      run->rec_w.push_back(g);
     }
     if (!first) {
       HIP_OK(in0, hipEventRecord(run->sides.back().join, gs));
@@ -1339,61 +1345,6 @@ rei_status batch_collect(BatchRun* run, const std::vector<rei_instance*>* taken 
     run->finished.push_back(in);
   }
   if (fold_prof && (r = batch_fold_prof(run)) != REI_OK) return r;
-  return REI_OK;
-}
-
-// The instances a batched call leaves to the per-chunk path (hand-offs,
-// instances that outgrew their rows, unbatchable ones): each is
-// latency-bound on its own, so up to 8 run at once, each on a pooled side
-// stream driven by its own host thread.
-rei_status solve_grid_instances(const std::vector<rei_instance*>& grid, hipStream_t s, double t0) {
-  if (grid.empty()) return REI_OK;
-  if (grid.size() == 1) {
-    rei_status r = search_levels(grid[0], s);
-    return r == REI_OK ? finish_solve(grid[0], t0) : r;
-  }
-  const size_t nt = std::min<size_t>(grid.size(), 8);
-  std::atomic<size_t> next{0};
-  std::vector<rei_status> st(nt, REI_OK);
-  std::vector<std::thread> pool;
-  for (size_t t = 0; t < nt; ++t)
-    pool.emplace_back([&, t] {
-      SideStream ss;
-      bool have = false;
-      for (size_t i; (i = next.fetch_add(1)) < grid.size();) {
-        rei_instance* in = grid[i];
-        rei_status r;
-        try {
-          if (hipSetDevice(in->device) != hipSuccess) {
-            st[t] = REI_ERR_DEVICE;
-            break;
-          }
-          if (!have) {
-            if ((r = side_acquire(in, &ss)) != REI_OK) {
-              st[t] = r;
-              break;
-            }
-            have = true;
-          }
-          r = search_levels(in, ss.s);
-          if (r == REI_OK) r = finish_solve(in, t0);
-        } catch (const std::bad_alloc&) {
-          r = REI_ERR_HOST_ALLOC;
-        }
-        if (r != REI_OK) {
-          st[t] = r;
-          break;
-        }
-      }
-      if (have) {
-        (void)hipStreamSynchronize(ss.s);
-        std::lock_guard<std::mutex> g(g_pool_mu);
-        g_side_free.push_back(ss);
-      }
-    });
-  for (auto& th : pool) th.join();
-  for (rei_status r : st)
-    if (r != REI_OK) return r;
   return REI_OK;
 }
 
@@ -1716,80 +1667,68 @@ rei_status rei_tune_batch(rei_instance* const* insts, size_t n, void* hip_stream
   for (size_t i = 0; i < n; ++i)
     if (!insts[i]) return REI_ERR_INVALID_ARG;
   if (arena_bytes == 0) arena_bytes = kDefaultArena;
-  hipStream_t s = (hipStream_t)hip_stream;
-  const uint32_t cand[3] = {256, 512, 1024};
-  double best_ms[kBatchMaxW + 1];
-  uint32_t best_t[kBatchMaxW + 1] = {0};
-  size_t group_n[kBatchMaxW + 1] = {0};
-  for (int g = 0; g <= kBatchMaxW; ++g) best_ms[g] = 1e300;
-  rei_status r;
   try {
-    for (int rep = 0; rep < 3 * 3; ++rep) {  // each shape three times, best of three
-      const uint32_t c = cand[rep % 3];
-      BatchRun run;
-      run.force_threads = c;
-      run.time_groups = true;
-      if ((r = batch_launch(insts, n, s, arena_bytes, &run)) == REI_OK) {
-        hipError_t se = hipStreamSynchronize(s);
-        if (se != hipSuccess) {
-          insts[0]->err = std::string("tuning launch: ") + hipGetErrorString(se);
-          r = REI_ERR_DEVICE;
-        }
+    const uint32_t cand[3] = {256, 512, 1024};
+    std::vector<rei_result> res(n);
+    rei_status r;
+    // the shortest of five whole calls (batched launches and the hand-offs
+    // they start), with the current shape and hand-off settings
+    auto time_calls = [&](double* best) -> rei_status {
+      for (int q = 0; q < 5; ++q) {
+        const double t = now_s();
+        rei_status st = rei_solve_batch(insts, n, hip_stream, arena_bytes, res.data());
+        if (st != REI_OK) return st;
+        *best = std::min(*best, now_s() - t);
       }
+      return REI_OK;
+    };
+    // Launch shape: every group at one shape, whole calls timed (what the
+    // caller waits for, hand-offs included, not the launches alone).
+    double shape_s[3] = {1e300, 1e300, 1e300};
+    for (int q = 0; q < 3; ++q) {
+      g_force_threads.store(cand[q]);
+      r = time_calls(&shape_s[q]);
+      g_force_threads.store(0);
+      if (r != REI_OK) return r;
+    }
+    const int bq = (int)(std::min_element(shape_s, shape_s + 3) - shape_s);
+    size_t group_n[kBatchMaxW + 1] = {0};
+    for (size_t i = 0; i < n; ++i)
+      if (batchable(insts[i])) ++group_n[insts[i]->inl ? 0 : insts[i]->st.W];
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      static const int slot[kBatchMaxW + 1] = {0, 1, 2, -1, 3, -1, -1, -1, 4};
       for (int g = 0; g <= kBatchMaxW; ++g) {
-        if (!run.gev[g][0]) continue;
-        float ms = 0;
-        if (r == REI_OK && run.threads[g] == c && hipEventElapsedTime(&ms, run.gev[g][0], run.gev[g][1]) == hipSuccess &&
-            ms < best_ms[g]) {
-          best_ms[g] = ms;
-          best_t[g] = c;
-        }
-        group_n[g] = run.members[g].size();
-        (void)hipEventDestroy(run.gev[g][0]);
-        (void)hipEventDestroy(run.gev[g][1]);
+        if (slot[g] < 0) continue;
+        const uint32_t t = group_n[g] ? std::min(cand[bq], max_threads(g)) : 0u;
+        if (t) g_tuned[{g, size_class(group_n[g])}] = t;
+        if (threads_out) threads_out[slot[g]] = t;
       }
-      if (r != REI_OK) {
-        (void)hipStreamSynchronize(s);
-        batch_release(&run);
+    }
+    // Hand-off level size (instances left at the default): whole calls with
+    // the shape just chosen, 2^13 .. 2^19, the shortest wins.
+    double best_s = 1e300;
+    uint64_t best_l = kBatchLevelMax;
+    for (int k = 13; k <= 19; ++k) {
+      g_level_max.store(1ull << k);
+      double t = 1e300;
+      if ((r = time_calls(&t)) != REI_OK) {
+        g_level_max.store(0);
         return r;
       }
-      if ((r = batch_collect(&run)) != REI_OK) return r;
-      if ((r = solve_grid_instances(run.grid, s, run.t0)) != REI_OK) return r;
+      if (t < best_s) {
+        best_s = t;
+        best_l = 1ull << k;
+      }
     }
+    g_level_max.store(best_l);
+    if (level_max_out) *level_max_out = best_l;
+    return REI_OK;
   } catch (const std::bad_alloc&) {
+    g_force_threads.store(0);
+    g_level_max.store(0);
     return REI_ERR_HOST_ALLOC;
   }
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    static const int slot[kBatchMaxW + 1] = {0, 1, 2, -1, 3, -1, -1, -1, 4};
-    for (int g = 0; g <= kBatchMaxW; ++g) {
-      if (slot[g] < 0) continue;
-      if (best_t[g]) g_tuned[{g, size_class(group_n[g])}] = best_t[g];
-      if (threads_out) threads_out[slot[g]] = best_t[g];
-    }
-  }
-  // Hand-off level size (instances left at the default): whole batched
-  // calls timed with the shapes just chosen, the shortest wins.
-  double best_s = 1e300;
-  uint64_t best_l = kBatchLevelMax;
-  std::vector<rei_result> res(n);
-  for (int rep = 0; rep < 3 * 7; ++rep) {  // 2^13 .. 2^19, best of three each
-    const int k = 13 + rep % 7;
-    g_level_max.store(1ull << k);
-    const double t = now_s();
-    if ((r = rei_solve_batch(insts, n, hip_stream, arena_bytes, res.data())) != REI_OK) {
-      g_level_max.store(0);
-      return r;
-    }
-    const double dt = now_s() - t;
-    if (dt < best_s) {
-      best_s = dt;
-      best_l = 1ull << k;
-    }
-  }
-  g_level_max.store(best_l);
-  if (level_max_out) *level_max_out = best_l;
-  return REI_OK;
 }
 
 void rei_destroy(rei_instance* inst) {
@@ -1919,6 +1858,18 @@ rei_status rei_set_on_the_fly(rei_instance* inst, int enable) {
 rei_status rei_set_max_errors(rei_instance* inst, uint32_t max_errors) {
   if (!inst) return REI_ERR_INVALID_ARG;
   inst->max_err = max_errors;
+  return REI_OK;
+}
+
+rei_status rei_set_profiling_class(rei_instance* inst, rei_kernel_class k) {
+  if (!inst || (int)k < 0 || (int)k >= REI_K_COUNT) return REI_ERR_INVALID_ARG;
+  for (int q = 0; q < REI_K_COUNT; ++q) {
+    inst->st_launch[q] = 0;
+    inst->st_ms[q] = 0;
+    inst->st_units[q] = 0;
+  }
+  inst->prof = 3;
+  inst->prof_class = (int)k;
   return REI_OK;
 }
 

@@ -911,17 +911,21 @@ __device__ bool tree_decode_index(const TreeArgs& t, const uint64_t* lstart, con
 __global__ __launch_bounds__(64) void decode_tree(TreeArgs t) {
   __shared__ uint64_t lstart[kTreeMaxLevels], lcount[kTreeMaxLevels];
   __shared__ uint64_t stk[64];
-  if (threadIdx.x != 0) return;
   const uint32_t ans_c = t.st->answer_cost;
   const uint64_t ans_e = t.st->answer_e;
-  if (t.st->stop != STOP_ANSWER || ans_c >= kTreeMaxLevels || ans_c < t.c1) {
+  const bool have = t.st->stop == STOP_ANSWER && ans_c < kTreeMaxLevels && ans_c >= t.c1;
+  // level sizes loaded by the whole wave, prefix sums by lane 0
+  if (have)
+    for (uint32_t c = threadIdx.x; c <= ans_c; c += blockDim.x) lcount[c] = c >= t.c1 ? t.levels[c] : 0ull;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  if (!have) {
     t.out[0] = 0;
     return;
   }
   uint64_t start = 0;
   for (uint32_t c = 0; c <= ans_c; ++c) {
     lstart[c] = start;
-    lcount[c] = c >= t.c1 ? t.levels[c] : 0ull;
     start += lcount[c];
   }
   uint32_t k = 0, sp = 0;
