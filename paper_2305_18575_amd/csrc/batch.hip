@@ -303,38 +303,48 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
             filter_emit<W, kInl>(probe, sink, valid, dup, key, (uint32_t)(rel0 + e));
           }
         } else if (blk.op == OP_STAR) {
-          uint64_t* Xt = s_tile[0];
-          uint64_t* Yt = s_tile[1];
-          for (uint64_t g0 = e0; g0 < e1; g0 += 64) {
-            for (int k = wave; k < W; k += kWaves) {
+          // r* for 64 rows per wave pair: the even wave of each pair owns
+          // the pair's two tiles (Xt = its own, Yt = its partner's), so
+          // kWaves/2 groups of rows run at once with wave-level syncs only.
+          // The workgroup barriers around the block keep the partner's tile
+          // out of the neighbouring blocks' per-wave use.
+          __syncthreads();
+          if ((wave & 1u) == 0) {
+            uint64_t* Xt = s_tile[wave];
+            uint64_t* Yt = s_tile[wave + 1];
+            constexpr uint32_t kPairs = kWaves / 2;
+            for (uint64_t g0 = e0 + 64 * (uint64_t)(wave >> 1); g0 < e1; g0 += 64 * (uint64_t)kPairs) {
               const uint64_t e = g0 + lane;
-              const uint64_t v = (e < e1) ? d.rows[(lst + e) * W + k] : 0ull;
-              Xt[64 * k + lane] = transpose64(v);
-            }
-            for (uint32_t w = tid; w < 64u * W; w += kT) Yt[w] = (w == 0) ? ~0ull : 0ull;
-            __syncthreads();
-            for (uint32_t l = 1; l <= d.max_len; ++l) {
-              const uint32_t lo = s_lo[l], hi = s_lo[l + 1];
-              for (uint32_t w = lo + tid; w < hi; w += kT) {
-                uint64_t acc = 0;
-                const uint32_t q1 = s_gto[w + 1];
-                for (uint32_t q = s_gto[w] + 1; q < q1; ++q) {  // cut 0 has u = eps
-                  const uint32_t p = s_gtp[q];
-                  acc |= Xt[p >> 16] & Yt[p & 0xFFFFu];
-                }
-                Yt[w] = acc;
+#pragma unroll
+              for (int k = 0; k < W; ++k) {
+                const uint64_t v = (e < e1) ? d.rows[(lst + e) * W + k] : 0ull;
+                Xt[64 * k + lane] = transpose64(v);
               }
-              __syncthreads();
-            }
-            if (wave == 0) {
+              for (uint32_t w = lane; w < 64u * W; w += 64) Yt[w] = (w == 0) ? ~0ull : 0ull;
+              wave_sync_lds();
+              // Y(eps) = 1; by increasing length, Y(w) = OR over cuts w = u v
+              // with u non-empty of X(u) & Y(v) (v is shorter)
+              for (uint32_t l = 1; l <= d.max_len; ++l) {
+                const uint32_t lo = s_lo[l], hi = s_lo[l + 1];
+                for (uint32_t w = lo + lane; w < hi; w += 64) {
+                  uint64_t acc = 0;
+                  const uint32_t q1 = s_gto[w + 1];
+                  for (uint32_t q = s_gto[w] + 1; q < q1; ++q) {  // cut 0 has u = eps
+                    const uint32_t p = s_gtp[q];
+                    acc |= Xt[p >> 16] & Yt[p & 0xFFFFu];
+                  }
+                  Yt[w] = acc;
+                }
+                wave_sync_lds();
+              }
               uint64_t key[W];
 #pragma unroll
               for (int k = 0; k < W; ++k) key[k] = transpose64(Yt[64 * k + lane]);
-              const uint64_t e = g0 + lane;
               filter_emit<W, kInl>(probe, sink, e < e1, false, key, (uint32_t)(rel0 + e));
+              wave_sync_lds();  // the tiles are rewritten by the next group
             }
-            __syncthreads();
           }
+          __syncthreads();
         } else {  // OP_CONCAT
           uint64_t* T = s_tile[wave];
           uint64_t* U = s_uni[wave];
