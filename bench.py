@@ -91,7 +91,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="single")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-errors", type=int, default=0)
     ap.add_argument("--serving-requests", type=int, default=200,
@@ -269,7 +269,7 @@ def main():
         t1 = time.perf_counter()
         cu = 0
         done = 0
-        while time.perf_counter() - t1 < args.cpu_seconds and done < 10 * len(insts):
+        while time.perf_counter() - t1 < args.cpu_seconds and done < 40 * len(insts):
             it = insts[done % len(insts)]
             r = oracle.solve(it.alphabet, it.pos, it.neg, it.costs, it.max_cost, 1 << 40,
                              args.max_errors, threads)
