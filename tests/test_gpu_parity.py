@@ -535,6 +535,40 @@ def test_kernel_statistics(rei):
     h.close()
 
 
+def test_profiling_one_class(rei):
+    """rei_set_profiling_class times the launches of one class only (the
+    same count as level 2 gives that class); a batch's launches are
+    counted on its first instance; results are unchanged; a class outside
+    the enumeration is refused."""
+    it = instances.single_instance(6, (1, 1, 1, 1, 1))
+    h = rei.Instance(it.alphabet, it.pos, it.neg, it.costs, it.max_cost)
+    classes = rei.KERNEL_CLASSES
+    h.set_profiling(True, level=2)
+    ref = h.solve()
+    full = {c: h.kernel_stats(k) for k, c in enumerate(classes)}
+    timed = [c for c in ("gen_concat", "gen_pieces", "insert_survivors") if full[c][0] > 0]
+    assert len(timed) >= 2
+    for c in timed:
+        h.set_profiling_class(c)
+        r = h.solve()
+        h.set_profiling(False)
+        got = {q: h.kernel_stats(k) for k, q in enumerate(classes)}
+        assert got[c][0] == full[c][0] > 0
+        assert all(got[q][0] == 0 for q in classes if q != c)
+        assert (r.status, r.cost, r.regex, r.unique, r.candidates) == (ref.status, ref.cost, ref.regex,
+                                                                        ref.unique, ref.candidates)
+    with pytest.raises(rei.ReiError):
+        h.set_profiling_class(len(classes))
+    hs = [rei.Instance(i.alphabet, i.pos, i.neg, i.costs, i.max_cost) for i in instances.batched_instances(0, 16)]
+    hs[0].set_profiling_class("solve_batch")
+    rei.solve_batch(hs)
+    n, ms, units = hs[0].kernel_stats(classes.index("solve_batch"))
+    assert n >= 1 and ms > 0 and units > 0
+    assert hs[0].kernel_stats(classes.index("gen_concat"))[0] == 0
+    for x in hs + [h]:
+        x.close()
+
+
 def test_timing_overhead_is_measured(rei):
     us = rei.timing_overhead_us()
     assert 0.0 < us < 1000.0
