@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 from dataclasses import dataclass
 from typing import Callable, List, Optional, Sequence
 
@@ -195,6 +196,9 @@ class Instance:
         lib = load_library()
         self._lib = lib
         self._h = None
+        # memory from a Python allocator is given back through Python: not
+        # possible while the interpreter shuts down (the process frees it)
+        self._py_alloc = _py_allocator_active
         h = ctypes.c_void_p()
         st = lib.rei_create(alphabet.encode("latin-1"), _strarr(pos), len(pos),
                             _strarr(neg), len(neg), _Costs(*costs), int(max_cost),
@@ -211,6 +215,8 @@ class Instance:
             self._h = None
 
     def __del__(self):
+        if getattr(self, "_py_alloc", False) and sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -343,12 +349,14 @@ def tune_batch(instances: Sequence["Instance"], stream: Optional[int] = -1,
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 _allocator_refs = []  # every pair ever registered: instances keep theirs until destroyed
+_py_allocator_active = False
 
 
 def set_allocator(alloc: Optional[Callable[[int], int]], free: Optional[Callable[[int], None]]):
     """``rei_set_allocator``: instances created from now on take their device
     memory from ``alloc(bytes) -> address`` (0 on failure) and give it back
     with ``free(address)``; ``None, None`` restores hipMalloc / hipFree."""
+    global _py_allocator_active
     lib = load_library()
     if alloc is None and free is None:
         st = lib.rei_set_allocator(_ALLOC_FN(), _FREE_FN(), None)
@@ -372,6 +380,7 @@ def set_allocator(alloc: Optional[Callable[[int], int]], free: Optional[Callable
         st = lib.rei_set_allocator(pair[0], pair[1], None)
     if st != 0:
         raise ReiError(st, "rei_set_allocator")
+    _py_allocator_active = alloc is not None
 
 
 def use_torch_allocator(device: Optional[int] = None):
