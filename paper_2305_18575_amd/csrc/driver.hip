@@ -1611,6 +1611,7 @@ rei_status rei_solve_batch(rei_instance* const* insts, size_t n, void* hip_strea
     std::vector<char> seen(members.size(), 0);
     size_t left = members.size();
     bool launches_done = false;
+    double last_query = 0;
     while (left) {
       bool progress = false;
       for (size_t i = 0; i < members.size(); ++i) {
@@ -1626,6 +1627,16 @@ rei_status rei_solve_batch(rei_instance* const* insts, size_t n, void* hip_strea
       }
       if (!left || progress) continue;
       if (launches_done) break;  // every flag is final: collected below
+      // the flags are plain host memory, read at every pass; the stream is
+      // asked (a runtime call the workers' launches contend with) every
+      // 50 us at most
+      if (now_s() - last_query < 50e-6) {
+        // a sleep would round up to the timer slack (tens of microseconds),
+        // which the deep instances' hand-offs would wait for
+        std::this_thread::yield();
+        continue;
+      }
+      last_query = now_s();
       const hipError_t q = hipStreamQuery(s);
       if (q == hipSuccess) {
         launches_done = true;  // one more pass sees every flag
@@ -1636,7 +1647,7 @@ rei_status rei_solve_batch(rei_instance* const* insts, size_t n, void* hip_strea
         batch_release(&run);
         return REI_ERR_DEVICE;
       } else {
-        std::this_thread::sleep_for(std::chrono::microseconds(20));
+        std::this_thread::yield();
       }
     }
     hipError_t se = hipStreamSynchronize(s);
