@@ -1349,77 +1349,104 @@ rei_status batch_collect(BatchRun* run, const std::vector<rei_instance*>* taken 
 }
 
 // Worker threads that run the per-chunk path for instances handed to them
-// while a batched launch still runs: up to 8 threads, each driving its own
-// pooled stream, started as instances arrive.
-class GridPool {
+// while a batched launch still runs: 8 threads for the whole process, each
+// driving its own pooled stream per device, started on first use and kept
+// (starting threads per call cost the polling thread tens of microseconds
+// per hand-off).  A GridPool is one call's group of instances on them.
+class Workers {
  public:
-  explicit GridPool(double t0) : t0_(t0) {}
-  ~GridPool() { (void)join(); }
-  void submit(rei_instance* in) {
+  struct Group {
+    double t0 = 0;
+    size_t pending = 0;
+    rei_status status = REI_OK;
+  };
+  static Workers& get() {
+    // never destroyed: threads parked on its condition variable at process
+    // exit must not see it torn down
+    static Workers* w = new Workers();
+    return *w;
+  }
+  void submit(Group* g, rei_instance* in) {
     std::lock_guard<std::mutex> lk(mu_);
-    q_.push_back(in);
-    if (idle_ == 0 && threads_.size() < 8) threads_.emplace_back([this] { work(); });
+    ++g->pending;
+    q_.push_back({g, in});
+    if (idle_ == 0 && threads_ < kThreads) {
+      ++threads_;
+      std::thread([this] { work(); }).detach();
+    }
     cv_.notify_one();
   }
-  // Waits for every submitted instance; the first error, if any.
-  rei_status join() {
-    {
-      std::lock_guard<std::mutex> lk(mu_);
-      closed_ = true;
-    }
-    cv_.notify_all();
-    for (auto& t : threads_)
-      if (t.joinable()) t.join();
-    threads_.clear();
-    return status_;
+  // Waits until every instance of the group is done; the first error.
+  rei_status wait(Group* g) {
+    std::unique_lock<std::mutex> lk(mu_);
+    done_cv_.wait(lk, [&] { return g->pending == 0; });
+    return g->status;
   }
 
  private:
+  static constexpr int kThreads = 8;
+  struct Job {
+    Group* g;
+    rei_instance* in;
+  };
   void work() {
-    SideStream ss;
-    bool have = false;
+    std::vector<SideStream> streams;  // one per device this thread has served
     for (;;) {
-      rei_instance* in = nullptr;
+      Job job;
       {
         std::unique_lock<std::mutex> lk(mu_);
         ++idle_;
-        cv_.wait(lk, [&] { return closed_ || !q_.empty(); });
+        cv_.wait(lk, [&] { return !q_.empty(); });
         --idle_;
-        if (q_.empty()) break;
-        in = q_.front();
+        job = q_.front();
         q_.pop_front();
       }
+      rei_instance* in = job.in;
       rei_status r = REI_OK;
       try {
         if (hipSetDevice(in->device) != hipSuccess) r = REI_ERR_DEVICE;
-        if (r == REI_OK && !have) {
-          r = side_acquire(in, &ss);
-          have = r == REI_OK;
+        SideStream* ss = nullptr;
+        for (auto& x : streams)
+          if (x.device == in->device) ss = &x;
+        if (r == REI_OK && !ss) {
+          SideStream n;
+          r = side_acquire(in, &n);
+          if (r == REI_OK) {
+            streams.push_back(n);
+            ss = &streams.back();
+          }
         }
-        if (r == REI_OK) r = search_levels(in, ss.s);
-        if (r == REI_OK) r = finish_solve(in, t0_);
+        if (r == REI_OK) r = search_levels(in, ss->s);
+        if (r == REI_OK) r = finish_solve(in, job.g->t0);
+        // the instance's work is on ss: finished before the caller sees it
+        if (r == REI_OK && hipStreamSynchronize(ss->s) != hipSuccess) r = REI_ERR_DEVICE;
       } catch (const std::bad_alloc&) {
         r = REI_ERR_HOST_ALLOC;
       }
-      if (r != REI_OK) {
+      {
         std::lock_guard<std::mutex> lk(mu_);
-        if (status_ == REI_OK) status_ = r;
+        if (r != REI_OK && job.g->status == REI_OK) job.g->status = r;
+        --job.g->pending;
       }
-    }
-    if (have) {
-      (void)hipStreamSynchronize(ss.s);
-      std::lock_guard<std::mutex> g(g_pool_mu);
-      g_side_free.push_back(ss);
+      done_cv_.notify_all();
     }
   }
-  double t0_;
   std::mutex mu_;
-  std::condition_variable cv_;
-  std::deque<rei_instance*> q_;
-  std::vector<std::thread> threads_;
+  std::condition_variable cv_, done_cv_;
+  std::deque<Job> q_;
+  int threads_ = 0;
   int idle_ = 0;
-  bool closed_ = false;
-  rei_status status_ = REI_OK;
+};
+
+class GridPool {
+ public:
+  explicit GridPool(double t0) { g_.t0 = t0; }
+  ~GridPool() { (void)join(); }
+  void submit(rei_instance* in) { Workers::get().submit(&g_, in); }
+  rei_status join() { return Workers::get().wait(&g_); }
+
+ private:
+  Workers::Group g_;
 };
 
 // Frees the language cache, the table and the chunk buffers (the staged
