@@ -641,3 +641,39 @@ def test_caller_allocator_gives_identical_results(rei):
     assert calls[0] > len(specs) and calls[0] == calls[1] and not live
     with pytest.raises(ValueError):
         rei.set_allocator(alloc, None)
+
+
+def test_concurrent_batched_calls(rei):
+    """Two threads call rei_solve_batch at once on disjoint instance sets
+    whose instances hand off early: the calls share the process's hand-off
+    workers and stream pools, and each gets the results of a call alone."""
+    import threading
+    specs = batch_specs()[::4]
+    key = lambda r: (r.status, r.cost, r.regex, r.unique, r.candidates)
+    sets = [[rei.Instance(a, p, n, c, m) for (a, p, n, c, m) in specs] for _ in range(2)]
+    for hs in sets:
+        for h in hs:
+            h.set_batch_level(300)
+    alone = [[key(r) for r in rei.solve_batch(hs)] for hs in sets]
+    assert alone[0] == alone[1]
+    got = [None, None]
+    errors = []
+
+    def run(k):
+        try:
+            for _ in range(3):
+                got[k] = [key(r) for r in rei.solve_batch(sets[k])]
+        except Exception as e:  # reported below, on the test's thread
+            errors.append(e)
+
+    print(f"\ntwo threads x {len(specs)} instances", flush=True)
+    ts = [threading.Thread(target=run, args=(k,)) for k in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert not errors, errors
+    assert got[0] == alone[0] and got[1] == alone[1]
+    for hs in sets:
+        for h in hs:
+            h.close()
