@@ -584,6 +584,36 @@ __global__ __launch_bounds__(256) void scan_reduce(ChunkArgs a) {
   if (t == 0) a.block_sums[b] = red[0];
 }
 
+// Chunks whose bitmap has at most kScanSingleWords words: the whole
+// exclusive scan of the winner bitmap in one workgroup (each thread a
+// contiguous run of words), total -> ctrl->winners.  Replaces the three
+// launches below for the mid-sized chunks a level starts with.
+constexpr uint32_t kScanSingleWords = 32768;
+__global__ __launch_bounds__(1024) void scan_single(ChunkArgs a) {
+  __shared__ uint32_t part[1024];
+  if (a.st->stop) return;
+  const uint32_t t = threadIdx.x;
+  const uint32_t words = a.n_bitmap_words;
+  const uint32_t per = (words + 1023) / 1024;
+  const uint32_t lo = min(words, t * per), hi = min(words, lo + per);
+  uint32_t s = 0;
+  for (uint32_t w = lo; w < hi; ++w) s += __popc(a.bitmap[w]);
+  part[t] = s;
+  __syncthreads();
+  for (uint32_t st = 1; st < 1024; st <<= 1) {
+    const uint32_t v = (t >= st) ? part[t - st] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - s;  // exclusive
+  for (uint32_t w = lo; w < hi; ++w) {
+    a.word_prefix[w] = run;
+    run += __popc(a.bitmap[w]);
+  }
+  if (t == 1023) a.ctrl->winners = part[1023];
+}
+
 // single workgroup: exclusive scan of the block sums, total -> ctrl->winners
 __global__ __launch_bounds__(1024) void scan_top(ChunkArgs a, uint32_t nb) {
   __shared__ uint32_t part[1024];
@@ -828,10 +858,14 @@ hipError_t launch_finalize(int W, const ChunkArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(mark_winners<true>, dim3(g), dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL(mark_winners<false>, dim3(g), dim3(256), 0, s, a);
-  const uint32_t nb = (a.n_bitmap_words + kScanBlock - 1) / kScanBlock;
-  hipLaunchKernelGGL(scan_reduce, dim3(nb), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(scan_top, dim3(1), dim3(1024), 0, s, a, nb);
-  hipLaunchKernelGGL(scan_down, dim3(nb), dim3(256), 0, s, a);
+  if (a.n_bitmap_words <= kScanSingleWords) {
+    hipLaunchKernelGGL(scan_single, dim3(1), dim3(1024), 0, s, a);
+  } else {
+    const uint32_t nb = (a.n_bitmap_words + kScanBlock - 1) / kScanBlock;
+    hipLaunchKernelGGL(scan_reduce, dim3(nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(scan_top, dim3(1), dim3(1024), 0, s, a, nb);
+    hipLaunchKernelGGL(scan_down, dim3(nb), dim3(256), 0, s, a);
+  }
   REI_DISPATCH_WI(W, a.inl, hipLaunchKernelGGL((compact_winners<kW, kI>), dim3(g), dim3(256), 0, s, a));
   hipLaunchKernelGGL(account_large, dim3(1), dim3(1), 0, s, a);
   return hipGetLastError();
