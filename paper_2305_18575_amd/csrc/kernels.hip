@@ -584,11 +584,12 @@ __global__ __launch_bounds__(256) void scan_reduce(ChunkArgs a) {
   if (t == 0) a.block_sums[b] = red[0];
 }
 
-// Chunks whose bitmap has at most kScanSingleWords words: the whole
-// exclusive scan of the winner bitmap in one workgroup (each thread a
-// contiguous run of words), total -> ctrl->winners.  Replaces the three
-// launches below for the mid-sized chunks a level starts with.
-constexpr uint32_t kScanSingleWords = 32768;
+// Chunks whose bitmap has at most kScanSingleWords words (2^18 candidates,
+// eight words per thread): the whole exclusive scan of the winner bitmap in
+// one workgroup (each thread a contiguous run of words), total ->
+// ctrl->winners.  Replaces the three launches below for the mid-sized
+// chunks a level starts with; larger bitmaps scan faster spread out.
+constexpr uint32_t kScanSingleWords = 8192;
 __global__ __launch_bounds__(1024) void scan_single(ChunkArgs a) {
   __shared__ uint32_t part[1024];
   if (a.st->stop) return;
