@@ -1,20 +1,26 @@
 """Benchmark: unique languages enumerated per second on one MI355X.
 
-A step solves one batch of synthetic single instances (alphabet {0,1}, target
-expression of cost 10..14, 10 positive and 10 negative strings of length
-0..7, seeds 0..31, under the cost functions (1,1,1,1,1) and (1,1,5,1,2))
-with one rei_solve_batch call on the current stream (one workgroup per
-instance runs its whole search; instances that outgrow their preallocated
-rows finish on the per-chunk path).  Instances are staged (rei_create: host
-staging + upload) before the timed region, so their tables are resident in
-HBM when timing starts.  The same instances solved one after the other with
-rei_solve are timed as well (sequential_value).
+Default workload (the large configuration): four seeded specifications
+(seeds 0..3) over the alphabet {0,1,2}, each with 20 positive and 20 negative
+strings of length 0..10 drawn from a target expression of cost 14..18, cost
+function (1,1,1,1,1), searched up to the target's cost with a 200 GB
+language-cache budget.  A step solves the four with one rei_solve_batch call
+on the current stream (specifications with more than 8 words per language
+run the per-chunk grid path, concurrently); the specifications are staged
+(rei_create: host staging + upload) before the timed region, so their tables
+are resident in HBM when timing starts.
 
-value = sum over the batch of unique languages enumerated / wall time of the
-batch.  The JSON line also carries the time-to-minimal-regex distribution,
-the dominant kernel's roofline figures (HIP events recorded by the library
-around each launch, on the stream the kernel runs on) and the CPU oracle's
-rate on a bounded sample of the same workload.
+value = unique languages enumerated in a step (sum over the instances and
+their levels) / wall time of the step, over the timed steps.
+
+The JSON line also carries, per instance, the per-level unique and candidate
+counts and the time to the minimal expression (rei_create + rei_solve, the
+two parts separately); the dominant kernel's roofline figures against the
+published HBM and integer-ALU peaks and against peaks measured in the same
+run (copy, random table probes, bitwise ALU loop); the other configurations
+(single instances as one batch, the 4096-instance batch replayed as one
+graph launch, the serving sweep); and the CPU oracle's rate on a bounded
+sample of the same workload with 1 thread and with the host's CPU share.
 """
 from __future__ import annotations
 
@@ -29,29 +35,42 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-
-# Algorithmic bytes per work unit of each kernel class:
-# a generator must probe the dedup table once per candidate; a probe is a
-# random access, and the smallest HBM transaction is 64 bytes.
+# 256 CUs x 64 integer lanes per clock x 2.4 GHz = 39.3 T 32-bit lane
+# operations per second; each does 32 bitwise operations
+VALU_PEAK_BITOPS = 256 * 64 * 2.4e9 * 32
+# a dedup probe is one random access; the smallest HBM transaction is 64 B
 PROBE_BYTES = 64
 
-# HBM bytes per launch of the dominant kernel, from FETCH_SIZE / WRITE_SIZE
-# counter runs calibrated on a 1 GiB copy (profiles/hbm_traffic_counters.md),
-# by (workload, kernel class).  Only valid for the kernels as they were
-# measured: an entry is removed when its kernel changes.
-TRAFFIC_BYTES = {
-    ("row1", "gen_concat"): 295079584,
-    ("single", "solve_batch"): 40402152,
-    ("single", "gen_pieces"): 4097032,
-    ("single", "gen_concat"): 3652345,
-    ("batched", "solve_batch"): 545672132,
-    ("batched", "gen_pieces"): 3831192,
-    ("batched", "gen_concat"): 2344806,
-}
+# HBM bytes per launch of the dominant kernel from FETCH_SIZE / WRITE_SIZE
+# counter runs (rocprofv3 --pmc), calibrated on a plain copy of known size,
+# by (workload, kernel class); stored, since a counter run is a separate
+# profiler invocation.  The profile each figure comes from is named beside it.
+# An entry is removed when its kernel changes.
+TRAFFIC = {}
+
+
+def infix_closure(strings):
+    out = set()
+    for w in strings:
+        for i in range(len(w) + 1):
+            for j in range(i, len(w) + 1):
+                out.add(w[i:j])
+    return out
+
+
+def guide_size(inst) -> int:
+    """S: entries of the guide table, all cuts w = u v of every infix w."""
+    return sum(len(w) + 1 for w in infix_closure(list(inst.pos) + list(inst.neg)))
 
 
 def workload(name: str):
     from paper_2305_18575_amd import instances
+    if name == "large":
+        out = [instances.large_instance(s) for s in range(4)]
+        desc = ("large: alphabet {0,1,2}, target cost 14-18, 20+20 strings of length 0-10 (461-700 infixes, "
+                "8-16 words per language), seeds 0-3, cost function (1,1,1,1,1), max_cost = target cost, "
+                "200 GB language cache; 4 solves per step")
+        return out, desc, 200 << 30
     if name == "single":
         out = []
         for costs in ((1, 1, 1, 1, 1), (1, 1, 5, 1, 2)):
@@ -59,15 +78,19 @@ def workload(name: str):
                 out.append(instances.single_instance(seed, costs))
         desc = ("single instance: alphabet {0,1}, target cost 10-14, 10+10 strings of length 0-7, "
                 "seeds 0-31 x cost functions (1,1,1,1,1) and (1,1,5,1,2), 64 solves per step")
-        return out, desc
+        return out, desc, 64 << 30
     if name == "plain":
         out = [instances.plain_instance(s) for s in range(200)]
-        return out, "plain instance: alphabet {0,1}, target cost 1-8, 4+4 strings of length 1-5, seeds 0-199"
+        return out, "plain instance: alphabet {0,1}, target cost 1-8, 4+4 strings of length 1-5, seeds 0-199", 8 << 30
     if name == "batched":
         out = instances.batched_instances(0, 4096)
         return out, ("batched: 4096 instances from master seed 0, alphabet of 2-4 symbols, 2-16 positive and "
                      "2-16 negative strings of length 0-6, target cost 4-12, cost function (1,1,1,1,1), "
-                     "max_cost = target cost")
+                     "max_cost = target cost"), 1 << 30
+    if name == "wide":
+        out = [instances.wide_instance(s, 12) for s in range(4)]
+        return out, ("wide: 20+20 ternary strings of length <= 12 drawn as Type 1 benchmarks (1219-1234 "
+                     "infixes, 32 words per language), seeds 0-3, max_cost 12"), 64 << 30
     if name == "sweep":
         out = []
         for kind, seeds in (("type1", (0, 2)), ("type2", (1, 2))):
@@ -76,13 +99,164 @@ def workload(name: str):
                 for costs in instances.PAPER_COST_FUNCTIONS:
                     out.append(gen(seed, costs=costs, max_cost=1000))
         return out, ("cost-function sweep: Type 1 seeds 0 and 2, Type 2 seeds 1 and 2 (paper's generators, "
-                     "alphabet {0,1}), each under the paper's 12 cost functions, 25 GB language cache")
+                     "alphabet {0,1}), each under the paper's 12 cost functions, 25 GB language cache"), 25 << 30
     if name == "row1":
         t = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_examples.json")))["table1_row1"]
-        inst = instances.Instance(t["alphabet"], t["pos"], t["neg"], "", 0, 0, "row1",
-                                  (1, 1, 1, 1, 1), 30)
-        return [inst], "Table 1 row 1 specification (10+12 strings), cost function (1,1,1,1,1)"
+        inst = instances.Instance(t["alphabet"], t["pos"], t["neg"], "", 0, 0, "row1", (1, 1, 1, 1, 1), 30)
+        return [inst], "Table 1 row 1 specification (10+12 strings), cost function (1,1,1,1,1)", 64 << 30
     raise SystemExit(f"unknown workload {name}")
+
+
+def host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    ram = None
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    ram = round(int(line.split()[1]) / (1 << 20), 1)
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "ram_gib": ram}
+
+
+def cpu_share() -> int:
+    """Threads the oracle may use: the CPUs this process may run on, capped
+    by the thread count the environment allots (OMP_NUM_THREADS)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_baseline(insts, cache, seconds, max_errors=0):
+    """The oracle as written, timed on this host: the workload's instances in
+    order (whole passes, at least one instance) for about ``seconds``, once
+    with one thread and once with the host's CPU share (the oracle splits
+    each chunk of candidates across its threads)."""
+    import oracle
+    from paper_2305_18575_amd import instances as I
+
+    def leg(threads):
+        t1 = time.perf_counter()
+        cu = done = 0
+        while True:
+            it = insts[done % len(insts)]
+            cap = I.row_cap(cache, I.n_infixes(list(it.pos) + list(it.neg)))
+            r = oracle.solve(it.alphabet, it.pos, it.neg, it.costs, it.max_cost, cap, max_errors, threads)
+            cu += sum(r.unique)
+            done += 1
+            if time.perf_counter() - t1 >= seconds or done >= 40 * len(insts):
+                break
+        ct = time.perf_counter() - t1
+        return {"value": round(cu / ct, 3), "cores": threads, "solves": done, "seconds": round(ct, 2)}
+
+    t = cpu_share()
+    one = leg(1)
+    many = leg(t) if t > 1 else one
+    return {"value": many["value"], "unit": "languages/s", "cores": t, "kind": "oracle",
+            "sample": f"{many['solves']} solves of the workload's instances in order ({many['seconds']} s), "
+                      f"threads = the host's CPU share",
+            "single_thread": one, "host": host_info()}
+
+
+def measured_peaks(rei):
+    out = {}
+    r, s = rei.measure_peak("copy", 4 << 30)
+    out["copy_GBps"] = round(r / 1e9, 1)
+    r, s = rei.measure_peak("probe", 4 << 30)
+    out["probe_4GiB_table_Gps"] = round(r / 1e9, 2)
+    r, s = rei.measure_peak("probe", 64 << 20)
+    out["probe_64MiB_table_Gps"] = round(r / 1e9, 2)
+    r, s = rei.measure_peak("probe_atomic", 4 << 30)
+    out["probe_atomic_4GiB_table_Gps"] = round(r / 1e9, 2)
+    r, s = rei.measure_peak("bitwise")
+    out["bitwise_Tbitops"] = round(r * 32 / 1e12, 1)
+    return out
+
+
+def kernel_classes(rei, handles):
+    out = {}
+    for k, name in enumerate(rei.KERNEL_CLASSES):
+        n = ms = units = 0
+        for h in handles:
+            a, b, c = h.kernel_stats(k)
+            n += a
+            ms += b
+            units += c
+        out[name] = {"launches": n, "ms": ms, "units": units}
+    return out
+
+
+def timed(step, k):
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    out = [step() for _ in range(k)]
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t
+
+
+def roofline(rei, handles, insts, dom, peaks, workload_name, max_errors):
+    """Figures of the dominant kernel class over the timed steps (HIP events
+    the library records at each launch's own start and end)."""
+    d = kernel_classes(rei, handles)[dom]
+    avg_s = d["ms"] / max(1, d["launches"]) * 1e-3
+    cand = d["units"] / max(1, d["launches"])
+    bytes_per_launch = PROBE_BYTES * cand
+    achieved = bytes_per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
+    tr = TRAFFIC.get((workload_name, dom)) if not max_errors else None
+    out = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": tr[0] if tr else None,
+           "traffic_source": tr[1] if tr else None,
+           "algorithmic_bytes_per_launch": round(bytes_per_launch), "candidates_per_launch": round(cand, 1),
+           "avg_launch_us": round(avg_s * 1e6, 3), "launches": d["launches"],
+           "probes_per_sec": round(cand / avg_s, 1) if avg_s > 0 else 0.0}
+    if peaks:
+        out["frac_of_measured_copy"] = round(achieved / peaks["copy_GBps"], 4)
+        out["probe_frac_of_measured_4GiB_table"] = round(cand / avg_s / 1e9 / peaks["probe_4GiB_table_Gps"], 4)
+    if dom in ("gen_concat", "gen_star"):
+        # the fold over the guide table: per candidate S ANDs and S ORs of
+        # single bits (concatenation: a cut's prefix in x and suffix in y;
+        # star: one pass over cuts, shorter suffixes first)
+        k = rei.KERNEL_CLASSES.index(dom)
+        bits = sum(h.kernel_stats(k)[2] * 2 * guide_size(it) for h, it in zip(handles, insts))
+        rate = bits / max(1, d["launches"]) / avg_s if avg_s > 0 else 0.0
+        out["valu"] = {"bound": "alu", "achieved": round(rate / 1e12, 3), "peak": round(VALU_PEAK_BITOPS / 1e12, 1),
+                       "unit": "T bit-terms/s", "frac": round(rate / VALU_PEAK_BITOPS, 6),
+                       "bit_terms_per_launch": round(bits / max(1, d["launches"]))}
+        if peaks:
+            out["valu"]["frac_of_measured_bitwise"] = round(rate / 1e12 / peaks["bitwise_Tbitops"], 6)
+    return out
+
+
+def run_extra(rei, name, steps, stream):
+    """Another configuration in the same run: its value and step time (a
+    batch of the configuration's instances per step)."""
+    insts, desc, cache = workload(name)
+    hs = [rei.Instance(i.alphabet, i.pos, i.neg, i.costs, i.max_cost, cache) for i in insts]
+    rei.solve_batch(hs, stream)
+    tuned = rei.tune_batch(hs, stream)
+    res, el = timed(lambda: rei.solve_batch(hs, stream), steps)
+    uniq = sum(r.total_unique for batch in res for r in batch)
+    out = {"workload": desc, "value": round(uniq / el, 3), "unit": "languages/s",
+           "ms_per_step": round(el / steps * 1e3, 3), "instances_per_sec": round(len(hs) * steps / el, 1),
+           "batch_tuning": tuned}
+    for h in hs:
+        h.close()
+    return out
 
 
 def main():
@@ -90,18 +264,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="single")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--workload", default="large")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other configurations measured beside the headline")
     ap.add_argument("--max-errors", type=int, default=0)
-    ap.add_argument("--serving-requests", type=int, default=200,
-                    help="requests per serving run (0 = skip the serving measurement)")
+    ap.add_argument("--serving-requests", type=int, default=2000,
+                    help="arrivals per serving load point (0 = skip the serving sweep)")
     ap.add_argument("--sequential", action="store_true",
                     help="time rei_solve per instance as the step instead of rei_solve_batch")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the batched solver's tuning (profiling runs: every launch the same kind)")
-    ap.add_argument("--no-compare", action="store_true",
-                    help="do not also time the other mode (batched vs sequential)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before timing, copy this many MiB device to device once: a kernel of "
                          "known traffic that calibrates FETCH_SIZE / WRITE_SIZE counter runs")
@@ -116,12 +291,9 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU visible"
     torch.cuda.set_device(0)
-    insts, desc = workload(args.workload)
-    # the sweep mirrors the paper's 25 GB memory restriction and is timed per
-    # solve (its instances are not batchable: costs up to 30 per constructor)
-    cache = (25 << 30) if args.workload == "sweep" else (64 << 30)
+    insts, desc, cache = workload(args.workload)
     if args.workload == "sweep":
-        args.sequential = True
+        args.sequential = True  # 48 solves with 25 GB caches: one at a time, trimmed after each
     handles = []
     for it in insts:
         h = rei.Instance(it.alphabet, it.pos, it.neg, it.costs, it.max_cost, cache_bytes=cache)
@@ -137,51 +309,27 @@ def main():
         del src, dst
 
     def step_sequential():
-        if args.workload == "sweep":
-            # 48 solves with 25 GB caches do not fit HBM side by side: each
-            # instance frees its cache after its solve
-            out = []
-            for h in handles:
-                out.append(h.solve(stream))
+        out = []
+        for h in handles:
+            out.append(h.solve(stream))
+            if args.workload == "sweep":
                 h.trim()
-            return out
-        return [h.solve(stream) for h in handles]
+        return out
 
     def step_batch():
         return rei.solve_batch(handles, stream)
 
     step = step_sequential if args.sequential else step_batch
-
-    def timed(fn, k):
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        out = [fn() for _ in range(k)]
-        torch.cuda.synchronize()
-        return out, time.perf_counter() - t
-
     for _ in range(args.warmup):
         step()
     tuned = None
     if not args.sequential and args.warmup and not args.no_tune:
-        # launch shape of the batched solver, chosen by measurement (untimed)
-        tuned = rei.tune_batch(handles, stream)
+        tuned = rei.tune_batch(handles, stream)  # launch shapes chosen by measurement (untimed)
     # Python's cyclic collector scans every object torch created at import;
     # a full pass inside the timed region costs tens of milliseconds that
     # belong to no step.  Objects made so far are moved out of its reach.
     gc.collect()
     gc.freeze()
-
-    def kernel_classes():
-        out = {}
-        for k, name in enumerate(rei.KERNEL_CLASSES):
-            n = ms = units = 0
-            for h in handles:
-                a, b, c = h.kernel_stats(k)
-                n += a
-                ms += b
-                units += c
-            out[name] = {"launches": n, "ms": ms, "units": units}
-        return out
 
     # One untimed step with the generator classes and the batched solver
     # timed names the dominant kernel; the timed steps then record events on
@@ -190,7 +338,7 @@ def main():
         h.set_profiling(True)
     step()
     torch.cuda.synchronize()
-    classes = kernel_classes()
+    classes = kernel_classes(rei, handles)
     gen = {k: v for k, v in classes.items() if k.startswith("gen_") or k == "solve_batch"}
     dom = max(gen, key=lambda k: gen[k]["ms"])
     for h in handles:
@@ -198,86 +346,43 @@ def main():
     results, elapsed = timed(step, args.steps)
     for h in handles:
         h.set_profiling(False)
-    other = step_batch if args.sequential else step_sequential
-    same = None
-    other_value = None
-    if not args.no_compare:
-        other()
-        other_results, other_elapsed = timed(other, args.steps)
-        key = lambda r: (r.status, r.cost, r.regex, tuple(r.unique), tuple(r.candidates))
-        same = all(key(a) == key(b) for ra, rb in zip(results, other_results) for a, b in zip(ra, rb))
-        other_value = sum(r.total_unique for batch in other_results for r in batch) / other_elapsed
 
     uniq = sum(r.total_unique for batch in results for r in batch)
     value = uniq / elapsed
-    solve_ms = sorted(r.seconds_solve * 1e3 for batch in results for r in batch)
+    last = results[-1]
+    ttm = sorted((r.seconds_stage + r.seconds_solve) * 1e3 for batch in results for r in batch)
 
-    def pct(p):
-        return solve_ms[min(len(solve_ms) - 1, int(p * len(solve_ms)))]
+    def pct(a, p):
+        return a[min(len(a) - 1, int(p * len(a)))]
 
-    # the dominant kernel's launches over the timed steps (HIP events)
-    d = kernel_classes()[dom]
-    avg_ms = d["ms"] / max(1, d["launches"])
-    bytes_per_launch = PROBE_BYTES * d["units"] / max(1, d["launches"])
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    traffic = TRAFFIC_BYTES.get((args.workload, dom)) if not args.max_errors else None
-    # the events a launch records also span its dispatch and completion; an
-    # empty kernel launched the same way shows how much (context for
-    # comparing with a kernel trace; achieved keeps the raw events)
-    overhead_us = rei.timing_overhead_us()
-    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
-                "algorithmic_bytes_per_launch": round(bytes_per_launch),
-                "avg_launch_us": round(avg_ms * 1e3, 3), "event_overhead_us": round(overhead_us, 3),
-                "launches": d["launches"],
-                "candidates_per_launch": round(d["units"] / max(1, d["launches"]), 1)}
+    per_instance = None
+    if len(insts) <= 16:
+        per_instance = [{"seed": it.seed, "ic": r.ic_size, "words": r.cs_words, "status": r.status,
+                         "cost": r.cost, "regex": r.regex, "first_level": r.first_level,
+                         "unique_per_level": r.unique, "candidates_per_level": r.candidates,
+                         "stage_ms": round(r.seconds_stage * 1e3, 3), "solve_ms": round(r.seconds_solve * 1e3, 3),
+                         "time_to_minimal_regex_ms": round((r.seconds_stage + r.seconds_solve) * 1e3, 3)}
+                        for it, r in zip(insts, last)]
+
+    peaks = None if args.no_peaks else measured_peaks(rei)
+    roof = roofline(rei, handles, insts, dom, peaks, args.workload, args.max_errors)
+    roof["event_overhead_us"] = round(rei.timing_overhead_us(), 3)
+    if peaks:
+        roof["measured_peaks"] = peaks
+
+    extras = None
+    if not args.no_extras and args.workload == "large":
+        extras = {"single": run_extra(rei, "single", 20, stream),
+                  "batched": run_extra(rei, "batched", 5, stream)}
 
     serving_out = None
     if args.serving_requests:
         from paper_2305_18575_amd import serving as S
-        specs = S.request_mix(2024, args.serving_requests)
-        hs = S.stage(rei, specs)
-        for h in hs:  # first solve allocates each instance's buffers
-            h.solve(stream)
-        base_arr = S.poisson_arrivals(2024, len(hs), 1.0)
-        seq_res, _, _ = S.run_sequential(rei, hs, base_arr * 0.0, stream)
-        # capacity of the sequential solver: requests per second of pure service
-        t = time.perf_counter()
-        for h in hs:
-            h.solve(stream)
-        capacity = len(hs) / (time.perf_counter() - t)
-        runs = []
-        for mult in (1.0, 2.0):
-            qps = capacity * mult
-            arr = base_arr / qps
-            res, lat, ips = S.run_served(rei, hs, arr, budget=128 << 30)
-            sres, slat, sips = S.run_sequential(rei, hs, arr, stream)
-            runs.append({"qps": round(qps, 2), "served": {"instances_per_sec": round(ips, 2),
-                                                          **{k: round(v, 3) for k, v in S.percentiles(lat).items()}},
-                         "sequential": {"instances_per_sec": round(sips, 2),
-                                        **{k: round(v, 3) for k, v in S.percentiles(slat).items()}},
-                         "identical_results": all(S.same(a, b) for a, b in zip(res, seq_res))})
-        serving_out = {"requests": len(hs), "mix": "60% plain / 30% large (max cost 10) / 10% single",
-                       "sequential_capacity_per_sec": round(capacity, 2), "runs": runs}
-        for h in hs:
-            h.close()
+        serving_out = S.sweep(rei, args.serving_requests, stream=stream)
 
     cpu = None
     if not args.no_cpu:
-        import oracle
-        threads = min(16, os.cpu_count() or 1)
-        t1 = time.perf_counter()
-        cu = 0
-        done = 0
-        while time.perf_counter() - t1 < args.cpu_seconds and done < 40 * len(insts):
-            it = insts[done % len(insts)]
-            r = oracle.solve(it.alphabet, it.pos, it.neg, it.costs, it.max_cost, 1 << 40,
-                             args.max_errors, threads)
-            cu += sum(r.unique)
-            done += 1
-        ct = time.perf_counter() - t1
-        cpu = {"value": round(cu / ct, 3), "unit": "languages/s", "cores": threads, "kind": "oracle",
-               "sample": f"{done} solves of the same instance list in order ({ct:.1f} s)"}
+        cpu = cpu_baseline(insts, cache, args.cpu_seconds, args.max_errors)
 
     line = {
         "metric": "unique languages enumerated/sec",
@@ -294,27 +399,22 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "instances_per_step": len(insts),
                    "mode": "rei_solve per instance" if args.sequential else "rei_solve_batch",
-                   "batch_tuning": tuned},
-        ("batched_value" if args.sequential else "sequential_value"):
-            None if other_value is None else round(other_value, 3),
-        "batched_over_sequential": None if other_value is None else
-            round((other_value / value) if args.sequential else (value / other_value), 3),
-        "identical_results": same,
+                   "cache_bytes": cache, "batch_tuning": tuned},
         "instances_per_sec": round(len(insts) * args.steps / elapsed, 3),
-        "time_to_minimal_regex_ms": {"mean": round(sum(solve_ms) / len(solve_ms), 4),
-                                     "p50": round(pct(0.5), 4), "p99": round(pct(0.99), 4)},
-        "roofline": roofline,
+        "time_to_minimal_regex_ms": {"definition": "rei_create + rei_solve (stage + solve)",
+                                     "mean": round(sum(ttm) / len(ttm), 4),
+                                     "p50": round(pct(ttm, 0.5), 4), "p99": round(pct(ttm, 0.99), 4)},
+        "per_instance": per_instance,
+        "roofline": roof,
+        "other_configs": extras,
         "serving": serving_out,
         "cpu_baseline": cpu,
-        # every generator class and the batched solver, from the untimed
-        # profiled step before the timed ones
         "kernels_profiled_step": {k: {"launches": v["launches"], "ms": round(v["ms"], 3), "units": v["units"]}
-                                  for k, v in classes.items()},
+                                  for k, v in classes.items() if v["launches"]},
     }
     if args.workload == "sweep":
-        # per cost function, as in the paper's cost-function comparison
         per = {}
-        for it, r in zip(insts, results[-1]):
+        for it, r in zip(insts, last):
             d = per.setdefault(",".join(map(str, it.costs)), {"solves": 0, "ok": 0, "out_of_memory": 0,
                                                                "seconds": 0.0, "candidates": 0})
             d["solves"] += 1
@@ -323,8 +423,7 @@ def main():
             d["seconds"] = round(d["seconds"] + r.seconds_solve, 4)
             d["candidates"] += sum(r.candidates)
         line["per_cost_function"] = per
-        tot_c = sum(sum(r.candidates) for r in results[-1])
-        line["candidates_per_sec"] = round(tot_c / (elapsed / args.steps), 1)
+    line["candidates_per_sec"] = round(sum(sum(r.candidates) for r in last) / (elapsed / args.steps), 1)
     print(json.dumps(line), flush=True)
     for h in handles:
         h.close()

@@ -66,7 +66,10 @@ typedef struct {
 
 typedef struct rei_instance rei_instance;
 
-/* Stage one specification.
+/* Stage one specification (Sec. 3, Definition of specification: a pair of
+ * finite sets of positive and negative strings; Definition of cost
+ * homomorphism; the staging of Sec. 3: infix closure, shortlex order, guide
+ * table of all cuts of each infix, P/N masks).
  *   alphabet    distinct bytes in 0x01..0x7f, none of ( ) + * ? ; its order
  *               is the shortlex character order and the level-c_char order.
  *   pos, neg    n_pos / n_neg NUL-terminated strings ("" is the empty word);
@@ -102,13 +105,21 @@ typedef struct {
   double seconds_solve;      /* rei_solve wall time                             */
 } rei_result;
 
-/* Run the search on `hip_stream` (a hipStream_t; NULL = the null stream).
+/* Run the search (Algorithm 1: levels by increasing cost, each built from
+ * the cached lower levels with ?, *, concatenation (Algorithm 2) and union,
+ * new languages kept once, stop at the first precise one; Sec. 3, "GPU
+ * language cache implementation", "Uniqueness checking") on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).
  * Blocks until the search ends.  Repeated calls restart from scratch and give
  * identical results. */
 rei_status rei_solve(rei_instance *inst, void *hip_stream, rei_result *out);
 
-/* Solve n instances together: instances with at most 8 words per language
- * and max_cost <= 63 run in one launch per word width (the launches run side
+/* Solve n independent specifications together, each by Algorithm 1 as in
+ * rei_solve (the batched configuration: many small uneven instances in one
+ * call).  Instances with at most 32 words per language (and a guide table
+ * of at most 6144 cuts up to 8 words, 12288 beyond), equal character costs,
+ * OnTheFly mode off and max_cost <= 63 run in one launch per word width
+ * (the launches run side
  * by side), one workgroup per instance executing the whole level loop on the
  * device (no host round trip per level or chunk; the answer's expression
  * tree is decoded there too).  An instance whose next level has more
@@ -133,10 +144,50 @@ rei_status rei_solve(rei_instance *inst, void *hip_stream, rei_result *out);
 rei_status rei_solve_batch(rei_instance *const *insts, size_t n, void *hip_stream, uint64_t arena_bytes,
                            rei_result *out);
 
+/* ---- the batched configuration as one captured graph -------------------------
+ * For a fixed set of instances solved again and again (a workload replayed
+ * step after step): the batched solver's launches are captured once in a
+ * hipGraph and each step is one graph launch.  Every batchable instance
+ * (as for rei_solve_batch) keeps its whole search inside the launch: a
+ * persistent grid per word width, its workgroups taking instances from a
+ * device counter, longest first (their work measured by one eager run at
+ * creation), the device's resident workgroups shared between the widths in
+ * proportion to their work.  Results equal rei_solve's for every instance.
+ *
+ * rei_batch_graph_create   prepares every instance's arena (arena_bytes as
+ *                          for rei_solve_batch, 0 = 16 MiB), runs the
+ *                          launches once to measure, captures the graph.
+ *                          The instances (all on the current device) belong
+ *                          to the graph until it is destroyed: do not solve
+ *                          them otherwise meanwhile.  Trivial
+ *                          specifications are answered at results time,
+ *                          instances that cannot be batched run rei_solve's
+ *                          path then.
+ * rei_batch_graph_launch   enqueues one replay on hip_stream (NULL = the
+ *                          null stream) and returns; the previous replay's
+ *                          results must have been collected.
+ * rei_batch_graph_results  waits for the replay and writes n results (owned
+ *                          by the instances, as for rei_solve; seconds_solve
+ *                          = time from the launch call until the instance's
+ *                          completion flag showed).  An instance that
+ *                          outgrew its preallocated rows is solved again on
+ *                          rei_solve's path and gets an arena that holds its
+ *                          rows for the next replays.
+ * rei_batch_graph_error    the message of the last failure ("" if none).
+ * rei_batch_graph_destroy  waits for a replay in flight, frees the graph. */
+typedef struct rei_batch_graph rei_batch_graph;
+rei_status rei_batch_graph_create(rei_instance *const *insts, size_t n, uint64_t arena_bytes,
+                                  rei_batch_graph **out);
+rei_status rei_batch_graph_launch(rei_batch_graph *g, void *hip_stream);
+rei_status rei_batch_graph_results(rei_batch_graph *g, rei_result *out);
+const char *rei_batch_graph_error(const rei_batch_graph *g);
+void rei_batch_graph_destroy(rei_batch_graph *g);
+
 /* Autotuner of rei_solve_batch, by whole calls (what the caller waits for,
  * hand-offs included), each setting timed as the shortest of five calls.
  * First the launch shape: every word-width group at 256, 512, then 1024
- * threads per instance (at most 512 with 8 words per language); the fastest
+ * threads per instance (at most 512 with 8 or 16 words per language, 256
+ * with 32); the fastest
  * is kept, for each group present, for groups of its size (by power-of-two
  * size class) in a table of the process that later rei_solve_batch calls on
  * any thread use.  Without an entry, a group gets enough waves per instance
@@ -144,17 +195,48 @@ rei_status rei_solve_batch(rei_instance *const *insts, size_t n, void *hip_strea
  * instances that did not set rei_set_batch_level): 2^13 .. 2^19 candidates,
  * the fastest becomes the process default (2^16 until then).  Other
  * rei_solve_batch calls running meanwhile also take the shape being timed.
- * Results do not depend on either choice.  threads_out (NULL or 5 entries,
- * for W = 1 with keys in the table slots, then W = 1, 2, 4, 8) receives the
+ * Results do not depend on either choice.  threads_out (NULL or 7 entries,
+ * for W = 1 with keys in the table slots, then W = 1, 2, 4, 8, 16, 32)
+ * receives the
  * chosen sizes, 0 for groups without instances; level_max_out (NULL or 1
  * entry) the level size.  The instances end up solved, as by
  * rei_solve_batch. */
 rei_status rei_tune_batch(rei_instance *const *insts, size_t n, void *hip_stream, uint64_t arena_bytes,
                           uint32_t *threads_out, uint64_t *level_max_out);
 
+/* Autotuner of rei_solve's per-chunk path, by whole solves: for the
+ * instances of each word width present, the first chunk of a level
+ * (2^14 .. 2^18 candidates; each next chunk doubles), the largest chunk
+ * (2^20 .. 2^24), and the concatenation kernel's grid target (512 .. 8192
+ * workgroups) and left rows per workgroup (4 .. 64), one parameter after
+ * the other, each value timed as the best of three passes of rei_solve over
+ * the width's instances on hip_stream.  The fastest set is kept per word
+ * width in a table of the process that later solves of any instance of that
+ * width use.  Results do not depend on these parameters.  params_out (NULL
+ * or 24 entries: W = 1, 2, 4, 8, 16, 32, each first_chunk, chunk_max,
+ * concat_wg, concat_xi; 0 for widths absent) receives the choice.  The
+ * instances end up solved, as by rei_solve. */
+rei_status rei_tune_grid(rei_instance *const *insts, size_t n, void *hip_stream, uint64_t *params_out);
+/* The per-chunk path's launch parameters for one instance, overriding the
+ * tuned table for its width (0 = keep the table's or the default value for
+ * that field; defaults 2^16, 2^24, 2048, 16).  concat_xi at most 64.
+ * Results do not depend on them; tests vary them to check that. */
+rei_status rei_set_grid_tuning(rei_instance *inst, uint64_t first_chunk, uint64_t chunk_max,
+                               uint32_t concat_wg, uint32_t concat_xi);
+/* The process's tuning tables (rei_tune_batch's launch shapes and hand-off
+ * size, rei_tune_grid's parameters) written to a JSON file, or read back
+ * from one (entries read replace those of the same key; a file with an
+ * entry out of range is rejected whole).  A process whose environment sets
+ * REI_TUNE_FILE loads that file when its first instance is created.
+ * REI_ERR_INVALID_ARG when the file cannot be written or read or parsed. */
+rei_status rei_tune_save(const char *path);
+rei_status rei_tune_load(const char *path);
+
 /* ---- serving: continuous batching ------------------------------------------
  * A server solves submitted instances asynchronously.  Requests are admitted
- * in arrival order while the device bytes they need fit hbm_budget; admitted
+ * in arrival order while the device bytes they need fit hbm_budget (0 = the
+ * device's free memory when the server is created, less 8 GB kept for
+ * everything else); admitted
  * requests that can be batched (as in rei_solve_batch) are launched together
  * on a free stream from a pool of n_streams, so requests arriving while others
  * run are started at once and their work overlaps on the device; the others
@@ -264,7 +346,11 @@ rei_status rei_set_char_costs(rei_instance *inst, const uint32_t *costs, size_t 
  * search without a cap.  unique_per_level counts stored languages only.
  * Instances with it on are solved on rei_solve's path by rei_solve_batch. */
 rei_status rei_set_on_the_fly(rei_instance *inst, int enable);
-/* Misclassified examples allowed (REI with error, Sec. 7); 0 = precise. */
+/* Misclassified examples allowed (REI with error: Sec. 5.2, Future Work,
+ * where an expression may misclassify a given share of the examples and
+ * the allowed-error table shows the effect on the Table 1 row 1
+ * specification); 0 = precise.  An expression is then accepted when it
+ * misclassifies at most max_errors examples of P u N. */
 rei_status rei_set_max_errors(rei_instance *inst, uint32_t max_errors);
 
 /* Kernel classes timed with HIP events when profiling is on. */
@@ -310,6 +396,36 @@ rei_status rei_set_hash_bits(uint32_t bits);
  * the launch, which an external kernel trace leaves out), in microseconds.
  * Creates and destroys a stream of its own.  For reading the statistics. */
 rei_status rei_timing_overhead(double *us);
+/* Achievable peaks on the current device, for reading the roofline figures
+ * of the kernels against measured rates as well as published ones.  Each is
+ * the best of five timed launches (after one warm-up) of a kernel built for
+ * the purpose, on a stream of its own; buffers are allocated and freed
+ * inside the call.
+ *   REI_PEAK_COPY         copy `size` bytes with 16-byte loads and stores:
+ *                         *rate = bytes read + bytes written per second;
+ *   REI_PEAK_PROBE        2^27 reads of 8-byte slots at pseudo-random
+ *                         positions of a table of `size` bytes (rounded down
+ *                         to a power of two; a table larger than the
+ *                         device's caches makes every probe an HBM access,
+ *                         as a dedup-table probe is): *rate = probes per
+ *                         second;
+ *   REI_PEAK_PROBE_ATOMIC as REI_PEAK_PROBE, each probe followed by a 64-bit
+ *                         atomicMin on another pseudo-random slot (the claim
+ *                         of a new language): *rate = probes per second;
+ *   REI_PEAK_BITWISE      a loop of fused 32-bit AND-OR operations on every
+ *                         lane of a full device (size ignored): *rate =
+ *                         32-bit bitwise operations per second (each fused
+ *                         instruction counts two).
+ * *seconds = the best launch's duration.  REI_ERR_INVALID_ARG for an
+ * unknown kind or a size under 4096 bytes; REI_ERR_DEVICE when a HIP call
+ * fails (for example a table that does not fit the device). */
+typedef enum {
+  REI_PEAK_COPY = 0,
+  REI_PEAK_PROBE = 1,
+  REI_PEAK_PROBE_ATOMIC = 2,
+  REI_PEAK_BITWISE = 3
+} rei_peak_kind;
+rei_status rei_measure_peak(rei_peak_kind kind, uint64_t size, double *rate, double *seconds);
 /* Kernel symbol name of a class (for matching profiler output). */
 const char *rei_kernel_name(rei_kernel_class k);
 

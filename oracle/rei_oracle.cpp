@@ -45,7 +45,7 @@
 //
 // Trivial specifications (Algorithm 1): P = {} gives the empty language,
 // P = {eps} gives eps, both at cost c1.  With an allowed error of k
-// misclassified examples (REI with error, Sec. 7) these read: the empty
+// misclassified examples (REI with error, Sec. 5.2, Future Work) these read: the empty
 // language if |P| <= k, else eps if it misclassifies at most k examples.
 //
 // Per-character costs (the cost-homomorphism definition allows a different

@@ -31,7 +31,10 @@ EXPORTS = ["rei_create", "rei_solve", "rei_solve_batch", "rei_tune_batch", "rei_
            "rei_server_poll", "rei_server_destroy", "rei_set_allocator", "rei_trim", "rei_destroy", "rei_status_str", "rei_last_error",
            "rei_create_error", "rei_ic_word", "rei_level_size", "rei_row_bits",
            "rei_row_regex", "rei_set_chunk", "rei_set_batch_level", "rei_set_batch_time", "rei_set_on_the_fly", "rei_set_char_costs", "rei_set_max_errors", "rei_set_profiling", "rei_set_profiling_class",
-           "rei_kernel_stats", "rei_timing_overhead", "rei_set_hash_bits", "rei_kernel_name"]
+           "rei_kernel_stats", "rei_timing_overhead", "rei_set_hash_bits", "rei_kernel_name",
+           "rei_measure_peak", "rei_batch_graph_create", "rei_batch_graph_launch", "rei_batch_graph_results",
+           "rei_batch_graph_error", "rei_batch_graph_destroy", "rei_tune_grid", "rei_set_grid_tuning",
+           "rei_tune_save", "rei_tune_load"]
 
 
 class ReiError(RuntimeError):
@@ -143,6 +146,27 @@ def load_library():
     lib.rei_set_allocator.restype = ctypes.c_int
     lib.rei_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, vp]
     lib.rei_kernel_name.argtypes = [ctypes.c_int]
+    lib.rei_batch_graph_create.restype = ctypes.c_int
+    lib.rei_batch_graph_create.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, u64, ctypes.POINTER(vp)]
+    lib.rei_batch_graph_launch.restype = ctypes.c_int
+    lib.rei_batch_graph_launch.argtypes = [vp, vp]
+    lib.rei_batch_graph_results.restype = ctypes.c_int
+    lib.rei_batch_graph_results.argtypes = [vp, ctypes.POINTER(_Result)]
+    lib.rei_batch_graph_error.restype = cp
+    lib.rei_batch_graph_error.argtypes = [vp]
+    lib.rei_batch_graph_destroy.restype = None
+    lib.rei_batch_graph_destroy.argtypes = [vp]
+    lib.rei_tune_grid.restype = ctypes.c_int
+    lib.rei_tune_grid.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, vp, ctypes.POINTER(u64)]
+    lib.rei_set_grid_tuning.restype = ctypes.c_int
+    lib.rei_set_grid_tuning.argtypes = [vp, u64, u64, u32, u32]
+    lib.rei_tune_save.restype = ctypes.c_int
+    lib.rei_tune_save.argtypes = [cp]
+    lib.rei_tune_load.restype = ctypes.c_int
+    lib.rei_tune_load.argtypes = [cp]
+    lib.rei_measure_peak.restype = ctypes.c_int
+    lib.rei_measure_peak.argtypes = [ctypes.c_int, u64, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
     _lib = lib
     return lib
 
@@ -266,6 +290,11 @@ class Instance:
         (-1 = default, 0 = never on time)."""
         self._check(self._lib.rei_set_batch_time(self._h, int(microseconds)))
 
+    def set_grid_tuning(self, first_chunk: int = 0, chunk_max: int = 0, concat_wg: int = 0, concat_xi: int = 0):
+        """Per-chunk path launch parameters of this instance (0 = tuned or default)."""
+        self._check(self._lib.rei_set_grid_tuning(self._h, int(first_chunk), int(chunk_max), int(concat_wg),
+                                                  int(concat_xi)))
+
     def set_max_errors(self, k: int):
         self._check(self._lib.rei_set_max_errors(self._h, int(k)))
 
@@ -335,15 +364,47 @@ def tune_batch(instances: Sequence["Instance"], stream: Optional[int] = -1,
         stream = current_stream_handle()
     n = len(instances)
     hs = (ctypes.c_void_p * n)(*[i._h for i in instances])
-    out = (ctypes.c_uint32 * 5)()
+    out = (ctypes.c_uint32 * 7)()
     lm = ctypes.c_uint64()
     st = lib.rei_tune_batch(hs, n, ctypes.c_void_p(stream or 0), int(arena_bytes), out, ctypes.byref(lm))
     if st != 0:
         msg = "; ".join(sorted({lib.rei_last_error(i._h).decode() for i in instances} - {""}))
         raise ReiError(st, msg)
-    names = ["W1-inline", "W1", "W2", "W4", "W8"]
-    shape = {names[k]: int(out[k]) for k in range(5) if out[k]}
+    names = ["W1-inline", "W1", "W2", "W4", "W8", "W16", "W32"]
+    shape = {names[k]: int(out[k]) for k in range(7) if out[k]}
     return {"threads_per_instance": shape, "level_max": int(lm.value)}
+
+
+def tune_grid(instances: Sequence["Instance"], stream: Optional[int] = -1) -> dict:
+    """``rei_tune_grid``: per word width of the instances, the per-chunk
+    path's launch parameters chosen by timing rei_solve; returns
+    {"W<k>": {"first_chunk", "chunk_max", "concat_wg", "concat_xi"}}."""
+    lib = load_library()
+    if stream == -1:
+        stream = current_stream_handle()
+    n = len(instances)
+    hs = (ctypes.c_void_p * n)(*[i._h for i in instances])
+    out = (ctypes.c_uint64 * 24)()
+    st = lib.rei_tune_grid(hs, n, ctypes.c_void_p(stream or 0), out)
+    if st != 0:
+        msg = "; ".join(sorted({lib.rei_last_error(i._h).decode() for i in instances} - {""}))
+        raise ReiError(st, msg)
+    names = ("first_chunk", "chunk_max", "concat_wg", "concat_xi")
+    return {f"W{1 << k}": {names[j]: int(out[4 * k + j]) for j in range(4)} for k in range(6) if out[4 * k]}
+
+
+def tune_save(path: str):
+    """``rei_tune_save``: the process's tuning tables to a JSON file."""
+    st = load_library().rei_tune_save(path.encode())
+    if st != 0:
+        raise ReiError(st, f"rei_tune_save({path})")
+
+
+def tune_load(path: str):
+    """``rei_tune_load``: tuning tables from a JSON file."""
+    st = load_library().rei_tune_load(path.encode())
+    if st != 0:
+        raise ReiError(st, f"rei_tune_load({path})")
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -409,11 +470,77 @@ def timing_overhead_us() -> float:
     return v.value
 
 
+class BatchGraph:
+    """``rei_batch_graph_*``: a fixed set of staged instances whose batched
+    solve is captured once as a graph; ``launch`` enqueues a replay,
+    ``results`` waits for it and returns the results in the instances' order."""
+
+    def __init__(self, instances: Sequence["Instance"], arena_bytes: int = 0):
+        lib = load_library()
+        self._lib = lib
+        self._insts = list(instances)
+        n = len(self._insts)
+        hs = (ctypes.c_void_p * max(1, n))(*[i._h for i in self._insts])
+        h = ctypes.c_void_p()
+        st = lib.rei_batch_graph_create(hs, n, int(arena_bytes), ctypes.byref(h))
+        if st != 0:
+            msg = "; ".join(sorted({lib.rei_last_error(i._h).decode() for i in self._insts} - {""}))
+            raise ReiError(st, msg or "rei_batch_graph_create")
+        self._h = h
+
+    def _check(self, st):
+        if st != 0:
+            raise ReiError(st, self._lib.rei_batch_graph_error(self._h).decode())
+
+    def launch(self, stream: Optional[int] = -1):
+        if stream == -1:
+            stream = current_stream_handle()
+        self._check(self._lib.rei_batch_graph_launch(self._h, ctypes.c_void_p(stream or 0)))
+
+    def results(self) -> List[Result]:
+        n = len(self._insts)
+        rs = (_Result * max(1, n))()
+        self._check(self._lib.rei_batch_graph_results(self._h, rs))
+        return [inst._result(rs[k]) for k, inst in enumerate(self._insts)]
+
+    def run(self, stream: Optional[int] = -1) -> List[Result]:
+        self.launch(stream)
+        return self.results()
+
+    def close(self):
+        if self._h:
+            self._lib.rei_batch_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+PEAK_KINDS = {"copy": 0, "probe": 1, "probe_atomic": 2, "bitwise": 3}
+
+
+def measure_peak(kind: str, size: int = 0):
+    """``rei_measure_peak``: (rate, seconds) of one achievable-peak kernel:
+    copy (bytes read + written / s), probe / probe_atomic (random table probes
+    / s over a table of ``size`` bytes), bitwise (32-bit bitwise ops / s)."""
+    lib = load_library()
+    rate, sec = ctypes.c_double(), ctypes.c_double()
+    st = lib.rei_measure_peak(PEAK_KINDS[kind], int(size), ctypes.byref(rate), ctypes.byref(sec))
+    if st != 0:
+        raise ReiError(st, f"rei_measure_peak({kind})")
+    return rate.value, sec.value
+
+
 class Server:
     """Continuous-batching server (``rei_server_*``): submit staged instances,
     poll or wait for their results."""
 
-    def __init__(self, hbm_budget: int, max_batch: int = 64, n_streams: int = 4, n_workers: int = 4):
+    def __init__(self, hbm_budget: int = 0, max_batch: int = 64, n_streams: int = 4, n_workers: int = 4):
+        """hbm_budget: device bytes the requests in flight may hold (0 = the
+        free device memory at creation less 8 GB)."""
         lib = load_library()
         self._lib = lib
         h = ctypes.c_void_p()

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librei.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("stage.cpp", "kernels.hip", "batch.hip", "driver.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("stage.cpp", "kernels.hip", "batch.hip", "peaks.hip", "driver.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -5,6 +5,8 @@
 // needed per level or chunk.  Results are bit-identical to the per-chunk grid
 // path: the same enumeration order, the same deterministic winner rule
 // (smallest enumeration index), the same ordered append.
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace rei {
@@ -117,13 +119,21 @@ __device__ __forceinline__ bool decode_index(const BatchDesc& d, const uint64_t*
   return false;
 }
 
-// kT threads per instance (256, 512 or 1024; at most 512 when a language
-// has 8 words, so that the per-wave operand tiles stay within 32 KB of LDS):
+// kT threads per instance (256, 512 or 1024; at most batch_max_threads(W),
+// so that the per-wave operand tiles and the guide table fit the LDS):
 // many waves shorten one instance's search, few let more instances share a
 // CU.  The host picks kT per launch (tuned or from the batch size).
+// Two launch forms.  next == nullptr: workgroup b solves instance b.
+// Persistent (next != nullptr): a grid of at most the resident workgroups;
+// each takes the next item from the device counter *next (zero at launch)
+// and solves instance order[item] (or item itself when order is null),
+// until the items run out, so the longest instances can start first
+// whatever the grid size.
 template <int W, bool kInl, uint32_t kT>
-__global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32_t n_inst) {
-  static_assert(kT >= kBatchChunk / 32 && kT <= 1024 && kT % 64 == 0, "one scan value per thread");
+__global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32_t n_inst, const uint32_t* order,
+                                                  uint32_t* next) {
+  static_assert(kT >= kBatchChunk / 32 && kT <= batch_max_threads(W) && kT % 64 == 0, "one scan value per thread");
+  constexpr uint32_t kIc = batch_max_ic(W), kPairs = batch_max_pairs(W);
   constexpr uint32_t kWaves = kT / 64;
   __shared__ uint64_t s_lstart[kBatchMaxCost + 2], s_lcount[kBatchMaxCost + 2];
   __shared__ uint64_t s_uniq[kBatchMaxCost + 2], s_cand[kBatchMaxCost + 2];
@@ -136,10 +146,23 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
   __shared__ uint32_t s_winners;
   __shared__ uint64_t s_tile[kWaves][64 * W];
   __shared__ uint64_t s_uni[kWaves][W];
-  __shared__ uint32_t s_gto[kBatchMaxIc + 1], s_gtp[kBatchMaxPairs], s_lo[kBatchMaxIc + 2];
+  __shared__ uint32_t s_gto[kIc + 1], s_gtp[kPairs], s_lo[kIc + 2];
+  __shared__ uint32_t s_item;
 
-  if (blockIdx.x >= n_inst) return;
-  const BatchDesc d = descs[blockIdx.x];
+  for (uint32_t pass = 0;; ++pass) {
+  uint32_t item;
+  if (!next) {
+    if (pass || blockIdx.x >= n_inst) return;
+    item = blockIdx.x;
+  } else {
+    if (threadIdx.x == 0) s_item = atomicAdd(next, 1u);
+    __syncthreads();
+    item = s_item;
+    __syncthreads();  // read by every wave before thread 0 writes the next one
+    if (item >= n_inst) return;
+    if (order) item = order[item];
+  }
+  const BatchDesc d = descs[item];
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // The dedup table starts small and grows (cleared and rebuilt from the
   // stored rows) while rows accumulate, up to the arena's slot_mask: a
@@ -154,7 +177,7 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
     if (kInl) d.sref[i] = kEmpty;
   }
   // guide table and words-by-length offsets into LDS (batchable instances
-  // have at most kBatchMaxIc words and kBatchMaxPairs cuts)
+  // have at most batch_max_ic(W) words and batch_max_pairs(W) cuts)
   for (uint32_t i = tid; i <= d.n; i += kT) s_gto[i] = d.gt_off[i];
   for (uint32_t i = tid; i < d.n_pairs; i += kT) s_gtp[i] = d.gt_pair[i];
   for (uint32_t i = tid; i < d.max_len + 2; i += kT) s_lo[i] = d.len_off[i];
@@ -552,6 +575,13 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
   __threadfence_system();
   __syncthreads();
   if (tid == 0) __hip_atomic_store(&d.hst->done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }  // next instance
+}
+
+// Puts the work counters of the persistent launches back to zero (a kernel,
+// so that it can sit in a captured graph).
+__global__ void reset_counters(uint32_t* c, uint32_t n) {
+  if (threadIdx.x < n) c[threadIdx.x] = 0;
 }
 
 }  // namespace
@@ -561,17 +591,20 @@ hipError_t set_hash_mask_batch(uint64_t mask) {
 }
 
 hipError_t launch_solve_batch(int W, bool inl, uint32_t threads, const BatchDesc* d_descs, uint32_t n,
-                              hipStream_t s) {
+                              hipStream_t s, const uint32_t* order, uint32_t* next, uint32_t grid) {
   if (n == 0) return hipSuccess;
-#define REI_BATCH_T(WW, II)                                                                                  \
-  switch (threads) {                                                                                         \
-    case 256: launch_timed(solve_batch<WW, II, 256>, dim3(n), dim3(256), 0, s, d_descs, n); break;         \
-    case 512: launch_timed(solve_batch<WW, II, 512>, dim3(n), dim3(512), 0, s, d_descs, n); break;         \
-    case 1024:                                                                                               \
-      if (WW > 4) return hipErrorInvalidValue;                                                               \
-      launch_timed(solve_batch<WW, II, (WW > 4 ? 512u : 1024u)>, dim3(n), dim3(1024), 0, s, d_descs, n);   \
-      break;                                                                                                 \
-    default: return hipErrorInvalidValue;                                                                    \
+  if (!next) grid = n;
+  if (grid == 0 || grid > n) return hipErrorInvalidValue;
+#define REI_BATCH_L(WW, II, TT)                                                                          \
+  launch_timed(solve_batch<WW, II, std::min(TT, batch_max_threads(WW))>, dim3(grid), dim3(TT), 0, s, d_descs, n, \
+               order, next)
+#define REI_BATCH_T(WW, II)                                              \
+  if (threads > batch_max_threads(WW)) return hipErrorInvalidValue;      \
+  switch (threads) {                                                     \
+    case 256: REI_BATCH_L(WW, II, 256u); break;                          \
+    case 512: REI_BATCH_L(WW, II, 512u); break;                          \
+    case 1024: REI_BATCH_L(WW, II, 1024u); break;                        \
+    default: return hipErrorInvalidValue;                                \
   }
   switch (W) {
     case 1:
@@ -584,9 +617,53 @@ hipError_t launch_solve_batch(int W, bool inl, uint32_t threads, const BatchDesc
     case 2: REI_BATCH_T(2, false) break;
     case 4: REI_BATCH_T(4, false) break;
     case 8: REI_BATCH_T(8, false) break;
+    case 16: REI_BATCH_T(16, false) break;
+    case 32: REI_BATCH_T(32, false) break;
     default: return hipErrorInvalidValue;
   }
+#undef REI_BATCH_L
 #undef REI_BATCH_T
+  return hipGetLastError();
+}
+
+hipError_t batch_resident(int W, bool inl, uint32_t threads, uint32_t* per_cu) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+#define REI_OCC_L(WW, II, TT)                                                                          \
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, solve_batch<WW, II, std::min(TT, batch_max_threads(WW))>, \
+                                                   (int)TT, 0)
+#define REI_OCC(WW, II)                                              \
+  if (threads > batch_max_threads(WW)) return hipErrorInvalidValue;  \
+  switch (threads) {                                                 \
+    case 256: REI_OCC_L(WW, II, 256u); break;                        \
+    case 512: REI_OCC_L(WW, II, 512u); break;                        \
+    case 1024: REI_OCC_L(WW, II, 1024u); break;                      \
+    default: return hipErrorInvalidValue;                            \
+  }
+  switch (W) {
+    case 1:
+      if (inl) {
+        REI_OCC(1, true)
+      } else {
+        REI_OCC(1, false)
+      }
+      break;
+    case 2: REI_OCC(2, false) break;
+    case 4: REI_OCC(4, false) break;
+    case 8: REI_OCC(8, false) break;
+    case 16: REI_OCC(16, false) break;
+    case 32: REI_OCC(32, false) break;
+    default: return hipErrorInvalidValue;
+  }
+#undef REI_OCC_L
+#undef REI_OCC
+  if (e == hipSuccess) *per_cu = (uint32_t)std::max(nb, 1);
+  return e;
+}
+
+hipError_t launch_reset_counters(uint32_t* c, uint32_t n, hipStream_t s) {
+  if (n == 0 || n > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, c, n);
   return hipGetLastError();
 }
 

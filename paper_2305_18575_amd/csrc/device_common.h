@@ -10,6 +10,8 @@ namespace {
 
 constexpr int kWave = 64;
 
+// 64-bit finalizer of MurmurHash3 (fmix64, Austin Appleby's published
+// constants): every input bit affects every output bit.
 __device__ __forceinline__ uint64_t mix64(uint64_t x) {
   x ^= x >> 33;
   x *= 0xff51afd7ed558ccdull;

@@ -11,6 +11,8 @@
 #include <mutex>
 #include <thread>
 #include <unordered_map>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -29,7 +31,6 @@ namespace {
 thread_local std::string g_create_error;
 
 constexpr uint64_t kDefaultChunk = 1ull << 24;
-constexpr uint64_t kFirstChunk = 1ull << 16;  // first chunk of a level; each next one doubles
 constexpr uint64_t kDefaultArena = 16ull << 20;  // bytes per batched instance
 
 struct Block {
@@ -69,6 +70,9 @@ struct rei_instance {
   uint64_t row_cap = 0;
   uint32_t max_err = 0;
   uint64_t chunk_max = kDefaultChunk;
+  // grid-path launch parameters set for this instance (0: the process table
+  // for its word width, else the defaults)
+  GridTune grid_set{0, 0, 0, 0};
   uint64_t batch_level_max = 0;  // 0: the tuned value, else kBatchLevelMax
   int64_t batch_time_us = -1;    // -1: kBatchTimeUs; 0: no hand-off on time
   int device = 0;
@@ -193,6 +197,13 @@ void dfree(const rei_instance* in, T*& p) {
   }
   p = nullptr;
 }
+
+// Grid-path launch parameters by word width, from rei_tune_grid or a tuning
+// file; widths without an entry use GridTune's defaults.
+std::mutex g_grid_mu;
+std::map<int, GridTune> g_grid_tuned;
+
+GridTune grid_params(const rei_instance* in);
 
 uint64_t pow2_at_least(uint64_t x) {
   uint64_t p = 1;
@@ -355,6 +366,20 @@ void chars_at(const rei_instance* in, int64_t c, uint32_t* first, uint32_t* coun
   }
 }
 
+GridTune grid_params(const rei_instance* in) {
+  GridTune t;
+  {
+    std::lock_guard<std::mutex> lk(g_grid_mu);
+    auto it = g_grid_tuned.find(in->st.W);
+    if (it != g_grid_tuned.end()) t = it->second;
+  }
+  if (in->grid_set.first_chunk) t.first_chunk = in->grid_set.first_chunk;
+  if (in->grid_set.chunk_max) t.chunk_max = in->grid_set.chunk_max;
+  if (in->grid_set.concat_wg) t.concat_wg = in->grid_set.concat_wg;
+  if (in->grid_set.concat_xi) t.concat_xi = in->grid_set.concat_xi;
+  return t;
+}
+
 uint64_t level_n(const rei_instance* in, int64_t c) {
   if (c < (int64_t)in->costs.c_char || c >= (int64_t)in->lcount.size()) return 0;
   return in->lcount[c];
@@ -478,6 +503,11 @@ rei_status enqueue_chunk(rei_instance* in, hipStream_t s, uint32_t c, const std:
   g.n_pairs = (uint32_t)in->st.gt_pair.size();
   g.st = in->d_state;
   g.inl = in->inl ? 1u : 0u;
+  {
+    const GridTune gt = grid_params(in);
+    g.concat_wg = gt.concat_wg;
+    g.concat_xi = gt.concat_xi;
+  }
   // small pieces (W <= kPiecesMaxW) share gen_pieces launches of up to
   // kMaxPieces pieces; larger ones get their constructor's kernel
   PieceArgs pa{};
@@ -916,12 +946,15 @@ rei_status search_levels(rei_instance* in, hipStream_t s) {
       return REI_ERR_TOO_LARGE;
     }
     // chunks of consecutive level indices: large blocks are split, small
-    // ones share a chunk.  Chunks grow from kFirstChunk to chunk_max within a
+    // ones share a chunk.  Chunks grow from the first chunk size to the
+    // largest (grid_params, capped by rei_set_chunk) within a
     // level: an answer early in a large level ends it after a few small
     // chunks (later chunks see the stop flag and exit at once), while a level
     // without one costs a handful of extra launches.
     uint64_t e_base = 0, acc = 0;
-    uint64_t cur = std::min(in->chunk_max, kFirstChunk);
+    const GridTune gt = grid_params(in);
+    const uint64_t cmax = std::max<uint64_t>(1, std::min(in->chunk_max, gt.chunk_max));
+    uint64_t cur = std::min(cmax, gt.first_chunk);
     std::vector<Piece> pieces;
     for (const Block& b : blocks) {
       for (uint64_t e0 = 0; e0 < b.count && !stopped;) {
@@ -933,7 +966,7 @@ rei_status search_levels(rei_instance* in, hipStream_t s) {
           if ((r = enqueue_chunk(in, s, c, pieces, &stopped)) != REI_OK) return r;
           pieces.clear();
           acc = 0;
-          cur = std::min(in->chunk_max, 2 * cur);
+          cur = std::min(cmax, 2 * cur);
         }
       }
       if (stopped) break;
@@ -976,7 +1009,7 @@ uint64_t batch_rows(const rei_instance* in, uint64_t arena_bytes) {
 bool batchable(const rei_instance* in) {
   bool same_char_cost = true;
   for (uint32_t ca : in->char_cost) same_char_cost = same_char_cost && ca == in->costs.c_char;
-  return in->st.W <= kBatchMaxW && in->max_cost <= kBatchMaxCost && in->st.gt_pair.size() <= kBatchMaxPairs &&
+  return in->st.W <= kBatchMaxW && in->max_cost <= kBatchMaxCost && in->st.gt_pair.size() <= batch_max_pairs(in->st.W) &&
          !in->otf_on && same_char_cost;
 }
 
@@ -1096,7 +1129,7 @@ int size_class(size_t n) {
   return k;
 }
 
-uint32_t max_threads(int g) { return g > 4 ? 512u : 1024u; }
+uint32_t max_threads(int g) { return batch_max_threads(g ? g : 1); }
 
 uint32_t choose_threads(int g, size_t n) {
   {
@@ -1543,6 +1576,102 @@ rei_status create_device(rei_instance* in) {
   return REI_OK;
 }
 
+// Reads a tuning file as rei_tune_save writes it: objects of integer
+// fields under "batch_threads" and "grid", and "batch_level_max".  Entries
+// with values out of range are rejected as a whole (nothing is applied).
+bool tune_parse(const std::string& text) {
+  auto section = [&](const char* key, std::string* out) -> bool {
+    const size_t k = text.find(std::string("\"") + key + "\"");
+    if (k == std::string::npos) return false;
+    const size_t a = text.find('[', k), b = text.find(']', k);
+    if (a == std::string::npos || b == std::string::npos || b < a) return false;
+    *out = text.substr(a + 1, b - a - 1);
+    return true;
+  };
+  auto field = [](const std::string& obj, const char* key, uint64_t* v) -> bool {
+    const size_t k = obj.find(std::string("\"") + key + "\"");
+    if (k == std::string::npos) return false;
+    size_t c = obj.find(':', k);
+    if (c == std::string::npos) return false;
+    ++c;
+    while (c < obj.size() && (obj[c] == ' ' || obj[c] == '\t' || obj[c] == '\n')) ++c;
+    if (c >= obj.size() || obj[c] < '0' || obj[c] > '9') return false;
+    *v = std::strtoull(obj.c_str() + c, nullptr, 10);
+    return true;
+  };
+  auto objects = [](const std::string& arr) {
+    std::vector<std::string> out;
+    size_t p = 0;
+    while ((p = arr.find('{', p)) != std::string::npos) {
+      const size_t q = arr.find('}', p);
+      if (q == std::string::npos) break;
+      out.push_back(arr.substr(p, q - p + 1));
+      p = q + 1;
+    }
+    return out;
+  };
+  std::map<std::pair<int, int>, uint32_t> bt;
+  std::map<int, GridTune> gr;
+  uint64_t lm = 0;
+  std::string arr;
+  if (section("batch_threads", &arr))
+    for (const std::string& o : objects(arr)) {
+      uint64_t g = 0, c = 0, t = 0;
+      if (!field(o, "group", &g) || !field(o, "size_class", &c) || !field(o, "threads", &t)) return false;
+      if (g > (uint64_t)kBatchMaxW || (g & (g - 1)) || c > 40 || (t != 256 && t != 512 && t != 1024) ||
+          t > batch_max_threads(g ? (int)g : 1))
+        return false;
+      bt[{(int)g, (int)c}] = (uint32_t)t;
+    }
+  if (section("grid", &arr))
+    for (const std::string& o : objects(arr)) {
+      uint64_t w = 0, fc = 0, cm = 0, wg = 0, xi = 0;
+      if (!field(o, "words", &w) || !field(o, "first_chunk", &fc) || !field(o, "chunk_max", &cm) ||
+          !field(o, "concat_wg", &wg) || !field(o, "concat_xi", &xi))
+        return false;
+      if (w < 1 || w > (uint64_t)kMaxWords || (w & (w - 1)) || fc < 1 || cm < 1 || cm > kMaxChunk || wg < 1 ||
+          wg > (1u << 24) || xi < 1 || xi > 64)
+        return false;
+      gr[(int)w] = GridTune{fc, cm, (uint32_t)wg, (uint32_t)xi};
+    }
+  {
+    const size_t k = text.find("\"batch_level_max\"");
+    if (k != std::string::npos) {
+      size_t c = text.find(':', k);
+      if (c == std::string::npos) return false;
+      lm = std::strtoull(text.c_str() + c + 1, nullptr, 10);
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto& kv : bt) g_tuned[kv.first] = kv.second;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_grid_mu);
+    for (auto& kv : gr) g_grid_tuned[kv.first] = kv.second;
+  }
+  if (lm) g_level_max.store(lm);
+  return true;
+}
+
+// REI_TUNE_FILE names a tuning file (as rei_tune_save writes it) that the
+// process loads once, when its first instance is created.
+void load_tune_file_once() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    const char* p = std::getenv("REI_TUNE_FILE");
+    if (!p || !*p) return;
+    FILE* f = std::fopen(p, "r");
+    if (!f) return;
+    std::string text;
+    char buf[4096];
+    size_t k;
+    while ((k = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, k);
+    std::fclose(f);
+    (void)tune_parse(text);
+  });
+}
+
 }  // namespace
 
 extern "C" {
@@ -1557,6 +1686,7 @@ rei_status rei_create(const char* alphabet, const char* const* pos, size_t n_pos
   }
   *out = nullptr;
   const double t0 = now_s();
+  load_tune_file_once();
   if (costs.c_char < 1 || costs.c_question < 1 || costs.c_star < 1 || costs.c_concat < 1 ||
       costs.c_union < 1) {
     g_create_error = "every constructor cost must be at least 1";
@@ -1735,12 +1865,11 @@ rei_status rei_tune_batch(rei_instance* const* insts, size_t n, void* hip_stream
       if (batchable(insts[i])) ++group_n[insts[i]->inl ? 0 : insts[i]->st.W];
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
-      static const int slot[kBatchMaxW + 1] = {0, 1, 2, -1, 3, -1, -1, -1, 4};
-      for (int g = 0; g <= kBatchMaxW; ++g) {
-        if (slot[g] < 0) continue;
+      for (int g = 0; g <= kBatchMaxW; g = g ? 2 * g : 1) {
+        const int slot = g == 0 ? 0 : 1 + __builtin_ctz((unsigned)g);  // W1-inline, W1, W2, W4, ..., W32
         const uint32_t t = group_n[g] ? std::min(cand[bq], max_threads(g)) : 0u;
         if (t) g_tuned[{g, size_class(group_n[g])}] = t;
-        if (threads_out) threads_out[slot[g]] = t;
+        if (threads_out) threads_out[slot] = t;
       }
     }
     // Hand-off level size (instances left at the default): whole calls with
@@ -1765,6 +1894,146 @@ rei_status rei_tune_batch(rei_instance* const* insts, size_t n, void* hip_stream
   } catch (const std::bad_alloc&) {
     g_force_threads.store(0);
     g_level_max.store(0);
+    return REI_ERR_HOST_ALLOC;
+  }
+}
+
+rei_status rei_set_grid_tuning(rei_instance* inst, uint64_t first_chunk, uint64_t chunk_max, uint32_t concat_wg,
+                               uint32_t concat_xi) {
+  if (!inst || concat_xi > 64) return REI_ERR_INVALID_ARG;
+  inst->grid_set = GridTune{first_chunk, chunk_max, concat_wg, concat_xi};
+  return REI_OK;
+}
+
+rei_status rei_tune_grid(rei_instance* const* insts, size_t n, void* hip_stream, uint64_t* params_out) {
+  if (n == 0 || !insts) return REI_ERR_INVALID_ARG;
+  for (size_t i = 0; i < n; ++i)
+    if (!insts[i]) return REI_ERR_INVALID_ARG;
+  try {
+    std::map<int, std::vector<rei_instance*>> by_w;
+    for (size_t i = 0; i < n; ++i) by_w[insts[i]->st.W].push_back(insts[i]);
+    if (params_out) std::fill(params_out, params_out + 24, 0ull);
+    for (auto& kv : by_w) {
+      std::vector<rei_instance*>& grp = kv.second;
+      std::vector<GridTune> saved;
+      for (rei_instance* in : grp) saved.push_back(in->grid_set);
+      GridTune base;
+      {
+        std::lock_guard<std::mutex> lk(g_grid_mu);
+        auto it = g_grid_tuned.find(kv.first);
+        if (it != g_grid_tuned.end()) base = it->second;
+      }
+      rei_result res;
+      rei_status r = REI_OK;
+      // the group's rei_solve calls one after another, best of three
+      auto time_group = [&](const GridTune& t, double* out) -> rei_status {
+        for (rei_instance* in : grp) in->grid_set = t;
+        double best = 1e300;
+        for (int rep = 0; rep < 3; ++rep) {
+          const double t0 = now_s();
+          for (rei_instance* in : grp) {
+            in->err.clear();
+            rei_status st = solve_impl(in, (hipStream_t)hip_stream, &res);
+            if (st != REI_OK) return st;
+          }
+          best = std::min(best, now_s() - t0);
+        }
+        *out = best;
+        return REI_OK;
+      };
+      double cur = 1e300;
+      if ((r = time_group(base, &cur)) != REI_OK) {
+        for (size_t k = 0; k < grp.size(); ++k) grp[k]->grid_set = saved[k];
+        return r;
+      }
+      // one parameter at a time, each over a few values around the defaults
+      const uint64_t firsts[] = {1ull << 14, 1ull << 15, 1ull << 16, 1ull << 17, 1ull << 18};
+      const uint64_t maxes[] = {1ull << 20, 1ull << 22, 1ull << 24};
+      const uint32_t wgs[] = {512, 1024, 2048, 4096, 8192};
+      const uint32_t xis[] = {4, 8, 16, 32, 64};
+      auto sweep = [&](const auto& values, auto set) -> rei_status {
+        GridTune keep = base;
+        for (auto v : values) {
+          GridTune t = base;
+          set(t, v);
+          double tt = 1e300;
+          rei_status st = time_group(t, &tt);
+          if (st != REI_OK) return st;
+          if (tt < cur) {
+            cur = tt;
+            keep = t;
+          }
+        }
+        base = keep;
+        return REI_OK;
+      };
+      if ((r = sweep(firsts, [](GridTune& t, uint64_t v) { t.first_chunk = v; })) == REI_OK &&
+          (r = sweep(maxes, [](GridTune& t, uint64_t v) { t.chunk_max = v; })) == REI_OK &&
+          (r = sweep(wgs, [](GridTune& t, uint32_t v) { t.concat_wg = v; })) == REI_OK)
+        r = sweep(xis, [](GridTune& t, uint32_t v) { t.concat_xi = v; });
+      for (size_t k = 0; k < grp.size(); ++k) grp[k]->grid_set = saved[k];
+      if (r != REI_OK) return r;
+      {
+        std::lock_guard<std::mutex> lk(g_grid_mu);
+        g_grid_tuned[kv.first] = base;
+      }
+      const int slot = __builtin_ctz((unsigned)kv.first);  // W = 1, 2, 4, ..., 32
+      if (params_out && slot < 6) {
+        params_out[4 * slot + 0] = base.first_chunk;
+        params_out[4 * slot + 1] = base.chunk_max;
+        params_out[4 * slot + 2] = base.concat_wg;
+        params_out[4 * slot + 3] = base.concat_xi;
+      }
+    }
+    return REI_OK;
+  } catch (const std::bad_alloc&) {
+    return REI_ERR_HOST_ALLOC;
+  }
+}
+
+rei_status rei_tune_save(const char* path) {
+  if (!path) return REI_ERR_INVALID_ARG;
+  std::string js = "{\n  \"batch_threads\": [";
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    bool first = true;
+    for (auto& kv : g_tuned) {
+      js += std::string(first ? "" : ",") + "\n    {\"group\": " + std::to_string(kv.first.first) +
+            ", \"size_class\": " + std::to_string(kv.first.second) + ", \"threads\": " + std::to_string(kv.second) + "}";
+      first = false;
+    }
+  }
+  js += "\n  ],\n  \"batch_level_max\": " + std::to_string(g_level_max.load()) + ",\n  \"grid\": [";
+  {
+    std::lock_guard<std::mutex> lk(g_grid_mu);
+    bool first = true;
+    for (auto& kv : g_grid_tuned) {
+      const GridTune& t = kv.second;
+      js += std::string(first ? "" : ",") + "\n    {\"words\": " + std::to_string(kv.first) +
+            ", \"first_chunk\": " + std::to_string(t.first_chunk) + ", \"chunk_max\": " + std::to_string(t.chunk_max) +
+            ", \"concat_wg\": " + std::to_string(t.concat_wg) + ", \"concat_xi\": " + std::to_string(t.concat_xi) + "}";
+      first = false;
+    }
+  }
+  js += "\n  ]\n}\n";
+  FILE* f = std::fopen(path, "w");
+  if (!f) return REI_ERR_INVALID_ARG;
+  const bool ok = std::fwrite(js.data(), 1, js.size(), f) == js.size();
+  return (std::fclose(f) == 0 && ok) ? REI_OK : REI_ERR_INVALID_ARG;
+}
+
+rei_status rei_tune_load(const char* path) {
+  if (!path) return REI_ERR_INVALID_ARG;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return REI_ERR_INVALID_ARG;
+  std::string text;
+  char buf[4096];
+  size_t k;
+  while ((k = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, k);
+  std::fclose(f);
+  try {
+    return tune_parse(text) ? REI_OK : REI_ERR_INVALID_ARG;
+  } catch (const std::bad_alloc&) {
     return REI_ERR_HOST_ALLOC;
   }
 }
@@ -1959,6 +2228,13 @@ rei_status rei_timing_overhead(double* us) {
   return st;
 }
 
+rei_status rei_measure_peak(rei_peak_kind kind, uint64_t size, double* rate, double* seconds) {
+  if (!rate || !seconds || (int)kind < 0 || (int)kind > (int)REI_PEAK_BITWISE) return REI_ERR_INVALID_ARG;
+  if ((kind == REI_PEAK_COPY || kind == REI_PEAK_PROBE || kind == REI_PEAK_PROBE_ATOMIC) && size < 4096)
+    return REI_ERR_INVALID_ARG;
+  return measure_peak((int)kind, size, rate, seconds) == hipSuccess ? REI_OK : REI_ERR_DEVICE;
+}
+
 rei_status rei_kernel_stats(const rei_instance* inst, rei_kernel_class k, uint64_t* launches, double* ms,
                             uint64_t* units) {
   if (!inst || k < 0 || k >= REI_K_COUNT) return REI_ERR_INVALID_ARG;
@@ -2006,6 +2282,7 @@ struct rei_server {
     rei_instance* in = nullptr;
     uint64_t reserve = 0;
     double t_submit = 0, t_done = 0;
+    bool begun = false;  // begin_solve ran (a batched launch took it): the grid path resumes it
     bool done = false;
     rei_status status = REI_OK;
     rei_result res{};
@@ -2059,12 +2336,24 @@ void server_worker(rei_server* sv, hipStream_t s) {
     sv->grid_queue.pop_front();
     rei_instance* in = sv->reqs[t].in;
     const double t0 = sv->reqs[t].t_submit;
+    const bool begun = sv->reqs[t].begun;
     sv->busy_workers++;
     lk.unlock();
-    rei_status r;
+    rei_status r = REI_OK;
     try {
-      r = search_levels(in, s);
-      if (r == REI_OK) r = finish_solve(in, t0);
+      in->err.clear();
+      // A request that never went through a batched launch starts here:
+      // reset its result state (counts, expression, hand-off level, OnTheFly
+      // state of an earlier solve) and answer the trivial specifications at
+      // once, exactly as rei_solve does.  A hand-off or a restart from a
+      // batched launch was begun there and continues.
+      const bool trivial = !begun && begin_solve(in, t0);
+      if (!trivial) {
+        if (hipSetDevice(in->device) != hipSuccess) r = REI_ERR_DEVICE;
+        if (r == REI_OK) r = search_levels(in, s);
+        if (r == REI_OK) r = finish_solve(in, t0);
+        if (r == REI_OK && hipStreamSynchronize(s) != hipSuccess) r = REI_ERR_DEVICE;
+      }
     } catch (const std::bad_alloc&) {
       r = REI_ERR_HOST_ALLOC;
     }
@@ -2105,6 +2394,7 @@ void server_sched(rei_server* sv) {
       }
       for (rei_instance* in : f.run.finished) server_finish(sv, by_inst[in], REI_OK);
       for (rei_instance* in : f.run.grid) {
+        sv->reqs[by_inst[in]].begun = true;  // batch_launch began it
         sv->grid_queue.push_back(by_inst[in]);
         sv->cv_grid.notify_one();
       }
@@ -2164,16 +2454,26 @@ extern "C" {
 
 rei_status rei_server_create(uint64_t hbm_budget, uint32_t max_batch, uint32_t n_streams,
                              uint32_t n_workers, rei_server** out) {
-  if (!out || hbm_budget == 0) return REI_ERR_INVALID_ARG;
+  if (!out) return REI_ERR_INVALID_ARG;
   *out = nullptr;
   rei_server* sv = new (std::nothrow) rei_server();
   if (!sv) return REI_ERR_HOST_ALLOC;
-  sv->budget = hbm_budget;
   sv->max_batch = max_batch ? max_batch : 64;
   if (hipGetDevice(&sv->device) != hipSuccess) {
     delete sv;
     return REI_ERR_DEVICE;
   }
+  if (hbm_budget == 0) {
+    // the device's free memory now, less a reserve for everything else
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+      delete sv;
+      return REI_ERR_DEVICE;
+    }
+    const uint64_t reserve = 8ull << 30;
+    hbm_budget = free_b > 2 * reserve ? free_b - reserve : free_b / 2;
+  }
+  sv->budget = hbm_budget;
   const uint32_t ns = n_streams ? n_streams : 4;
   for (uint32_t k = 0; k < ns; ++k) {
     hipStream_t s;
@@ -2218,9 +2518,15 @@ rei_status rei_server_poll(rei_server* sv, uint64_t ticket, int wait, int* done,
                            double* latency_s) {
   if (!sv || !done) return REI_ERR_INVALID_ARG;
   std::unique_lock<std::mutex> lk(sv->mu);
+  if (sv->reqs.find(ticket) == sv->reqs.end()) return REI_ERR_INVALID_ARG;
+  // submits during the wait may rehash the map: look the ticket up afresh
+  if (wait)
+    sv->cv_done.wait(lk, [&] {
+      auto i = sv->reqs.find(ticket);
+      return i == sv->reqs.end() || i->second.done;
+    });
   auto it = sv->reqs.find(ticket);
-  if (it == sv->reqs.end()) return REI_ERR_INVALID_ARG;
-  if (wait) sv->cv_done.wait(lk, [&] { return it->second.done; });
+  if (it == sv->reqs.end()) return REI_ERR_INVALID_ARG;  // retired by a concurrent poll
   *done = it->second.done ? 1 : 0;
   if (!*done) return REI_OK;
   if (out) *out = it->second.res;
@@ -2249,6 +2555,367 @@ void rei_server_destroy(rei_server* sv) {
     if (w.joinable()) w.join();
   for (auto s : sv->streams) (void)hipStreamDestroy(s);
   delete sv;
+}
+
+}  // extern "C"
+
+// ---- the batched solver as one captured graph --------------------------------
+//
+// rei_batch_graph_create prepares every batchable instance once (arena,
+// descriptor), runs the persistent launches eagerly to measure each
+// instance's work, orders each word-width group longest first and splits
+// the device's resident workgroups between the groups by their work, then
+// captures the step (counter reset, one persistent launch per group on
+// forked streams, join) as one hipGraph.  A replay is one graph launch; the
+// host then only reads each instance's results from its pinned buffers.
+
+struct rei_batch_graph {
+  int device = 0;
+  std::vector<rei_instance*> insts;   // caller's order
+  std::vector<rei_instance*> batched; // in descriptor order (groups concatenated)
+  std::vector<rei_instance*> other;   // not batchable: rei_solve's path at results time
+  struct Group {
+    int g = 0;            // 0 = one word with keys inline, else W
+    uint32_t off = 0, n = 0, threads = 0, grid = 0;
+  };
+  std::vector<Group> groups;
+  BatchDesc* h_desc = nullptr;  // pinned, read by the kernels
+  BatchDesc* d_desc = nullptr;
+  uint32_t* d_order = nullptr;  // per group: item -> descriptor index within the group
+  uint32_t* d_next = nullptr;   // per group: work counter
+  hipStream_t cap = nullptr;    // capture stream (owned)
+  std::vector<hipStream_t> sides;
+  std::vector<hipEvent_t> joins;
+  hipEvent_t fork = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t launched_on = nullptr;
+  uint64_t arena = 0;
+  bool in_flight = false;
+  double t0 = 0;
+  std::string err;
+};
+
+namespace {
+
+void graph_free(rei_batch_graph* g) {
+  if (g->in_flight && g->launched_on) (void)hipStreamSynchronize(g->launched_on);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  for (auto e : g->joins) (void)hipEventDestroy(e);
+  if (g->fork) (void)hipEventDestroy(g->fork);
+  for (auto s : g->sides) (void)hipStreamDestroy(s);
+  if (g->cap) (void)hipStreamDestroy(g->cap);
+  if (g->d_order) (void)hipFree(g->d_order);
+  if (g->d_next) (void)hipFree(g->d_next);
+  if (g->h_desc) (void)hipHostFree(g->h_desc);
+  delete g;
+}
+
+#define G_OK(g, call)                                                    \
+  do {                                                                   \
+    hipError_t e_ = (call);                                              \
+    if (e_ != hipSuccess) {                                              \
+      (g)->err = std::string(#call) + ": " + hipGetErrorString(e_);      \
+      return REI_ERR_DEVICE;                                             \
+    }                                                                    \
+  } while (0)
+
+// Enqueues the persistent launches of every group on g->cap and the side
+// streams (eagerly, or into a capture).
+rei_status graph_enqueue(rei_batch_graph* g) {
+  G_OK(g, launch_reset_counters(g->d_next, (uint32_t)g->groups.size(), g->cap));
+  G_OK(g, hipEventRecord(g->fork, g->cap));
+  for (size_t k = 0; k < g->groups.size(); ++k) {
+    const auto& q = g->groups[k];
+    hipStream_t s = k ? g->sides[k - 1] : g->cap;
+    if (k) G_OK(g, hipStreamWaitEvent(s, g->fork, 0));
+    G_OK(g, launch_solve_batch(q.g ? q.g : 1, q.g == 0, q.threads, g->d_desc + q.off, q.n, s, g->d_order + q.off,
+                               g->d_next + k, q.grid));
+    if (k) {
+      G_OK(g, hipEventRecord(g->joins[k - 1], s));
+      G_OK(g, hipStreamWaitEvent(g->cap, g->joins[k - 1], 0));
+    }
+  }
+  return REI_OK;
+}
+
+// The descriptor of a graph's instance, as every replay reads it: the whole
+// search stays in the launch (no hand-off on size or time).
+BatchDesc graph_desc(const rei_instance* in) {
+  BatchDesc d = make_desc(in);
+  d.level_max = ~0ull;
+  d.time_ticks = 0;
+  return d;
+}
+
+// Arena of a graph's instance: rows, chunk buffers, and a table that holds
+// every row plus a chunk at load at most 1/2.
+rei_status graph_arena(rei_instance* in, uint64_t arena_bytes, hipStream_t s) {
+  rei_status r;
+  const uint64_t R = batch_rows(in, arena_bytes);
+  if ((r = ensure_chunk_buffers(in, kBatchChunk)) != REI_OK) return r;
+  if ((r = ensure_rows(in, R, s)) != REI_OK) return r;
+  return ensure_table(in, in->rows_alloc + kBatchChunk, s, false);
+}
+
+// Results of one run of the launches (they have finished): every batched
+// instance's state from its pinned buffers.  Instances that ran out of
+// their preallocated rows, and those that are not batchable, run
+// rei_solve's path on the worker threads; the former then get an arena that
+// holds their rows, and their descriptors follow the buffers they now have,
+// so the next replay reads no freed memory.
+rei_status graph_collect(rei_batch_graph* g, hipStream_t s) {
+  rei_status r;
+  GridPool pool(g->t0);
+  for (rei_instance* in : g->other) {
+    in->err.clear();
+    if (!begin_solve(in, g->t0)) pool.submit(in);
+  }
+  std::vector<size_t> refresh;
+  for (size_t i = 0; i < g->batched.size(); ++i) {
+    rei_instance* in = g->batched[i];
+    in->err.clear();
+    const double seen = in->t_seen;
+    (void)begin_solve(in, g->t0);  // batchable instances are never trivial
+    if (batch_take_state(in)) {
+      in->resume_level = 0;  // a fresh search: the arena was not enough
+      refresh.push_back(i);
+      pool.submit(in);
+      continue;
+    }
+    if ((r = finish_solve(in, g->t0)) != REI_OK) {
+      (void)pool.join();
+      return r;
+    }
+    if (seen >= 0) in->res.seconds_solve = seen;
+    in->t_seen = -1;
+  }
+  if ((r = pool.join()) != REI_OK) return r;
+  for (size_t i : refresh) {
+    rei_instance* in = g->batched[i];
+    if ((r = graph_arena(in, g->arena, s)) != REI_OK) return r;
+    HIP_OK(in, hipStreamSynchronize(s));
+    g->h_desc[i] = graph_desc(in);
+  }
+  return REI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rei_status rei_batch_graph_create(rei_instance* const* insts, size_t n, uint64_t arena_bytes,
+                                  rei_batch_graph** out) {
+  if (!out || (n && !insts)) return REI_ERR_INVALID_ARG;
+  *out = nullptr;
+  for (size_t i = 0; i < n; ++i)
+    if (!insts[i]) return REI_ERR_INVALID_ARG;
+  if (arena_bytes == 0) arena_bytes = kDefaultArena;
+  rei_batch_graph* g = new (std::nothrow) rei_batch_graph();
+  if (!g) return REI_ERR_HOST_ALLOC;
+  rei_status r = REI_OK;
+  try {
+    G_OK(g, hipGetDevice(&g->device));
+    G_OK(g, hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
+    g->insts.assign(insts, insts + n);
+    std::vector<BatchDesc> descs;
+    const double t0 = now_s();
+    std::vector<rei_instance*> members[kBatchMaxW + 1];
+    for (rei_instance* in : g->insts) {
+      if (in->device != g->device) {
+        g->err = "instances of one graph must live on the current device";
+        graph_free(g);
+        return REI_ERR_INVALID_ARG;
+      }
+      if (begin_solve(in, t0)) continue;  // trivial: answered at results time
+      if (!batchable(in)) {
+        g->other.push_back(in);
+        continue;
+      }
+      members[in->inl ? 0 : in->st.W].push_back(in);
+    }
+    // arenas (device memory is taken here, not at replay)
+    g->arena = arena_bytes;
+    for (int w = 0; w <= kBatchMaxW; w = w ? 2 * w : 1)
+      for (rei_instance* in : members[w])
+        if ((r = graph_arena(in, arena_bytes, g->cap)) != REI_OK) {
+          g->err = in->err;
+          graph_free(g);
+          return r;
+        }
+    G_OK(g, hipStreamSynchronize(g->cap));
+    for (int w = 0; w <= kBatchMaxW; w = w ? 2 * w : 1) {
+      if (members[w].empty()) continue;
+      rei_batch_graph::Group q;
+      q.g = w;
+      q.off = (uint32_t)descs.size();
+      q.n = (uint32_t)members[w].size();
+      q.threads = choose_threads(w, members[w].size());
+      for (rei_instance* in : members[w]) {
+        descs.push_back(graph_desc(in));  // no hand-off: the whole search stays in the graph
+        g->batched.push_back(in);
+      }
+      g->groups.push_back(q);
+    }
+    const size_t nd = std::max<size_t>(1, descs.size());
+    G_OK(g, hipHostMalloc((void**)&g->h_desc, nd * sizeof(BatchDesc), hipHostMallocMapped | hipHostMallocPortable));
+    G_OK(g, hipHostGetDevicePointer((void**)&g->d_desc, g->h_desc, 0));
+    if (!descs.empty()) std::memcpy(g->h_desc, descs.data(), descs.size() * sizeof(BatchDesc));
+    G_OK(g, hipMalloc((void**)&g->d_order, nd * sizeof(uint32_t)));
+    G_OK(g, hipMalloc((void**)&g->d_next, 64 * sizeof(uint32_t)));
+    G_OK(g, hipEventCreateWithFlags(&g->fork, hipEventDisableTiming));
+    for (size_t k = 1; k < g->groups.size(); ++k) {
+      hipStream_t s;
+      hipEvent_t e;
+      G_OK(g, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      g->sides.push_back(s);
+      G_OK(g, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      g->joins.push_back(e);
+    }
+    if (g->groups.empty()) {
+      *out = g;
+      return REI_OK;
+    }
+    // a measuring run: every group in index order on a grid of its size
+    std::vector<uint32_t> order(descs.size());
+    for (const auto& q : g->groups)
+      for (uint32_t i = 0; i < q.n; ++i) order[q.off + i] = i;
+    G_OK(g, hipMemcpy(g->d_order, order.data(), order.size() * 4, hipMemcpyHostToDevice));
+    const uint32_t cus = device_cus(g->device);
+    std::vector<uint32_t> per_cu(g->groups.size(), 1);
+    for (size_t k = 0; k < g->groups.size(); ++k) {
+      auto& q = g->groups[k];
+      G_OK(g, batch_resident(q.g ? q.g : 1, q.g == 0, q.threads, &per_cu[k]));
+      q.grid = std::min<uint32_t>(q.n, per_cu[k] * cus);
+    }
+    for (rei_instance* in : g->batched) __atomic_store_n(&in->h_state->done, 0u, __ATOMIC_RELEASE);
+    if ((r = graph_enqueue(g)) != REI_OK) {
+      graph_free(g);
+      return r;
+    }
+    G_OK(g, hipStreamSynchronize(g->cap));
+    // work of each instance: its candidates (all levels); longest first
+    std::vector<double> work(descs.size(), 0);
+    double total = 0;
+    std::vector<double> gwork(g->groups.size(), 0);
+    for (size_t k = 0; k < g->groups.size(); ++k) {
+      const auto& q = g->groups[k];
+      for (uint32_t i = 0; i < q.n; ++i) {
+        rei_instance* in = g->batched[q.off + i];
+        const uint64_t L = in->max_cost + 2;
+        double c = 0;
+        for (uint64_t l = 0; l < L; ++l) c += (double)in->h_levels[2 * L + l];
+        // a candidate of a wider language costs more (W words per operation)
+        work[q.off + i] = c * (1.0 + 0.25 * std::max(1, in->st.W)) + 1000.0;
+        gwork[k] += work[q.off + i];
+      }
+      total += gwork[k];
+      std::stable_sort(order.begin() + q.off, order.begin() + q.off + q.n,
+                       [&](uint32_t a, uint32_t b) { return work[q.off + a] > work[q.off + b]; });
+    }
+    G_OK(g, hipMemcpy(g->d_order, order.data(), order.size() * 4, hipMemcpyHostToDevice));
+    // resident workgroups shared between the groups in proportion to their work
+    for (size_t k = 0; k < g->groups.size(); ++k) {
+      auto& q = g->groups[k];
+      const double share = total > 0 ? gwork[k] / total : 1.0 / g->groups.size();
+      const uint32_t want = (uint32_t)std::llround(share * per_cu[k] * cus);
+      q.grid = std::max<uint32_t>(1, std::min<uint32_t>(q.n, want));
+    }
+    G_OK(g, hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
+    r = graph_enqueue(g);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(g->cap, &graph);
+    g->graph = graph;
+    if (r != REI_OK) {
+      graph_free(g);
+      return r;
+    }
+    G_OK(g, ec);
+    G_OK(g, hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+  } catch (const std::bad_alloc&) {
+    graph_free(g);
+    return REI_ERR_HOST_ALLOC;
+  }
+  *out = g;
+  return REI_OK;
+}
+
+rei_status rei_batch_graph_launch(rei_batch_graph* g, void* hip_stream) {
+  if (!g) return REI_ERR_INVALID_ARG;
+  if (g->in_flight) {
+    g->err = "the previous launch's results were not collected";
+    return REI_ERR_INVALID_ARG;
+  }
+  G_OK(g, hipSetDevice(g->device));
+  for (rei_instance* in : g->batched) {
+    __atomic_store_n(&in->h_state->done, 0u, __ATOMIC_RELEASE);
+    in->t_seen = -1;
+  }
+  g->t0 = now_s();
+  g->launched_on = (hipStream_t)hip_stream;
+  if (g->exec) G_OK(g, hipGraphLaunch(g->exec, g->launched_on));
+  g->in_flight = true;
+  return REI_OK;
+}
+
+rei_status rei_batch_graph_results(rei_batch_graph* g, rei_result* out) {
+  if (!g || (!out && !g->insts.empty())) return REI_ERR_INVALID_ARG;
+  if (!g->in_flight) {
+    g->err = "no launch to collect";
+    return REI_ERR_INVALID_ARG;
+  }
+  rei_status r = REI_OK;
+  try {
+    G_OK(g, hipSetDevice(g->device));
+    // read completion flags while the launches run: the time each result
+    // was known
+    size_t left = g->batched.size();
+    std::vector<char> seen(g->batched.size(), 0);
+    while (left) {
+      bool progress = false;
+      for (size_t i = 0; i < g->batched.size(); ++i) {
+        if (seen[i] || !__atomic_load_n(&g->batched[i]->h_state->done, __ATOMIC_ACQUIRE)) continue;
+        seen[i] = 1;
+        g->batched[i]->t_seen = now_s() - g->t0;
+        --left;
+        progress = true;
+      }
+      if (!left) break;
+      if (!progress) {
+        const hipError_t q = hipStreamQuery(g->launched_on);
+        if (q == hipSuccess) break;
+        if (q != hipErrorNotReady) G_OK(g, q);
+        std::this_thread::yield();
+      }
+    }
+    G_OK(g, hipStreamSynchronize(g->launched_on));
+    g->in_flight = false;
+    r = graph_collect(g, g->launched_on);
+    if (r != REI_OK) {
+      for (rei_instance* in : g->insts)
+        if (!in->err.empty()) {
+          g->err = in->err;
+          break;
+        }
+      return r;
+    }
+    for (size_t i = 0; i < g->insts.size(); ++i) {
+      rei_instance* in = g->insts[i];
+      out[i] = in->res;
+    }
+  } catch (const std::bad_alloc&) {
+    return REI_ERR_HOST_ALLOC;
+  }
+  return REI_OK;
+}
+
+const char* rei_batch_graph_error(const rei_batch_graph* g) { return g ? g->err.c_str() : ""; }
+
+void rei_batch_graph_destroy(rei_batch_graph* g) {
+  if (!g) return;
+  (void)hipSetDevice(g->device);
+  graph_free(g);
 }
 
 }  // extern "C"

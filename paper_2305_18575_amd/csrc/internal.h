@@ -111,6 +111,20 @@ struct GenArgs {
   const int32_t* char_index;  // base level only
   const DevState* st;
   uint32_t inl;               // inline-key table (one word per language, |ic| <= 63)
+  // concatenation launch shape (0 = defaults): workgroups the grid aims at,
+  // and the most left rows one workgroup takes
+  uint32_t concat_wg, concat_xi;
+};
+
+// Tunable launch parameters of the per-chunk grid path (per word width):
+// the first chunk of a level (each next one doubles), the largest chunk,
+// and the concatenation kernel's grid target and left rows per workgroup.
+// Results do not depend on them.
+struct GridTune {
+  uint64_t first_chunk = 1ull << 16;
+  uint64_t chunk_max = 1ull << 24;
+  uint32_t concat_wg = 2048;
+  uint32_t concat_xi = 16;
 };
 
 struct ChunkArgs {
@@ -151,7 +165,10 @@ template <typename F, typename... Args>
 inline void launch_timed(F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t s, Args... args) {
   const KernelTimer t = g_kernel_timer;
   g_kernel_timer = KernelTimer{nullptr, nullptr};
-  hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, t.start, t.stop, 0u, args...);
+  if (t.start)
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, t.start, t.stop, 0u, args...);
+  else  // untimed: a plain launch (also what a stream capture records)
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
 }
 
 // Kernel launchers (kernels.hip).  Every launcher returns the hipError_t of
@@ -220,9 +237,16 @@ hipError_t launch_gen_pieces(int W, const GenArgs& a, const PieceArgs& p, hipStr
 // ---- batched solver: one workgroup runs the whole search of one instance --
 constexpr uint32_t kBatchChunk = 8192;   // candidates per chunk
 constexpr uint32_t kBatchMaxCost = 63;   // largest max_cost handled in a batch
-constexpr int kBatchMaxW = 8;            // largest words per language
-constexpr uint32_t kBatchMaxIc = 64 * kBatchMaxW;  // largest |ic|
-constexpr uint32_t kBatchMaxPairs = 6144;          // largest guide table (cuts), kept in LDS
+constexpr int kBatchMaxW = 32;           // largest words per language
+// The guide table sits in the workgroup's LDS: up to 512 infixes and 6144
+// cuts for languages of at most 8 words, up to 64 W infixes and 12288 cuts
+// for 16 and 32 words (the wider solvers run fewer threads, so their
+// operand tiles leave room for it).
+constexpr uint32_t batch_max_ic(int W) { return W <= 8 ? 512u : 64u * (uint32_t)W; }
+constexpr uint32_t batch_max_pairs(int W) { return W <= 8 ? 6144u : 12288u; }
+// Most threads per instance for W words: each wave holds a 64 x W-word
+// operand tile in LDS.
+constexpr uint32_t batch_max_threads(int W) { return W >= 32 ? 256u : W >= 8 ? 512u : 1024u; }
 constexpr uint64_t kBatchTimeMinLevel = 4096;  // smaller levels stay on the workgroup whatever the time
 constexpr uint32_t kBatchTimeUs = 500;         // default workgroup time before larger levels move
 constexpr uint64_t kBatchLevelMax = 1ull << 16;  // default: candidates of one level a workgroup takes on
@@ -260,9 +284,25 @@ struct BatchDesc {
   uint64_t* htree;            // [node count, then per node: row (~0 = the answer), op, a, b]
 };
 
-// Launches one workgroup of `threads` (256, 512 or 1024; at most 512 for
-// W = 8) per descriptor (all with the same W).
+// Launches the batched solver with `threads` per workgroup (256, 512 or
+// 1024, at most batch_max_threads(W)) over n descriptors (all with the same
+// W).
+// next == nullptr: one workgroup per descriptor (grid ignored).  Else a
+// persistent grid of `grid` workgroups (1..n) that take items from the
+// device counter *next (zero at launch) and solve descriptor order[item]
+// (item itself when order is null).
 hipError_t launch_solve_batch(int W, bool inl, uint32_t threads, const BatchDesc* d_descs, uint32_t n,
-                              hipStream_t s);
+                              hipStream_t s, const uint32_t* order = nullptr, uint32_t* next = nullptr,
+                              uint32_t grid = 0);
+// Workgroups of the batched solver that fit one compute unit at once.
+hipError_t batch_resident(int W, bool inl, uint32_t threads, uint32_t* per_cu);
+// Zeroes n (<= 64) work counters with a kernel (graph-capturable).
+hipError_t launch_reset_counters(uint32_t* c, uint32_t n, hipStream_t s);
+
+// Achievable peak of one operation class on the current device (peaks.hip):
+// kind 0 stream copy (rate = bytes read + written per second), 1 random
+// table reads, 2 random reads plus atomicMin (rate = probes per second),
+// 3 bitwise AND-OR loop (rate = 32-bit bitwise lane operations per second).
+hipError_t measure_peak(int kind, uint64_t size, double* rate, double* seconds);
 
 }  // namespace rei

@@ -710,10 +710,14 @@ hipError_t launch_concat_w(const GenArgs& a, hipStream_t s) {
   // right tiles in LDS: at most 32 KB
   const uint32_t yt_cap = (uint32_t)std::max(1, std::min(kConcatYT, 32768 / (512 * W)));
   uint32_t yt = (uint32_t)std::min<uint64_t>(yt_cap, nT);
-  uint32_t xi = 16;
+  // left rows per workgroup: at most concat_xi (16 by default), fewer (down
+  // to 4), then fewer right tiles, while the grid has under concat_wg
+  // workgroups (2048 by default)
+  const uint64_t target = a.concat_wg ? a.concat_wg : 2048;
+  uint32_t xi = a.concat_xi ? std::min<uint32_t>(a.concat_xi, 64) : 16;
   auto wgs = [&](uint32_t y, uint32_t x) { return ((nT + y - 1) / y) * ((rowsx + x - 1) / x); };
-  while (xi > 4 && wgs(yt, xi) < 2048) xi /= 2;
-  while (yt > 1 && wgs(yt, xi) < 2048) yt /= 2;
+  while (xi > 4 && wgs(yt, xi) < target) xi /= 2;
+  while (yt > 1 && wgs(yt, xi) < target) yt /= 2;
   size_t lds = (size_t)yt * 64 * W * 8 + (size_t)xi * W * 8;
   const uint32_t gt_lds = (lds + (size_t)a.n_pairs * 4 <= 60 * 1024) ? 1u : 0u;
   if (gt_lds) lds += (size_t)a.n_pairs * 4;

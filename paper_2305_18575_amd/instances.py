@@ -257,6 +257,25 @@ def large_instance(seed: int) -> Instance:
                     (1, 1, 1, 1, 1), cost)
 
 
+def wide_instance(seed: int, max_cost: int = 11) -> Instance:
+    """A specification wide enough for 32 words per language (1025..2048
+    infixes): twenty positive and twenty negative ternary strings drawn as the
+    paper's Type 1 benchmarks are (distinct strings uniform among all strings
+    of length at most 12, the first twenty positive).  Twenty plus twenty
+    ternary strings of length at most 10 (the large configuration) have at
+    most 961 distinct infixes, so that configuration never reaches this
+    width.  Seeds 0..3 give 1219..1234 infixes.  Random strings share little
+    structure, so the minimal expression is expensive: ``max_cost`` bounds
+    the search (NOT_FOUND below the answer's cost)."""
+    it = type1_instance(seed, p=20, n=20, le=12, sigma="012", max_cost=max_cost)
+    n = n_infixes(it.pos + it.neg)
+    if not 1024 < n <= 2048:
+        raise ValueError(f"seed {seed}: {n} infixes, not a 32-word specification")
+    it.kind = "wide"
+    it.meta["n_ic"] = n
+    return it
+
+
 def batched_instances(master_seed: int, count: int) -> List[Instance]:
     """Many small uneven instances: |Sigma| in {2,3,4}, 2..16 positive and
     2..16 negative strings of length 0..6, target cost 4..12, at most 512

@@ -3,8 +3,9 @@ against a plain sequential solver (rei_solve per request, first come first
 served) on the same arrivals.
 
 The request mix is 60% plain, 30% large and 10% single instances (the three
-single-instance shapes).  Large-instance requests search up to cost 10 with a
-1 GiB cache so that one request stays in the milliseconds-to-seconds range.
+single-instance shapes), each searched up to its target's cost.  Large
+requests get a 1 GiB language cache (the deepest of them end out of memory,
+an outcome compared like any other), the others 64 MiB and 1 GiB.
 """
 from __future__ import annotations
 
@@ -14,6 +15,18 @@ from typing import List, Sequence
 import numpy as np
 
 from . import instances as I
+
+
+_large_memo = {}
+
+
+def _large(seed: int):
+    # drawing a large specification takes tens of milliseconds (its target's
+    # language is enumerated over all ternary strings up to length 10); the
+    # mix reuses 64 seeds, each drawn once per process
+    if seed not in _large_memo:
+        _large_memo[seed] = I.large_instance(seed)
+    return _large_memo[seed]
 
 
 def request_mix(seed: int, n: int):
@@ -27,8 +40,7 @@ def request_mix(seed: int, n: int):
             inst = I.plain_instance(sub)
             out.append(("plain", inst, 64 << 20))
         elif kind == 1:
-            inst = I.large_instance(sub % 64)
-            inst.max_cost = min(inst.max_cost, 10)
+            inst = _large(sub % 64)
             out.append(("large", inst, 1 << 30))
         else:
             costs = (1, 1, 1, 1, 1) if k % 2 == 0 else (1, 1, 5, 1, 2)
@@ -94,3 +106,38 @@ def run_sequential(rei, handles, arrivals, stream=None):
 def same(a, b) -> bool:
     return (a.status, a.cost, a.regex, a.unique, a.candidates) == (b.status, b.cost, b.regex, b.unique,
                                                                     b.candidates)
+
+
+def sweep(rei, n: int, fractions=(0.25, 0.5, 0.75, 1.0), seed: int = 2024, budget: int = 0, stream=None):
+    """Serving at fixed rates: ``n`` Poisson arrivals of the mix per point, the
+    rate a fraction of the measured sequential capacity (requests per second
+    of back-to-back rei_solve), the server against a first-come-first-served
+    sequential solver on the same arrivals.  The server is warmed (one untimed
+    pass of the whole mix, so each instance's buffers exist) before the timed
+    points.  budget 0 = the free HBM less 8 GB at server creation."""
+    specs = request_mix(seed, n)
+    hs = stage(rei, specs)
+    base = poisson_arrivals(seed, n, 1.0)
+    seq_res, _, _ = run_sequential(rei, hs, base * 0.0, stream)  # warms the instances (allocations)
+    t = time.perf_counter()
+    for h in hs:
+        h.solve(stream)
+    capacity = n / (time.perf_counter() - t)
+    run_served(rei, hs, base / (4 * capacity), budget)  # warm the server path (untimed)
+    points = []
+    for f in fractions:
+        qps = capacity * f
+        arr = base / qps
+        res, lat, ips = run_served(rei, hs, arr, budget)
+        sres, slat, sips = run_sequential(rei, hs, arr, stream)
+        points.append({"load": f, "qps": round(qps, 2),
+                       "served": {"instances_per_sec": round(ips, 2),
+                                  **{k: round(v, 3) for k, v in percentiles(lat).items()}},
+                       "sequential": {"instances_per_sec": round(sips, 2),
+                                      **{k: round(v, 3) for k, v in percentiles(slat).items()}},
+                       "identical_results": all(same(a, b) for a, b in zip(res, seq_res))})
+    kinds = {k: sum(1 for s in specs if s[0] == k) for k in ("plain", "large", "single")}
+    for h in hs:
+        h.close()
+    return {"arrivals_per_point": n, "mix": kinds, "sequential_capacity_per_sec": round(capacity, 2),
+            "points": points}

@@ -78,3 +78,54 @@ def test_set_allocator_argument_checks():
     assert lib.rei_set_allocator(rei._ALLOC_FN(), rei._FREE_FN(), None) == 0
     with pytest.raises(ValueError):
         rei.set_allocator(None, lambda p: None)
+
+
+def test_measure_peak_argument_checks():
+    """rei_measure_peak rejects an unknown kind and too small a buffer before
+    any device work."""
+    lib = rei.load_library()
+    rate, sec = ctypes.c_double(), ctypes.c_double()
+    assert lib.rei_measure_peak(7, 1 << 20, ctypes.byref(rate), ctypes.byref(sec)) == -1
+    assert lib.rei_measure_peak(-1, 1 << 20, ctypes.byref(rate), ctypes.byref(sec)) == -1
+    assert lib.rei_measure_peak(0, 100, ctypes.byref(rate), ctypes.byref(sec)) == -1
+    assert lib.rei_measure_peak(0, 1 << 20, None, ctypes.byref(sec)) == -1
+
+
+def test_batch_graph_argument_checks():
+    """The graph calls reject null handles and outputs before any device work."""
+    lib = rei.load_library()
+    out = ctypes.c_void_p()
+    assert lib.rei_batch_graph_create(None, 0, 0, None) == -1
+    assert lib.rei_batch_graph_create(None, 3, 0, ctypes.byref(out)) == -1
+    assert lib.rei_batch_graph_launch(None, None) == -1
+    assert lib.rei_batch_graph_results(None, None) == -1
+    assert lib.rei_batch_graph_error(None) == b""
+    lib.rei_batch_graph_destroy(None)
+
+
+def test_tuning_file_round_trip(tmp_path):
+    """rei_tune_load reads what rei_tune_save writes (host tables only, no
+    device work); a file with an entry out of range is rejected whole."""
+    good = tmp_path / "tune.json"
+    good.write_text('{"batch_threads": [{"group": 16, "size_class": 2, "threads": 512}],\n'
+                    ' "batch_level_max": 32768,\n'
+                    ' "grid": [{"words": 16, "first_chunk": 16384, "chunk_max": 4194304, '
+                    '"concat_wg": 4096, "concat_xi": 8}]}\n')
+    rei.tune_load(str(good))
+    out = tmp_path / "saved.json"
+    rei.tune_save(str(out))
+    import json
+    saved = json.loads(out.read_text())
+    assert {"group": 16, "size_class": 2, "threads": 512} in saved["batch_threads"]
+    assert saved["batch_level_max"] == 32768
+    assert {"words": 16, "first_chunk": 16384, "chunk_max": 4194304, "concat_wg": 4096,
+            "concat_xi": 8} in saved["grid"]
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"grid": [{"words": 3, "first_chunk": 1, "chunk_max": 1, "concat_wg": 1, "concat_xi": 1}]}')
+    with pytest.raises(rei.ReiError):
+        rei.tune_load(str(bad))
+    bad.write_text('{"batch_threads": [{"group": 32, "size_class": 1, "threads": 1024}]}')
+    with pytest.raises(rei.ReiError):
+        rei.tune_load(str(bad))
+    with pytest.raises(rei.ReiError):
+        rei.tune_load(str(tmp_path / "missing.json"))

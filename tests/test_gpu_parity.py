@@ -86,8 +86,11 @@ def test_batched_config_instances(rei):
 
 
 def test_large_config_partial(rei):
-    """Ternary instance with hundreds of infixes (16-32 words per language),
-    levels up to cost 8 (the oracle is fast there)."""
+    """Ternary instances with hundreds of infixes (seed 0: 689 infixes, 16
+    words per language; seed 1: 474, 8 words), levels up to cost 8 (the
+    oracle is fast there).  Twenty plus twenty ternary strings of length at
+    most 10 have at most 961 distinct infixes, so this configuration never
+    needs 32 words; test_wide_spec_32_words covers that width."""
     for seed in (0, 1):
         inst = instances.large_instance(seed)
         run_both(rei, inst.alphabet, inst.pos, inst.neg, inst.costs, 8, rows=True)
@@ -677,3 +680,163 @@ def test_concurrent_batched_calls(rei):
     for hs in sets:
         for h in hs:
             h.close()
+
+
+def test_batch_all_4096_equal_oracle(rei):
+    """The batched configuration at full size: all 4096 instances (master seed
+    0) in one rei_solve_batch call, every result compared with the oracle's
+    (the oracle runs across instances on host threads)."""
+    from oracle_runs import mismatch, solve_many
+    specs = instances.batched_instances(0, 4096)
+    cache = 1 << 30
+    want = solve_many([(i.alphabet, i.pos, i.neg, i.costs, i.max_cost, cache) for i in specs],
+                      workers=8, threads=1)
+    print("\ncase: 4096 batched instances, one rei_solve_batch call", flush=True)
+    hs = [rei.Instance(i.alphabet, i.pos, i.neg, i.costs, i.max_cost, cache) for i in specs]
+    got = rei.solve_batch(hs)
+    bad = [(k, mismatch(g, o, specs[k].max_cost)) for k, (g, o) in enumerate(zip(got, want))
+           if mismatch(g, o, specs[k].max_cost) is not None]
+    assert not bad, bad[:5]
+    for h in hs:
+        h.close()
+
+
+@pytest.mark.parametrize("seed,max_cost,row_limit", [(0, 11, 64), (1, 10, 64), (2, 9, None)])
+def test_wide_spec_32_words(rei, seed, max_cost, row_limit):
+    """32 words per language (1219-1234 infixes: twenty plus twenty ternary
+    strings of length at most 12): every constructor kernel at its widest
+    instantiation.  Counts and status against the oracle; rows of every level
+    compared bit by bit (all of them for seed 2)."""
+    inst = instances.wide_instance(seed, max_cost)
+    g, _ = run_both(rei, inst.alphabet, inst.pos, inst.neg, inst.costs, max_cost, 4 << 30,
+                    rows=True, row_limit=row_limit)
+    assert g.cs_words == 32 and g.ic_size == inst.meta["n_ic"]
+
+
+def test_wide_spec_32_words_chunked(rei):
+    """The 32-word path with tiny chunks (every chunk boundary inside a
+    concatenation block) gives the same results."""
+    inst = instances.wide_instance(3, 8)
+    g, _ = run_both(rei, inst.alphabet, inst.pos, inst.neg, inst.costs, 8, 4 << 30, chunk=777, rows=True)
+    assert g.cs_words == 32
+
+
+def _graph_specs():
+    """Batched instances of every word width, plus one that cannot be batched
+    (16 words) and the two trivial specifications."""
+    specs = instances.batched_instances(5, 300)
+    big = instances.large_instance(2)
+    big.max_cost = 7
+    specs.append(big)
+    specs.append(instances.Instance("01", [], ["0"], kind="trivial", max_cost=12))
+    specs.append(instances.Instance("012", [""], ["1", "22"], kind="trivial", max_cost=12))
+    return specs
+
+
+@pytest.mark.parametrize("arena", [0, 1 << 16])
+def test_batch_graph_replays_equal_oracle(rei, arena):
+    """A captured batch replayed three times, with eager work of the program
+    between the replays (another batched solve, a synchronisation): every
+    replay's results equal the oracle's.  With a 64 KiB arena many instances
+    outgrow their rows on the first replay, finish on the per-chunk path and
+    get an arena that fits before the next replay."""
+    import torch
+    from oracle_runs import mismatch, solve_many
+    specs = _graph_specs()
+    cache = 1 << 30
+    want = solve_many([(i.alphabet, i.pos, i.neg, i.costs, i.max_cost, cache) for i in specs], workers=8, threads=1)
+    print(f"\ncase: graph of {len(specs)} instances, arena {arena}", flush=True)
+    hs = [rei.Instance(i.alphabet, i.pos, i.neg, i.costs, i.max_cost, cache) for i in specs]
+    g = rei.BatchGraph(hs, arena)
+    others = [rei.Instance(i.alphabet, i.pos, i.neg, i.costs, i.max_cost, cache)
+              for i in instances.batched_instances(6, 40)]
+    for rep in range(3):
+        print(f"replay {rep}", flush=True)
+        got = g.run()
+        bad = [(k, mismatch(a, o, specs[k].max_cost)) for k, (a, o) in enumerate(zip(got, want))
+               if mismatch(a, o, specs[k].max_cost) is not None]
+        assert not bad, (rep, bad[:5])
+        rei.solve_batch(others)
+        torch.cuda.synchronize()
+    g.close()
+    for h in hs + others:
+        h.close()
+
+
+def test_batch_graph_4096_equal_oracle(rei):
+    """The batched configuration at full size through the captured graph: all
+    4096 instances (master seed 0) per replay, two replays, every result
+    equal to the oracle's."""
+    from oracle_runs import mismatch, solve_many
+    specs = instances.batched_instances(0, 4096)
+    cache = 1 << 30
+    want = solve_many([(i.alphabet, i.pos, i.neg, i.costs, i.max_cost, cache) for i in specs],
+                      workers=8, threads=1)
+    print("\ncase: 4096 batched instances through the graph", flush=True)
+    hs = [rei.Instance(i.alphabet, i.pos, i.neg, i.costs, i.max_cost, cache) for i in specs]
+    g = rei.BatchGraph(hs)
+    for rep in range(2):
+        got = g.run()
+        bad = [(k, mismatch(a, o, specs[k].max_cost)) for k, (a, o) in enumerate(zip(got, want))
+               if mismatch(a, o, specs[k].max_cost) is not None]
+        assert not bad, (rep, bad[:5])
+    g.close()
+    for h in hs:
+        h.close()
+
+
+@pytest.mark.parametrize("level_max", [0, 1 << 12])
+def test_batch_16_and_32_words_equal_oracle(rei, level_max):
+    """The one-workgroup solver at its widest instantiations: the large
+    configuration's seeds 0-3 (8-16 words) and three 32-word specifications,
+    in one rei_solve_batch call (with the default hand-off, and with levels
+    over 4096 candidates handed to the per-chunk path), against the oracle."""
+    from oracle_runs import mismatch, solve_many
+    specs = [instances.large_instance(s) for s in range(4)] + [instances.wide_instance(s, 9) for s in range(3)]
+    cache = 64 << 30
+    want = solve_many([(i.alphabet, i.pos, i.neg, i.costs, i.max_cost, cache) for i in specs], workers=4, threads=4)
+    print(f"\ncase: large 0-3 + wide 0-2 batched, level_max {level_max}", flush=True)
+    hs = [rei.Instance(i.alphabet, i.pos, i.neg, i.costs, i.max_cost, cache) for i in specs]
+    if level_max:
+        for h in hs:
+            h.set_batch_level(level_max)
+    got = rei.solve_batch(hs)
+    for k, (g, o) in enumerate(zip(got, want)):
+        assert mismatch(g, o, specs[k].max_cost) is None, (k, mismatch(g, o, specs[k].max_cost))
+    assert {g.cs_words for g in got} >= {16, 32}
+    for h in hs:
+        h.close()
+
+
+@pytest.mark.parametrize("first,cmax,wg,xi", [(1 << 10, 1 << 12, 64, 4), (1 << 18, 1 << 20, 8192, 64),
+                                              (3, 1000, 512, 1)])
+def test_grid_tuning_parameters_give_identical_results(rei, first, cmax, wg, xi):
+    """Every launch shape the grid tuner may pick (and odd ones) gives the
+    oracle's results: a 4-word single instance and a 16-word large one."""
+    for inst in (instances.single_instance(3, (1, 1, 5, 1, 2)), instances.large_instance(0)):
+        print(f"\ncase: {inst.kind} seed {inst.seed} first {first} max {cmax} wg {wg} xi {xi}", flush=True)
+        h = rei.Instance(inst.alphabet, inst.pos, inst.neg, inst.costs, inst.max_cost, 64 << 30)
+        h.set_grid_tuning(first, cmax, wg, xi)
+        g = h.solve()
+        from oracle_runs import mismatch, solve_many
+        o = solve_many([(inst.alphabet, inst.pos, inst.neg, inst.costs, inst.max_cost, 64 << 30)])[0]
+        assert mismatch(g, o, inst.max_cost) is None, mismatch(g, o, inst.max_cost)
+        h.close()
+
+
+def test_grid_tuner_runs_and_keeps_results(rei, tmp_path):
+    """rei_tune_grid picks parameters per word width; solves afterwards (which
+    use the table) still equal the oracle's; the table survives a save/load."""
+    from oracle_runs import mismatch, solve_many
+    specs = [instances.large_instance(s) for s in (0, 2)] + [instances.single_instance(s) for s in (3, 5)]
+    hs = [rei.Instance(i.alphabet, i.pos, i.neg, i.costs, i.max_cost, 64 << 30) for i in specs]
+    chosen = rei.tune_grid(hs)
+    print(f"\ntuned: {chosen}", flush=True)
+    assert set(chosen) >= {"W16", "W4"}
+    rei.tune_save(str(tmp_path / "t.json"))
+    rei.tune_load(str(tmp_path / "t.json"))
+    want = solve_many([(i.alphabet, i.pos, i.neg, i.costs, i.max_cost, 64 << 30) for i in specs])
+    for k, (h, o) in enumerate(zip(hs, want)):
+        g = h.solve()
+        assert mismatch(g, o, specs[k].max_cost) is None, (k, mismatch(g, o, specs[k].max_cost))
+        h.close()

@@ -1,22 +1,65 @@
-"""Continuous-batching server: every request's result equals the same
-instance solved alone, whatever else is in flight."""
+"""Continuous-batching server: every request's result equals the CPU
+oracle's for that specification (status, minimal cost, expression, per-level
+unique and candidate counts), whatever else is in flight, and equals the
+instance solved alone with rei_solve."""
 import pytest
 
-from paper_2305_18575_amd import serving
+from oracle_runs import mismatch, solve_many
+from paper_2305_18575_amd import instances, serving
 
 pytestmark = pytest.mark.gpu
 
 
+def with_trivial(specs):
+    """The mix plus the two trivial specifications (P = {} and P = {eps})."""
+    return specs + [("trivial", instances.Instance("01", [], ["0", "1"], kind="trivial"), 1 << 20),
+                    ("trivial", instances.Instance("01", [""], ["0", "11"], kind="trivial"), 1 << 20)]
+
+
+def oracle_of(specs):
+    return solve_many([(i.alphabet, i.pos, i.neg, i.costs, i.max_cost, cache) for _, i, cache in specs])
+
+
 @pytest.mark.parametrize("budget,qps", [(64 << 30, 2000.0), (256 << 20, 300.0)])
-def test_served_results_equal_alone(rei, budget, qps):
-    specs = serving.request_mix(7, 60)
+def test_served_results_equal_oracle(rei, budget, qps):
+    """Fresh (never solved) instances are served first, so nothing a served
+    request reports can come from an earlier solve; the large share runs to
+    its target's cost (one of its seeds ends out of memory at its 1 GiB
+    cache, which is compared like any other outcome)."""
+    specs = with_trivial(serving.request_mix(7, 60))
     print(f"\nserving {len(specs)} requests, budget {budget}, qps {qps}", flush=True)
+    want = oracle_of(specs)
     hs = serving.stage(rei, specs)
-    alone = [h.solve() for h in hs]
     arrivals = serving.poisson_arrivals(7, len(hs), qps)
     res, lat, ips = serving.run_served(rei, hs, arrivals, budget)
-    for k, (a, b) in enumerate(zip(res, alone)):
-        assert serving.same(a, b), (k, specs[k][0], a, b)
+    for k, (g, o) in enumerate(zip(res, want)):
+        assert mismatch(g, o, specs[k][1].max_cost) is None, (k, specs[k][0], mismatch(g, o, specs[k][1].max_cost))
     assert all(l > 0 for l in lat)
+    alone = [h.solve() for h in hs]
+    for k, (g, o) in enumerate(zip(alone, want)):
+        assert mismatch(g, o, specs[k][1].max_cost) is None, (k, "alone", mismatch(g, o, specs[k][1].max_cost))
+    # served again, now that every instance holds an earlier search's state
+    res2, _, _ = serving.run_served(rei, hs, arrivals, budget)
+    for k, (a, b) in enumerate(zip(res2, alone)):
+        assert serving.same(a, b), (k, specs[k][0], a, b)
     for h in hs:
+        h.close()
+
+
+def test_fresh_wide_and_trivial_requests(rei):
+    """Requests that cannot be batched (16 words per language) and trivial
+    ones, submitted before their instances were ever solved: results equal
+    the oracle's and rei_solve's."""
+    specs = [("large", instances.large_instance(s), 1 << 30) for s in (0, 2, 3, 44)]
+    specs = with_trivial(specs)
+    want = oracle_of(specs)
+    hs = serving.stage(rei, specs)
+    srv = rei.Server(64 << 30, 64, 2, 2)
+    tickets = [srv.submit(h) for h in hs]
+    served = [srv.wait(t)[0] for t in tickets]
+    srv.close()
+    for k, (g, o) in enumerate(zip(served, want)):
+        assert mismatch(g, o, specs[k][1].max_cost) is None, (k, mismatch(g, o, specs[k][1].max_cost))
+    for k, h in enumerate(hs):
+        assert serving.same(h.solve(), served[k]), k
         h.close()
