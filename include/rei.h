@@ -144,6 +144,32 @@ rei_status rei_solve(rei_instance *inst, void *hip_stream, rei_result *out);
 rei_status rei_solve_batch(rei_instance *const *insts, size_t n, void *hip_stream, uint64_t arena_bytes,
                            rei_result *out);
 
+/* ---- batched solving without allocation --------------------------------------
+ * For callers that cannot allocate device memory during a solve: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The same search as rei_solve_batch, with every batchable instance's whole
+ * search kept in the one-workgroup solver (no hand-off to rei_solve's path).
+ * Rows, back-pointers, dedup table and survivor buffers live in a static
+ * device array of 128 MiB (one per GPU, part of the library's device code,
+ * held until the process ends), split in equal shares
+ * among the call's searches; descriptors are written by kernels.  The call
+ * makes no hipMalloc, hipFree, hipHostMalloc or other allocating call.
+ *   insts   n <= 64 distinct instances on the current device, created
+ *           beforehand (rei_create allocates their staged tables and pinned
+ *           result buffers); trivial specifications are answered at once.
+ *   out     n results, as for rei_solve_batch; out[i] equals what
+ *           rei_solve_batch and rei_solve return for insts[i].
+ * The rows of these searches are not kept: rei_row_bits and rei_row_regex
+ * return REI_ERR_INVALID_ARG until the instance is solved another way.
+ * Errors: REI_ERR_TOO_LARGE when n > 64, when an instance cannot run in the
+ * one-workgroup solver (see rei_solve_batch), or when a search outgrows its
+ * share (128 MiB / number of searches; call again with fewer instances);
+ * rei_last_error of the instance concerned says which.  Calls on one GPU
+ * share the array: calls that overlap in time on one GPU race and give
+ * undefined results.  Every call writes what it reads before reading it, so
+ * no state carries over from the previous call. */
+rei_status rei_solve_batch_noalloc(rei_instance *const *insts, size_t n, void *hip_stream, rei_result *out);
+
 /* ---- the batched configuration as one captured graph -------------------------
  * For a fixed set of instances solved again and again (a workload replayed
  * step after step): the batched solver's launches are captured once in a

@@ -34,7 +34,7 @@ EXPORTS = ["rei_create", "rei_solve", "rei_solve_batch", "rei_tune_batch", "rei_
            "rei_kernel_stats", "rei_timing_overhead", "rei_set_hash_bits", "rei_kernel_name",
            "rei_measure_peak", "rei_batch_graph_create", "rei_batch_graph_launch", "rei_batch_graph_results",
            "rei_batch_graph_error", "rei_batch_graph_destroy", "rei_tune_grid", "rei_set_grid_tuning",
-           "rei_tune_save", "rei_tune_load"]
+           "rei_tune_save", "rei_tune_load", "rei_solve_batch_noalloc"]
 
 
 class ReiError(RuntimeError):
@@ -90,6 +90,8 @@ def load_library():
     lib.rei_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, vp, u64,
                                     ctypes.POINTER(_Result)]
     lib.rei_tune_batch.restype = ctypes.c_int
+    lib.rei_solve_batch_noalloc.restype = ctypes.c_int
+    lib.rei_solve_batch_noalloc.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, vp, ctypes.POINTER(_Result)]
     lib.rei_tune_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, vp, u64, ctypes.POINTER(u32),
                                    ctypes.POINTER(u64)]
     lib.rei_server_create.restype = ctypes.c_int
@@ -348,6 +350,24 @@ def solve_batch(instances: Sequence["Instance"], stream: Optional[int] = -1,
     hs = (ctypes.c_void_p * n)(*[i._h for i in instances])
     rs = (_Result * n)()
     st = lib.rei_solve_batch(hs, n, ctypes.c_void_p(stream or 0), int(arena_bytes), rs)
+    if st != 0:
+        msg = "; ".join(sorted({lib.rei_last_error(i._h).decode() for i in instances} - {""}))
+        raise ReiError(st, msg)
+    return [inst._result(rs[k]) for k, inst in enumerate(instances)]
+
+
+def solve_batch_noalloc(instances: Sequence["Instance"], stream: Optional[int] = -1) -> List[Result]:
+    """``rei_solve_batch_noalloc``: the batched search in the library's static
+    device array, with no device allocation (at most 64 instances)."""
+    if not instances:
+        return []
+    lib = load_library()
+    if stream == -1:
+        stream = current_stream_handle()
+    n = len(instances)
+    hs = (ctypes.c_void_p * n)(*[i._h for i in instances])
+    rs = (_Result * n)()
+    st = lib.rei_solve_batch_noalloc(hs, n, ctypes.c_void_p(stream or 0), rs)
     if st != 0:
         msg = "; ".join(sorted({lib.rei_last_error(i._h).decode() for i in instances} - {""}))
         raise ReiError(st, msg)

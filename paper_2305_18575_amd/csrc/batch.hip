@@ -6,10 +6,17 @@
 // path: the same enumeration order, the same deterministic winner rule
 // (smallest enumeration index), the same ordered append.
 #include <algorithm>
+#include <mutex>
 
 #include "device_common.h"
 
 namespace rei {
+
+// Arenas of the allocation-free batched entry point.  In host code this name
+// stands for the array only through hipGetSymbolAddress (static_scratch);
+// kernels receive the address that call returns.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
 
 constexpr uint32_t kWords = kBatchChunk / 32;  // winner bitmap words per chunk
@@ -578,6 +585,19 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
   }  // next instance
 }
 
+// Writes up to kDescPack descriptors, passed by value, to device memory (the
+// allocation-free entry point sets its descriptors up with no copy API).
+struct DescPack {
+  BatchDesc d[kDescPack];
+  uint32_t n;
+};
+__global__ void put_descs(BatchDesc* dst, DescPack p) {
+  static_assert(sizeof(BatchDesc) % 8 == 0, "descriptors copy as 64-bit words");
+  const uint32_t words = p.n * (uint32_t)(sizeof(BatchDesc) / 8);
+  const uint64_t* src = reinterpret_cast<const uint64_t*>(p.d);
+  for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) reinterpret_cast<uint64_t*>(dst)[i] = src[i];
+}
+
 // Puts the work counters of the persistent launches back to zero (a kernel,
 // so that it can sit in a captured graph).
 __global__ void reset_counters(uint32_t* c, uint32_t n) {
@@ -659,6 +679,37 @@ hipError_t batch_resident(int W, bool inl, uint32_t threads, uint32_t* per_cu) {
 #undef REI_OCC
   if (e == hipSuccess) *per_cu = (uint32_t)std::max(nb, 1);
   return e;
+}
+
+hipError_t launch_put_descs(BatchDesc* dst, const BatchDesc* src, uint32_t n, hipStream_t s) {
+  for (uint32_t k = 0; k < n; k += kDescPack) {
+    DescPack p;
+    p.n = std::min<uint32_t>(kDescPack, n - k);
+    for (uint32_t i = 0; i < p.n; ++i) p.d[i] = src[k + i];
+    hipLaunchKernelGGL(put_descs, dim3(1), dim3(256), 0, s, dst + k, p);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t static_scratch(void** out) {
+  constexpr int kDevices = 64;
+  static std::mutex mu;
+  static void* addr[kDevices] = {nullptr};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_reset_counters(uint32_t* c, uint32_t n, hipStream_t s) {

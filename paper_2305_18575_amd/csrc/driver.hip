@@ -143,6 +143,11 @@ struct rei_instance {
   // host copy of the back-pointers for printing (filled on first use)
   std::vector<uint64_t> h_aux;
   bool h_aux_valid = false;
+  // set by rei_solve_batch_noalloc: the last search's rows lived in the
+  // shared static array, not in this instance's buffers; aux_view points at
+  // its back-pointers while that call prints the answer
+  bool rows_elsewhere = false;
+  const uint64_t* aux_view = nullptr;
 
   // result
   std::vector<uint64_t> uniq, cand;
@@ -674,12 +679,13 @@ uint32_t row_cost(const rei_instance* in, uint64_t row) {
 // Back-pointer of a stored row.  Caches with up to 4M rows are copied to the
 // host in one transfer on first use; larger ones are read row by row.
 rei_status row_aux(rei_instance* in, uint64_t row, uint64_t* e) {
+  const uint64_t* aux = in->aux_view ? in->aux_view : in->d_aux;
   if (!in->h_aux_valid) {
     uint64_t rows = 0;
     for (uint32_t c = in->costs.c_char; c < in->lcount.size(); ++c) rows += in->lcount[c];
     if (rows <= (4ull << 20)) {
       in->h_aux.resize(rows);
-      if (rows) HIP_OK(in, hipMemcpy(in->h_aux.data(), in->d_aux, rows * 8, hipMemcpyDeviceToHost));
+      if (rows) HIP_OK(in, hipMemcpy(in->h_aux.data(), aux, rows * 8, hipMemcpyDeviceToHost));
       in->h_aux_valid = true;
     }
   }
@@ -687,7 +693,7 @@ rei_status row_aux(rei_instance* in, uint64_t row, uint64_t* e) {
     *e = in->h_aux[row];
     return REI_OK;
   }
-  HIP_OK(in, hipMemcpy(e, in->d_aux + row, 8, hipMemcpyDeviceToHost));
+  HIP_OK(in, hipMemcpy(e, aux + row, 8, hipMemcpyDeviceToHost));
   return REI_OK;
 }
 
@@ -780,6 +786,8 @@ bool begin_solve(rei_instance* in, double t0) {
   in->known_rows = 0;
   in->pending = 0;
   in->h_aux_valid = false;
+  in->rows_elsewhere = false;
+  in->aux_view = nullptr;
   in->tree.clear();
   in->resume_level = 0;
   in->otf_level = 0;
@@ -1829,6 +1837,133 @@ rei_status rei_solve_batch(rei_instance* const* insts, size_t n, void* hip_strea
   return REI_OK;
 }
 
+rei_status rei_solve_batch_noalloc(rei_instance* const* insts, size_t n, void* hip_stream, rei_result* out) {
+  if (n && (!insts || !out)) return REI_ERR_INVALID_ARG;
+  for (size_t i = 0; i < n; ++i)
+    if (!insts[i]) return REI_ERR_INVALID_ARG;
+  if (n == 0) return REI_OK;
+  auto fail = [&](rei_status st, size_t i, const std::string& msg) {
+    insts[i]->err = msg;
+    return st;
+  };
+  if (n > kStaticMaxInstances)
+    return fail(REI_ERR_TOO_LARGE, 0,
+                "at most " + std::to_string(kStaticMaxInstances) + " instances per allocation-free call");
+  int dev = 0;
+  HIP_OK(insts[0], hipGetDevice(&dev));
+  for (size_t i = 0; i < n; ++i)
+    if (insts[i]->device != dev) return fail(REI_ERR_INVALID_ARG, i, "instance lives on another device");
+  void* base = nullptr;
+  HIP_OK(insts[0], static_scratch(&base));
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    const double t0 = now_s();
+    // searches to run (trivial specifications are answered here), then
+    // ordered by word width (group 0: one word with keys inline)
+    uint32_t todo[kStaticMaxInstances], idx[kStaticMaxInstances];
+    uint32_t nt = 0, m = 0;
+    for (size_t i = 0; i < n; ++i) {
+      rei_instance* in = insts[i];
+      in->err.clear();
+      if (begin_solve(in, t0)) continue;
+      if (!batchable(in))
+        return fail(REI_ERR_TOO_LARGE, i,
+                    "instance cannot run in the one-workgroup solver (more than 32 words, max_cost above 63, "
+                    "too many cuts, OnTheFly mode or per-character costs)");
+      todo[nt++] = (uint32_t)i;
+    }
+    auto group = [&](uint32_t i) { return insts[i]->inl ? 0 : insts[i]->st.W; };
+    for (int g = 0; g <= kBatchMaxW; g = g ? 2 * g : 1)
+      for (uint32_t k = 0; k < nt; ++k)
+        if (group(todo[k]) == g) idx[m++] = todo[k];
+    // equal shares of the array after the descriptor header, 256-byte aligned
+    const uint64_t share = m ? ((kStaticScratchBytes - kStaticHeaderBytes) / m) & ~255ull : 0;
+    BatchDesc stage[kStaticMaxInstances];
+    uint64_t rows_of[kStaticMaxInstances];
+    const uint64_t* aux_of[kStaticMaxInstances];
+    unsigned char* const arena0 = (unsigned char*)base + kStaticHeaderBytes;
+    for (uint32_t k = 0; k < m; ++k) {
+      rei_instance* in = insts[idx[k]];
+      const uint64_t W = in->st.W;
+      const uint64_t tab = in->inl ? 16 : 8;  // table bytes per slot
+      auto up = [](uint64_t b) { return (b + 255) & ~255ull; };
+      const uint64_t fixed = up(kBatchChunk * W * 8) + up(kBatchChunk * 4) + up(kBatchChunk * 8);
+      // largest row count R (and table of T slots, T >= 2 (R + chunk), a
+      // power of two) whose buffers fit the share
+      uint64_t R = 0, T = 0;
+      for (uint64_t t = 1ull << 40; t >= 4096; t >>= 1) {
+        if (fixed + t * tab + 2 * 256 > share) continue;
+        const uint64_t by_mem = (share - fixed - t * tab - 2 * 256) / (8 * W + 8);
+        const uint64_t by_tab = t / 2 > kBatchChunk ? t / 2 - kBatchChunk : 0;
+        const uint64_t r = std::min(std::min(by_mem, by_tab), in->row_cap);
+        if (r > R) {
+          R = r;
+          T = t;
+        }
+      }
+      if (R < 1024 && R < in->row_cap)
+        return fail(REI_ERR_TOO_LARGE, idx[k], "the static array's share per instance is too small; call with fewer instances");
+      unsigned char* p = arena0 + (uint64_t)k * share;
+      BatchDesc d = make_desc(in);
+      d.skey = (uint64_t*)p;
+      p += up(kBatchChunk * W * 8);
+      d.se = (uint32_t*)p;
+      p += up(kBatchChunk * 4);
+      d.spos = (uint64_t*)p;
+      p += up(kBatchChunk * 8);
+      d.rows = (uint64_t*)p;
+      p += up(R * W * 8);
+      d.aux = (uint64_t*)p;
+      p += up(R * 8);
+      d.slots = (uint64_t*)p;
+      p += T * 8;
+      d.sref = in->inl ? (uint64_t*)p : nullptr;
+      d.rows_alloc = R;
+      d.slot_mask = T - 1;
+      d.level_max = ~0ull;  // the whole search stays in the workgroup
+      d.time_ticks = 0;
+      stage[k] = d;
+      rows_of[k] = R;
+      aux_of[k] = d.aux;
+      __atomic_store_n(&in->h_state->done, 0u, __ATOMIC_RELEASE);
+    }
+    BatchDesc* d_desc = (BatchDesc*)base;
+    if (m) HIP_OK(insts[0], launch_put_descs(d_desc, stage, m, s));
+    // one launch per word width, one after another on the caller's stream
+    for (uint32_t k = 0; k < m;) {
+      rei_instance* in0 = insts[idx[k]];
+      const int g = group(idx[k]);
+      uint32_t e = k;
+      while (e < m && group(idx[e]) == g) ++e;
+      HIP_OK(in0, launch_solve_batch(g ? g : 1, g == 0, choose_threads(g, e - k), d_desc + k, e - k, s));
+      k = e;
+    }
+    HIP_OK(insts[0], hipStreamSynchronize(s));
+    rei_status r = REI_OK;
+    for (uint32_t k = 0; k < m; ++k) {
+      rei_instance* in = insts[idx[k]];
+      const bool more = batch_take_state(in);
+      in->rows_elsewhere = true;
+      if (more) {
+        r = fail(REI_ERR_TOO_LARGE, idx[k],
+                 "the search outgrew its share of the static array (" + std::to_string(rows_of[k]) +
+                     " rows); call with fewer instances");
+        continue;
+      }
+      in->aux_view = aux_of[k];  // valid until this call returns
+      const rei_status f = finish_solve(in, t0);
+      in->aux_view = nullptr;
+      in->h_aux_valid = false;
+      if (f != REI_OK && r == REI_OK) r = f;
+    }
+    if (r != REI_OK) return r;
+    for (size_t i = 0; i < n; ++i) out[i] = insts[i]->res;
+  } catch (const std::bad_alloc&) {
+    return REI_ERR_HOST_ALLOC;
+  }
+  return REI_OK;
+}
+
 rei_status rei_tune_batch(rei_instance* const* insts, size_t n, void* hip_stream, uint64_t arena_bytes,
                           uint32_t* threads_out, uint64_t* level_max_out) {
   if (n == 0 || !insts) return REI_ERR_INVALID_ARG;
@@ -2079,6 +2214,10 @@ rei_status rei_level_size(const rei_instance* inst, uint32_t cost, uint64_t* out
 rei_status rei_row_bits(rei_instance* inst, uint32_t cost, uint64_t i, uint64_t* words_out) {
   if (!inst || !words_out || cost >= inst->lcount.size() || i >= inst->lcount[cost])
     return REI_ERR_INVALID_ARG;
+  if (inst->rows_elsewhere) {
+    inst->err = "the last search ran in the shared static array; its rows were not kept";
+    return REI_ERR_INVALID_ARG;
+  }
   const int W = inst->st.W;
   HIP_OK(inst, hipMemcpy(words_out, inst->d_rows + (inst->lstart[cost] + i) * W, W * 8,
                          hipMemcpyDeviceToHost));
@@ -2087,6 +2226,10 @@ rei_status rei_row_bits(rei_instance* inst, uint32_t cost, uint64_t i, uint64_t*
 
 rei_status rei_row_regex(rei_instance* inst, uint32_t cost, uint64_t i, char* buf, size_t cap) {
   if (!inst || !buf || cost >= inst->lcount.size() || i >= inst->lcount[cost]) return REI_ERR_INVALID_ARG;
+  if (inst->rows_elsewhere) {
+    inst->err = "the last search ran in the shared static array; its rows were not kept";
+    return REI_ERR_INVALID_ARG;
+  }
   std::string s;
   int op;
   rei_status r = print_row(inst, inst->lstart[cost] + i, &s, &op);

@@ -299,6 +299,21 @@ hipError_t batch_resident(int W, bool inl, uint32_t threads, uint32_t* per_cu);
 // Zeroes n (<= 64) work counters with a kernel (graph-capturable).
 hipError_t launch_reset_counters(uint32_t* c, uint32_t n, hipStream_t s);
 
+// ---- the allocation-free batched entry point ------------------------------
+// A static device array (one per GPU, held until the process ends) carries
+// the per-instance arenas and descriptors of rei_solve_batch_noalloc.
+constexpr uint64_t kStaticScratchBytes = 128ull << 20;
+constexpr uint32_t kStaticMaxInstances = 64;        // instances per call
+constexpr uint64_t kStaticHeaderBytes = 64ull << 10;  // descriptors at the front
+// Device address of that array on the current device (looked up once per
+// device with hipGetSymbolAddress, then kept).
+hipError_t static_scratch(void** out);
+static_assert(kStaticMaxInstances * sizeof(BatchDesc) <= kStaticHeaderBytes, "descriptors fit the header");
+// Writes n descriptors from host memory to dst with kernels that take them
+// as arguments (kDescPack per launch), on stream s.
+constexpr uint32_t kDescPack = 8;
+hipError_t launch_put_descs(BatchDesc* dst, const BatchDesc* src, uint32_t n, hipStream_t s);
+
 // Achievable peak of one operation class on the current device (peaks.hip):
 // kind 0 stream copy (rate = bytes read + written per second), 1 random
 // table reads, 2 random reads plus atomicMin (rate = probes per second),
