@@ -262,14 +262,23 @@ rei_status rei_tune_load(const char *path);
  * A server solves submitted instances asynchronously.  Requests are admitted
  * in arrival order while the device bytes they need fit hbm_budget (0 = the
  * device's free memory when the server is created, less 8 GB kept for
- * everything else); admitted
- * requests that can be batched (as in rei_solve_batch) are launched together
- * on a free stream from a pool of n_streams, so requests arriving while others
- * run are started at once and their work overlaps on the device; the others
- * (and batched ones that hand off or outgrow their preallocated rows) run
- * rei_solve's path on one of n_workers worker threads, each with its own
- * stream (0 = defaults: 64 per batch, 4 streams, 4 workers).  Each result
- * equals rei_solve's for that instance.  The budget counts the device bytes
+ * everything else), and their device buffers are allocated at admission.
+ * Admitted requests that can be batched (as in rei_solve_batch) reach the
+ * device in one of two modes (rei_server_set_queue_mode):
+ *  - queue mode (default): per word-width group a persistent launch of the
+ *    batched solver takes requests from a ring in pinned host memory while
+ *    it runs; each admitted request is written into the ring and published,
+ *    and the next free workgroup starts it, with no launch in between.  A
+ *    launch ends after its workgroups found no work for 2 ms; the next
+ *    admitted request of the group starts another.
+ *  - launch mode: admitted requests are launched together on a free stream
+ *    from a pool of n_streams (at most max_batch per launch), so requests
+ *    arriving while others run are started at once and their work overlaps
+ *    on the device.
+ * The others (and batched ones that hand off or outgrow their preallocated
+ * rows) run rei_solve's path on one of n_workers worker threads, each with
+ * its own stream (0 = defaults: 64 per batch, 4 streams, 4 workers).  Each
+ * result equals rei_solve's for that instance.  The budget counts the device bytes
  * of requests in flight (an estimate made at submit: the batched arena, or
  * the cache budget plus its table for the per-chunk path); a finished
  * instance keeps its buffers until rei_destroy, so that nothing on the
@@ -289,6 +298,9 @@ rei_status rei_server_poll(rei_server *srv, uint64_t ticket, int wait, int *done
                            double *latency_s);
 /* Finishes every submitted request, then frees the server. */
 void rei_server_destroy(rei_server *srv);
+/* Queue mode (enable != 0, the default) or launch mode, as described above.
+ * REI_ERR_INVALID_ARG once a request has been submitted. */
+rei_status rei_server_set_queue_mode(rei_server *srv, int enable);
 
 /* Free the device memory of the instance's last search (language cache,
  * dedup table, chunk buffers) but keep the staged specification and the

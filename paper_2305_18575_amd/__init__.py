@@ -34,7 +34,7 @@ EXPORTS = ["rei_create", "rei_solve", "rei_solve_batch", "rei_tune_batch", "rei_
            "rei_kernel_stats", "rei_timing_overhead", "rei_set_hash_bits", "rei_kernel_name",
            "rei_measure_peak", "rei_batch_graph_create", "rei_batch_graph_launch", "rei_batch_graph_results",
            "rei_batch_graph_error", "rei_batch_graph_destroy", "rei_tune_grid", "rei_set_grid_tuning",
-           "rei_tune_save", "rei_tune_load", "rei_solve_batch_noalloc"]
+           "rei_tune_save", "rei_tune_load", "rei_solve_batch_noalloc", "rei_server_set_queue_mode"]
 
 
 class ReiError(RuntimeError):
@@ -103,6 +103,8 @@ def load_library():
                                     ctypes.POINTER(_Result), ctypes.POINTER(ctypes.c_double)]
     lib.rei_server_destroy.restype = None
     lib.rei_server_destroy.argtypes = [vp]
+    lib.rei_server_set_queue_mode.restype = ctypes.c_int
+    lib.rei_server_set_queue_mode.argtypes = [vp, ctypes.c_int]
     lib.rei_destroy.restype = None
     lib.rei_destroy.argtypes = [vp]
     lib.rei_trim.restype = ctypes.c_int
@@ -558,9 +560,12 @@ class Server:
     """Continuous-batching server (``rei_server_*``): submit staged instances,
     poll or wait for their results."""
 
-    def __init__(self, hbm_budget: int = 0, max_batch: int = 64, n_streams: int = 4, n_workers: int = 4):
+    def __init__(self, hbm_budget: int = 0, max_batch: int = 64, n_streams: int = 4, n_workers: int = 4,
+                 queue: bool = True):
         """hbm_budget: device bytes the requests in flight may hold (0 = the
-        free device memory at creation less 8 GB)."""
+        free device memory at creation less 8 GB).  queue: persistent
+        launches fed from a ring while they run (True) or one batched launch
+        per admitted group (False)."""
         lib = load_library()
         self._lib = lib
         h = ctypes.c_void_p()
@@ -570,6 +575,9 @@ class Server:
             raise ReiError(st, "rei_server_create")
         self._h = h
         self._inst = {}
+        st = lib.rei_server_set_queue_mode(h, 1 if queue else 0)
+        if st != 0:
+            raise ReiError(st, "rei_server_set_queue_mode")
 
     def submit(self, inst: "Instance") -> int:
         t = ctypes.c_uint64()

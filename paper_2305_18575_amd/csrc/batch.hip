@@ -136,9 +136,16 @@ __device__ __forceinline__ bool decode_index(const BatchDesc& d, const uint64_t*
 // and solves instance order[item] (or item itself when order is null),
 // until the items run out, so the longest instances can start first
 // whatever the grid size.
+// Queue (qc != nullptr, with next): descs is a ring the host fills while the
+// launch runs (n_inst slots, published up to qc->tail); a workgroup claims
+// the next published slot by compare-and-swap on *next (zero at launch), so
+// a slot is taken only once it exists and exactly once.  Every workgroup
+// leaves once it has waited qc->idle_ticks without finding a slot, or when
+// the host sets qc->closing; slots published after the last one left are
+// found unsolved by the host and published again in its next launch.
 template <int W, bool kInl, uint32_t kT>
 __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32_t n_inst, const uint32_t* order,
-                                                  uint32_t* next) {
+                                                  uint32_t* next, const QueueCtl* qc) {
   static_assert(kT >= kBatchChunk / 32 && kT <= batch_max_threads(W) && kT % 64 == 0, "one scan value per thread");
   constexpr uint32_t kIc = batch_max_ic(W), kPairs = batch_max_pairs(W);
   constexpr uint32_t kWaves = kT / 64;
@@ -161,6 +168,30 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
   if (!next) {
     if (pass || blockIdx.x >= n_inst) return;
     item = blockIdx.x;
+  } else if (qc) {
+    if (threadIdx.x == 0) {
+      uint32_t got = ~0u;
+      const long long t_wait = wall_clock64();
+      for (;;) {
+        const uint32_t tail = __hip_atomic_load(&qc->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+        const uint32_t h = __hip_atomic_load(next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (h < tail && h < n_inst) {
+          if (atomicCAS(next, h, h + 1) == h) {
+            got = h;
+            break;
+          }
+          continue;  // another workgroup took it: look again
+        }
+        const uint32_t closing = __hip_atomic_load(&qc->closing, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (closing || (uint64_t)(wall_clock64() - t_wait) > qc->idle_ticks) break;
+        __builtin_amdgcn_s_sleep(16);
+      }
+      s_item = got;
+    }
+    __syncthreads();
+    item = s_item;
+    __syncthreads();
+    if (item >= n_inst) return;
   } else {
     if (threadIdx.x == 0) s_item = atomicAdd(next, 1u);
     __syncthreads();
@@ -611,13 +642,15 @@ hipError_t set_hash_mask_batch(uint64_t mask) {
 }
 
 hipError_t launch_solve_batch(int W, bool inl, uint32_t threads, const BatchDesc* d_descs, uint32_t n,
-                              hipStream_t s, const uint32_t* order, uint32_t* next, uint32_t grid) {
+                              hipStream_t s, const uint32_t* order, uint32_t* next, uint32_t grid,
+                              const QueueCtl* qc) {
   if (n == 0) return hipSuccess;
   if (!next) grid = n;
-  if (grid == 0 || grid > n) return hipErrorInvalidValue;
+  if (qc && !next) return hipErrorInvalidValue;
+  if (grid == 0 || (grid > n && !qc)) return hipErrorInvalidValue;
 #define REI_BATCH_L(WW, II, TT)                                                                          \
   launch_timed(solve_batch<WW, II, std::min(TT, batch_max_threads(WW))>, dim3(grid), dim3(TT), 0, s, d_descs, n, \
-               order, next)
+               order, next, qc)
 #define REI_BATCH_T(WW, II)                                              \
   if (threads > batch_max_threads(WW)) return hipErrorInvalidValue;      \
   switch (threads) {                                                     \

@@ -38,28 +38,121 @@ __device__ __forceinline__ uint64_t fingerprint(uint64_t h) { return (h >> 40) &
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
-__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
-  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
-  lo = __shfl_xor((int)lo, m, kWave);
-  hi = __shfl_xor((int)hi, m, kWave);
-  return ((uint64_t)hi << 32) | lo;
+// The value of lane (lane ^ J) for one 32-bit register, J a power of two
+// below 64, by the cheapest cross-lane route: DPP quad permutes for 1 and 2,
+// a DPP rotate by 8 within each 16-lane row for 8 (i + 8 mod 16 = i ^ 8),
+// a ds_swizzle in bit-mask mode (and 0x1f, xor J, within 32 lanes) for 4
+// and 16, and a ds_bpermute for 32.
+template <int J>
+__device__ __forceinline__ uint32_t lane_xor32(uint32_t v) {
+  if constexpr (J == 1)
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
+  else if constexpr (J == 2)
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
+  else if constexpr (J == 8)
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, true);  // row_ror:8
+  else if constexpr (J == 4 || J == 16)
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (J << 10));
+  else
+    return (uint32_t)__shfl_xor((int)v, J, kWave);
+}
+
+// One stage of the transpose on one 32-bit half, J < 32: swaps bit J of the
+// row index with bit J of the column index.  M has the bits whose index has
+// bit J clear.  A lane with bit J clear keeps its M bits and takes the
+// partner's M bits moved up by J (a left rotate by J puts them there); a
+// lane with bit J set keeps ~M and takes the partner's ~M bits moved down
+// (a right rotate by J).  One cross-lane move, one rotate (alignbit with a
+// per-lane amount), one bit select.
+template <int J, uint32_t M>
+__device__ __forceinline__ uint32_t transpose_stage32(uint32_t x, uint32_t lane) {
+  const bool up = (lane & J) != 0;
+  const uint32_t keep = up ? ~M : M;
+  const uint32_t rot = up ? (uint32_t)J : 32u - J;  // right-rotate amount
+  const uint32_t b = lane_xor32<J>(x);
+  const uint32_t moved = __builtin_amdgcn_alignbit(b, b, rot);
+  return (x & keep) | (moved & ~keep);
 }
 
 // 64x64 bit-matrix transpose across a wave: on entry lane r holds row r, on
-// exit lane c holds column c (bit r of the result = bit c of row r).  Each
-// stage swaps one bit of the row index with the same bit of the column index.
+// exit lane c holds column c (bit r of the result = bit c of row r).  The
+// first stage (bit 5) exchanges 32-bit halves between lanes 32 apart; the
+// other five work on each half alone.
 __device__ __forceinline__ uint64_t transpose64(uint64_t a) {
   const uint32_t lane = lane_id();
-  const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
-                             0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    const int j = 32 >> s;
-    const uint64_t m = masks[s];
-    uint64_t b = shfl_xor64(a, j);
-    a = (lane & j) ? ((a & ~m) | ((b >> j) & m)) : ((a & m) | ((b & m) << j));
+  uint32_t lo = (uint32_t)a, hi = (uint32_t)(a >> 32);
+  {
+    const uint32_t blo = lane_xor32<32>(lo), bhi = lane_xor32<32>(hi);
+    const bool up = (lane & 32) != 0;
+    const uint32_t nlo = up ? bhi : lo, nhi = up ? hi : blo;
+    lo = nlo;
+    hi = nhi;
   }
-  return a;
+  lo = transpose_stage32<16, 0x0000FFFFu>(lo, lane);
+  hi = transpose_stage32<16, 0x0000FFFFu>(hi, lane);
+  lo = transpose_stage32<8, 0x00FF00FFu>(lo, lane);
+  hi = transpose_stage32<8, 0x00FF00FFu>(hi, lane);
+  lo = transpose_stage32<4, 0x0F0F0F0Fu>(lo, lane);
+  hi = transpose_stage32<4, 0x0F0F0F0Fu>(hi, lane);
+  lo = transpose_stage32<2, 0x33333333u>(lo, lane);
+  hi = transpose_stage32<2, 0x33333333u>(hi, lane);
+  lo = transpose_stage32<1, 0x55555555u>(lo, lane);
+  hi = transpose_stage32<1, 0x55555555u>(hi, lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// The W words of row `row` (zeros when !valid), read as 16-byte loads that
+// are all issued before any is used (rows are 16-byte aligned for W >= 2).
+template <int W>
+__device__ __forceinline__ void load_row(const uint64_t* rows, uint64_t row, bool valid, uint64_t (&v)[W]) {
+  if constexpr (W == 1) {
+    v[0] = valid ? rows[row] : 0ull;
+  } else {
+#pragma unroll
+    for (int k = 0; k < W; ++k) v[k] = 0;
+    if (valid) {
+      const ulonglong2* p = reinterpret_cast<const ulonglong2*>(rows + row * W);
+      ulonglong2 t[W / 2];
+#pragma unroll
+      for (int k = 0; k < W / 2; ++k) t[k] = p[k];
+#pragma unroll
+      for (int k = 0; k < W / 2; ++k) {
+        v[2 * k] = t[k].x;
+        v[2 * k + 1] = t[k].y;
+      }
+    }
+  }
+}
+
+// Copies n 32-bit values from global memory to LDS with threads tid, tid +
+// nt, ...: 16-byte loads, four in flight per thread, when both ends are
+// 16-byte aligned; single values otherwise and for the tail.
+__device__ __forceinline__ void stage_u32(uint32_t* dst, const uint32_t* src, uint32_t n, uint32_t tid, uint32_t nt) {
+  uint32_t done = 0;
+  if ((((size_t)dst | (size_t)src) & 15) == 0) {
+    const uint32_t n4 = n / 4;
+    const uint4* s4 = reinterpret_cast<const uint4*>(src);
+    uint4* d4 = reinterpret_cast<uint4*>(dst);
+    uint32_t q = tid;
+    for (; q + 3 * nt < n4; q += 4 * nt) {
+      const uint4 v0 = s4[q], v1 = s4[q + nt], v2 = s4[q + 2 * nt], v3 = s4[q + 3 * nt];
+      d4[q] = v0;
+      d4[q + nt] = v1;
+      d4[q + 2 * nt] = v2;
+      d4[q + 3 * nt] = v3;
+    }
+    for (; q < n4; q += nt) d4[q] = s4[q];
+    done = 4 * n4;
+  }
+  uint32_t q = done + tid;
+  for (; q + 3 * nt < n; q += 4 * nt) {
+    const uint32_t v0 = src[q], v1 = src[q + nt], v2 = src[q + 2 * nt], v3 = src[q + 3 * nt];
+    dst[q] = v0;
+    dst[q + nt] = v1;
+    dst[q + 2 * nt] = v2;
+    dst[q + 3 * nt] = v3;
+  }
+  for (; q < n; q += nt) dst[q] = src[q];
 }
 
 // ---- dedup table -----------------------------------------------------------

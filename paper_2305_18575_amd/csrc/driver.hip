@@ -2408,12 +2408,21 @@ const char* rei_kernel_name(rei_kernel_class k) {
 // ---- serving: continuous batching -----------------------------------------
 //
 // Requests (staged instances) queue on submit.  A scheduler thread admits
-// them in arrival order while their device bytes fit the budget, launches
-// each admitted group as one batched solve on a free stream (so groups that
-// arrive while others run overlap on the device), collects finished groups by
-// event, and hands instances that cannot be batched, or that outgrew their
-// preallocated rows, to worker threads that run the per-chunk path on their
-// own streams.  Every result equals rei_solve's for that instance.
+// them in arrival order while their device bytes fit the budget (their
+// arenas are allocated at admission), and hands instances that cannot be
+// batched, or that outgrew their preallocated rows or reached a level too
+// large for one workgroup, to worker threads that run the per-chunk path on
+// their own streams.  Batchable requests reach the device one of two ways:
+//  * queue mode (the default): per word-width group, a persistent launch of
+//    the batched solver takes requests from a ring in pinned memory while it
+//    runs; the scheduler writes each admitted request's descriptor into the
+//    ring and publishes it, so a request arriving while others are on the
+//    device starts as soon as a workgroup is free, with no launch.  A launch
+//    ends when its workgroups have found no work for a while; the next
+//    admission starts a new one.
+//  * launch mode: each admitted group is one batched solve on a free stream
+//    (groups that arrive while others run overlap on the device).
+// Every result equals rei_solve's for that instance.
 
 struct rei_server {
   uint64_t budget = 0;
@@ -2449,6 +2458,27 @@ struct rei_server {
   std::thread sched;
   std::vector<std::thread> workers;
   int busy_workers = 0;
+  // queue mode: one ring and persistent launch per word-width group (slot
+  // 0: one word with keys inline; slot 1 + log2 W otherwise)
+  bool queue_mode = true;
+  struct QGroup {
+    BatchDesc* h_ring = nullptr;  // pinned, read by the launch
+    BatchDesc* d_ring = nullptr;
+    QueueCtl* h_ctl = nullptr;    // pinned control block
+    QueueCtl* d_ctl = nullptr;
+    uint32_t* d_next = nullptr;   // next slot to claim (device)
+    hipStream_t s = nullptr;
+    hipEvent_t ev = nullptr;      // recorded after the launch
+    bool running = false;
+    uint32_t tail = 0;            // slots published to the current launch
+    std::vector<uint64_t> slot;   // ticket of each published slot
+    std::deque<uint64_t> pending; // admitted, not yet published
+    uint32_t threads = 0, grid = 0;
+  };
+  QGroup qg[8];
+  std::vector<uint64_t> published;  // tickets published, results not yet taken
+  hipStream_t setup = nullptr;      // arena set-up at admission
+  uint64_t idle_ticks = 0;
 };
 
 namespace {
@@ -2506,13 +2536,268 @@ void server_worker(rei_server* sv, hipStream_t s) {
   }
 }
 
+constexpr uint32_t kRing = 4096;        // ring slots per queue launch
+constexpr uint32_t kQueueIdleUs = 2000;  // a queue launch's workgroups leave after this long without work
+
+int queue_slot(const rei_instance* in) {
+  if (in->inl) return 0;
+  int k = 1;
+  for (int w = in->st.W; w > 1; w >>= 1) ++k;
+  return k;
+}
+
+// The ring, control block, counter, stream and event of a group, on first use.
+rei_status queue_group_init(rei_server* sv, int slot, rei_instance* in) {
+  rei_server::QGroup& q = sv->qg[slot];
+  if (q.h_ring) return REI_OK;
+  const unsigned fl = hipHostMallocMapped | hipHostMallocPortable | hipHostMallocCoherent;
+  HIP_OK(in, hipHostMalloc((void**)&q.h_ring, kRing * sizeof(BatchDesc), fl));
+  HIP_OK(in, hipHostGetDevicePointer((void**)&q.d_ring, q.h_ring, 0));
+  HIP_OK(in, hipHostMalloc((void**)&q.h_ctl, sizeof(QueueCtl), fl));
+  HIP_OK(in, hipHostGetDevicePointer((void**)&q.d_ctl, q.h_ctl, 0));
+  q.h_ctl->tail = 0;
+  q.h_ctl->closing = 0;
+  q.h_ctl->idle_ticks = sv->idle_ticks;
+  HIP_OK(in, hipMalloc((void**)&q.d_next, 64 * sizeof(uint32_t)));
+  HIP_OK(in, hipStreamCreateWithFlags(&q.s, hipStreamNonBlocking));
+  HIP_OK(in, hipEventCreateWithFlags(&q.ev, hipEventDisableTiming));
+  // 256 threads per workgroup and a quarter of the compute units per group:
+  // a workgroup of the batched solver needs about 165 VGPRs per lane, so a
+  // compute unit holds three of 256 threads (one of 512); with every group
+  // launched, the persistent launches of all groups are resident side by
+  // side, and one group busy with a stream of requests never keeps another
+  // group's launch from starting
+  q.threads = 256;
+  q.grid = std::max<uint32_t>(1, device_cus(sv->device) / 4);
+  return REI_OK;
+}
+
+// Starts a queue launch of group slot over the slots published so far.
+rei_status queue_launch(rei_server* sv, int slot, rei_instance* in) {
+  rei_server::QGroup& q = sv->qg[slot];
+  const int g = slot == 0 ? 0 : 1 << (slot - 1);
+  q.h_ctl->closing = 0;
+  q.h_ctl->idle_ticks = sv->idle_ticks;
+  HIP_OK(in, launch_reset_counters(q.d_next, 1, q.s));
+  HIP_OK(in, launch_solve_batch(g ? g : 1, g == 0, q.threads, q.d_ring, kRing, q.s, nullptr, q.d_next, q.grid,
+                                q.d_ctl));
+  HIP_OK(in, hipEventRecord(q.ev, q.s));
+  q.running = true;
+  return REI_OK;
+}
+
 uint64_t request_reserve(const rei_server* sv, const rei_instance* in) {
   uint64_t b = batchable(in) ? batch_reserve(in, sv->arena)
                              : in->cache_bytes + pow2_at_least(4 * (in->row_cap + 1)) * 8;
   return std::min(b, sv->budget);
 }
 
+// The descriptor of a served request: hand-off of large levels as for
+// rei_solve_batch, none on time (the persistent launches hold their
+// compute units anyway).
+BatchDesc queue_desc(const rei_instance* in) {
+  BatchDesc d = make_desc(in);
+  d.time_ticks = 0;
+  return d;
+}
+
+void server_sched_queue(rei_server* sv) {
+  (void)hipSetDevice(sv->device);
+  std::unique_lock<std::mutex> lk(sv->mu);
+  for (;;) {
+    bool worked = false, any_running = false;
+    // launches that ended: published slots still unsolved were never
+    // claimed; they go back to the front of their group, in order
+    for (int k = 0; k < 8; ++k) {
+      rei_server::QGroup& q = sv->qg[k];
+      if (!q.running) continue;
+      if (hipEventQuery(q.ev) != hipSuccess) {
+        any_running = true;
+        continue;
+      }
+      q.running = false;
+      std::vector<uint64_t> again;
+      for (uint32_t i = 0; i < q.tail; ++i) {
+        const uint64_t t = q.slot[i];
+        auto it = std::find(sv->published.begin(), sv->published.end(), t);
+        if (it == sv->published.end()) continue;  // result taken already
+        if (__atomic_load_n(&sv->reqs[t].in->h_state->done, __ATOMIC_ACQUIRE)) continue;  // taken below
+        sv->published.erase(it);
+        again.push_back(t);
+      }
+      for (auto it = again.rbegin(); it != again.rend(); ++it) q.pending.push_front(*it);
+      q.tail = 0;
+      q.slot.clear();
+      __atomic_store_n(&q.h_ctl->tail, 0u, __ATOMIC_RELEASE);
+      worked = true;
+    }
+    // finished requests: results from their pinned buffers
+    struct Fin {
+      uint64_t t;
+      rei_instance* in;
+      double t0;
+      bool more;
+      rei_status r;
+    };
+    std::vector<Fin> fin;
+    for (size_t i = 0; i < sv->published.size();) {
+      const uint64_t t = sv->published[i];
+      const auto& rq = sv->reqs[t];
+      if (__atomic_load_n(&rq.in->h_state->done, __ATOMIC_ACQUIRE)) {
+        fin.push_back({t, rq.in, rq.t_submit, false, REI_OK});
+        sv->published.erase(sv->published.begin() + (long)i);
+      } else {
+        ++i;
+      }
+    }
+    if (!fin.empty()) {
+      lk.unlock();
+      for (Fin& f : fin) {
+        try {
+          f.more = batch_take_state(f.in);
+          if (!f.more) f.r = finish_solve(f.in, f.t0);
+        } catch (const std::bad_alloc&) {
+          f.r = REI_ERR_HOST_ALLOC;
+        }
+      }
+      lk.lock();
+      for (const Fin& f : fin) {
+        if (f.more) {
+          sv->reqs[f.t].begun = true;  // begun at admission: the per-chunk path continues it
+          sv->grid_queue.push_back(f.t);
+          sv->cv_grid.notify_one();
+        } else {
+          server_finish(sv, f.t, f.r);
+        }
+      }
+      worked = true;
+    }
+    // admission in arrival order while the bytes fit; arenas allocated now
+    struct Adm {
+      uint64_t t;
+      rei_instance* in;
+      double t0;
+      bool trivial;
+      rei_status r;
+    };
+    std::vector<Adm> adm;
+    while (!sv->queue.empty()) {
+      const uint64_t t = sv->queue.front();
+      auto& rq = sv->reqs[t];
+      if (sv->in_use + rq.reserve > sv->budget) break;
+      sv->in_use += rq.reserve;
+      sv->queue.pop_front();
+      if (batchable(rq.in)) {
+        adm.push_back({t, rq.in, rq.t_submit, false, REI_OK});
+      } else {
+        sv->grid_queue.push_back(t);
+        sv->cv_grid.notify_one();
+      }
+    }
+    if (!adm.empty()) {
+      lk.unlock();
+      bool setup_used = false;
+      for (Adm& a : adm) {
+        rei_instance* in = a.in;
+        try {
+          in->err.clear();
+          if (begin_solve(in, a.t0)) {
+            a.trivial = true;
+            continue;
+          }
+          const uint64_t R = batch_rows(in, sv->arena);
+          if ((a.r = ensure_chunk_buffers(in, kBatchChunk)) != REI_OK) continue;
+          if ((a.r = ensure_rows(in, R, sv->setup)) != REI_OK) continue;
+          if ((a.r = ensure_table(in, in->rows_alloc + kBatchChunk, sv->setup, false)) != REI_OK) continue;
+          setup_used = true;
+          __atomic_store_n(&in->h_state->done, 0u, __ATOMIC_RELEASE);
+        } catch (const std::bad_alloc&) {
+          a.r = REI_ERR_HOST_ALLOC;
+        }
+      }
+      if (setup_used && hipStreamSynchronize(sv->setup) != hipSuccess)
+        for (Adm& a : adm)
+          if (a.r == REI_OK && !a.trivial) a.r = REI_ERR_DEVICE;
+      lk.lock();
+      for (const Adm& a : adm) {
+        if (a.r != REI_OK || a.trivial) {
+          server_finish(sv, a.t, a.r);
+          continue;
+        }
+        const int k = queue_slot(a.in);
+        rei_status r = queue_group_init(sv, k, a.in);
+        if (r != REI_OK) {
+          server_finish(sv, a.t, r);
+          continue;
+        }
+        sv->qg[k].pending.push_back(a.t);
+      }
+      worked = true;
+    }
+    // publish pending requests into their group's ring; start a launch
+    // where none runs; a full ring is closed and published again once its
+    // launch has ended
+    for (int k = 0; k < 8; ++k) {
+      rei_server::QGroup& q = sv->qg[k];
+      if (q.pending.empty()) continue;
+      if (q.tail >= kRing) {
+        if (q.running) __atomic_store_n(&q.h_ctl->closing, 1u, __ATOMIC_RELEASE);
+        continue;
+      }
+      rei_instance* first = sv->reqs[q.pending.front()].in;
+      const uint32_t before = q.tail;
+      while (!q.pending.empty() && q.tail < kRing) {
+        const uint64_t t = q.pending.front();
+        q.pending.pop_front();
+        q.h_ring[q.tail] = queue_desc(sv->reqs[t].in);
+        q.slot.push_back(t);
+        sv->published.push_back(t);
+        ++q.tail;
+      }
+      std::atomic_thread_fence(std::memory_order_release);
+      __atomic_store_n(&q.h_ctl->tail, q.tail, __ATOMIC_RELEASE);
+      if (!q.running) {
+        const rei_status r = queue_launch(sv, k, first);
+        if (r != REI_OK) {
+          // nothing of this launch runs: its slots fail
+          for (uint32_t i = before; i < q.tail; ++i) {
+            const uint64_t t = q.slot[i];
+            sv->published.erase(std::find(sv->published.begin(), sv->published.end(), t));
+            server_finish(sv, t, r);
+          }
+          q.tail = before;
+          q.slot.resize(before);
+          __atomic_store_n(&q.h_ctl->tail, q.tail, __ATOMIC_RELEASE);
+          continue;
+        }
+      }
+      any_running = true;
+      worked = true;
+    }
+    bool idle = sv->queue.empty() && sv->published.empty();
+    for (int k = 0; k < 8; ++k) idle = idle && sv->qg[k].pending.empty();
+    if (sv->stopping && idle) {
+      // no more work: end the launches still waiting for some
+      for (int k = 0; k < 8; ++k)
+        if (sv->qg[k].running) __atomic_store_n(&sv->qg[k].h_ctl->closing, 1u, __ATOMIC_RELEASE);
+      bool any = false;
+      for (int k = 0; k < 8; ++k) any = any || sv->qg[k].running;
+      if (!any) return;
+    }
+    if (!worked) sv->cv_sched.wait_for(lk, std::chrono::microseconds(any_running || !sv->published.empty() ? 10 : 2000));
+  }
+}
+
 void server_sched(rei_server* sv) {
+  {
+    // the mode is fixed once the first request is in
+    std::unique_lock<std::mutex> lk(sv->mu);
+    sv->cv_sched.wait(lk, [&] { return sv->stopping || !sv->queue.empty(); });
+  }
+  if (sv->queue_mode) {
+    server_sched_queue(sv);
+    return;
+  }
   (void)hipSetDevice(sv->device);
   std::unique_lock<std::mutex> lk(sv->mu);
   for (;;) {
@@ -2617,6 +2902,11 @@ rei_status rei_server_create(uint64_t hbm_budget, uint32_t max_batch, uint32_t n
     hbm_budget = free_b > 2 * reserve ? free_b - reserve : free_b / 2;
   }
   sv->budget = hbm_budget;
+  sv->idle_ticks = (uint64_t)kQueueIdleUs * wall_ticks_per_us(sv->device);
+  if (hipStreamCreateWithFlags(&sv->setup, hipStreamNonBlocking) != hipSuccess) {
+    delete sv;
+    return REI_ERR_DEVICE;
+  }
   const uint32_t ns = n_streams ? n_streams : 4;
   for (uint32_t k = 0; k < ns; ++k) {
     hipStream_t s;
@@ -2696,8 +2986,25 @@ void rei_server_destroy(rei_server* sv) {
   }
   for (auto& w : sv->workers)
     if (w.joinable()) w.join();
+  for (auto& q : sv->qg) {
+    if (q.s) (void)hipStreamSynchronize(q.s);
+    if (q.ev) (void)hipEventDestroy(q.ev);
+    if (q.s) (void)hipStreamDestroy(q.s);
+    if (q.d_next) (void)hipFree(q.d_next);
+    if (q.h_ctl) (void)hipHostFree(q.h_ctl);
+    if (q.h_ring) (void)hipHostFree(q.h_ring);
+  }
+  if (sv->setup) (void)hipStreamDestroy(sv->setup);
   for (auto s : sv->streams) (void)hipStreamDestroy(s);
   delete sv;
+}
+
+rei_status rei_server_set_queue_mode(rei_server* sv, int enable) {
+  if (!sv) return REI_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> g(sv->mu);
+  if (sv->next_ticket != 1) return REI_ERR_INVALID_ARG;  // fixed once a request was submitted
+  sv->queue_mode = enable != 0;
+  return REI_OK;
 }
 
 }  // extern "C"

@@ -217,7 +217,7 @@ hipError_t set_hash_mask_batch(uint64_t mask);
 // rows, when the right level is small).
 constexpr int kMaxPieces = 32;
 constexpr uint64_t kSmallPiece = 16384;  // pieces up to this size go to gen_pieces
-constexpr int kPiecesMaxW = 8;           // widest languages gen_pieces handles
+constexpr int kPiecesMaxW = 32;          // widest languages gen_pieces handles
 struct PieceD {
   uint32_t op, same, left_lanes, char_off;
   uint32_t rel0, pad;
@@ -284,6 +284,16 @@ struct BatchDesc {
   uint64_t* htree;            // [node count, then per node: row (~0 = the answer), op, a, b]
 };
 
+// Host-written control block of a queue launch of the batched solver (in
+// coherent pinned memory): ring slots published so far, a request to leave,
+// and how long a workgroup waits without work before it leaves (wall-clock
+// ticks).
+struct QueueCtl {
+  uint32_t tail;
+  uint32_t closing;
+  uint64_t idle_ticks;
+};
+
 // Launches the batched solver with `threads` per workgroup (256, 512 or
 // 1024, at most batch_max_threads(W)) over n descriptors (all with the same
 // W).
@@ -291,9 +301,11 @@ struct BatchDesc {
 // persistent grid of `grid` workgroups (1..n) that take items from the
 // device counter *next (zero at launch) and solve descriptor order[item]
 // (item itself when order is null).
+// qc != nullptr (with next): queue form over a ring of n slots (see
+// solve_batch); grid may exceed n.
 hipError_t launch_solve_batch(int W, bool inl, uint32_t threads, const BatchDesc* d_descs, uint32_t n,
                               hipStream_t s, const uint32_t* order = nullptr, uint32_t* next = nullptr,
-                              uint32_t grid = 0);
+                              uint32_t grid = 0, const QueueCtl* qc = nullptr);
 // Workgroups of the batched solver that fit one compute unit at once.
 hipError_t batch_resident(int W, bool inl, uint32_t threads, uint32_t* per_cu);
 // Zeroes n (<= 64) work counters with a kernel (graph-capturable).

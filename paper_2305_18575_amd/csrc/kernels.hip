@@ -19,6 +19,8 @@
 //             unique ones enter the cache: Sec. 3, GPU language cache).
 #include <algorithm>
 
+#include <cstdlib>
+
 #include "device_common.h"
 
 namespace rei {
@@ -118,6 +120,7 @@ __global__ __launch_bounds__(256) void gen_star(GenArgs a) {
 // (Algorithm 2, the fold over the guide table, done for 64 candidates at once).
 // A wave transpose then gives lane t the W words of candidate (x, y_t).
 constexpr int kConcatYT = 8;
+constexpr uint64_t kConcatWideWaves = 256 * 8;  // waves below which the cut-outer fold is used
 
 // kShort: every word has at most 32 cuts (length <= 31), so the cuts whose
 // prefix is in x fit one 32-bit mask per output word; otherwise the prefix
@@ -126,7 +129,12 @@ constexpr int kConcatYT = 8;
 // time so that every access has a fixed address space: reading LDS through a
 // generic pointer (chosen at run time between LDS and global memory) gave
 // wrong prefix bits now and then on gfx950.
-template <int W, bool kShort, bool kInl, bool kGtLds>
+// kWide (with kShort): the prefix masks and the fold visit cut position q
+// in the outer loop and the lane's W words inside, every word's read issued
+// each round (clamped to its last cut, masked after), so W independent LDS
+// reads are in flight per round instead of one: fewer rounds of latency
+// for small launches, more LDS instructions for large ones.
+template <int W, bool kShort, bool kInl, bool kGtLds, bool kWide>
 __global__ __launch_bounds__(256) void gen_concat(GenArgs a, uint32_t yt_per_wg, uint32_t xi_per_wg,
                                                   uint64_t i_lo, uint64_t i_hi, uint32_t n_tile_groups) {
   extern __shared__ uint64_t lds[];
@@ -143,17 +151,29 @@ __global__ __launch_bounds__(256) void gen_concat(GenArgs a, uint32_t yt_per_wg,
   const uint64_t x0 = i_lo + (uint64_t)(blockIdx.x / n_tile_groups) * xi_per_wg;
   const uint32_t nx = (uint32_t)min<uint64_t>(xi_per_wg, i_hi + 1 - x0);
 
-  // stage right tiles (transposed), left rows and guide table
-  for (uint32_t job = wave; job < nt * W; job += 4) {
-    const uint32_t tq = job / W, k = job % W;
+  // stage right tiles (transposed), left rows and guide table; every load
+  // of a thread is issued before the first is used
+  for (uint32_t tq = wave; tq < nt; tq += 4) {
     const uint64_t j = (t0 + tq) * 64 + lane;
-    const uint64_t v = (j < nR) ? a.rows[(a.rstart + j) * W + k] : 0ull;
-    Yt[(size_t)tq * 64 * W + 64 * k + lane] = transpose64(v);
+    uint64_t v[W];
+    load_row<W>(a.rows, a.rstart + j, j < nR, v);
+#pragma unroll
+    for (int k = 0; k < W; ++k) Yt[(size_t)tq * 64 * W + 64 * k + lane] = transpose64(v[k]);
   }
-  for (uint32_t q = threadIdx.x; q < nx * W; q += 256)
-    Xs[q] = a.rows[(a.lstart + x0 + q / W) * W + q % W];
-  if constexpr (kGtLds)
-    for (uint32_t q = threadIdx.x; q < a.n_pairs; q += 256) G[q] = a.gt_pair[q];
+  {
+    const uint64_t* src = a.rows + (a.lstart + x0) * W;
+    const uint32_t total = nx * W;
+    uint32_t q = threadIdx.x;
+    for (; q + 3 * 256 < total; q += 4 * 256) {
+      const uint64_t v0 = src[q], v1 = src[q + 256], v2 = src[q + 512], v3 = src[q + 768];
+      Xs[q] = v0;
+      Xs[q + 256] = v1;
+      Xs[q + 512] = v2;
+      Xs[q + 768] = v3;
+    }
+    for (; q < total; q += 256) Xs[q] = src[q];
+  }
+  if constexpr (kGtLds) stage_u32(G, a.gt_pair, a.n_pairs, threadIdx.x, 256);
   __syncthreads();
   const uint32_t* gp;
   if constexpr (kGtLds)
@@ -169,19 +189,43 @@ __global__ __launch_bounds__(256) void gen_concat(GenArgs a, uint32_t yt_per_wg,
     off[k] = (w < a.n) ? a.gt_off[w] : 0u;
     cnt[k] = (w < a.n) ? a.gt_off[w + 1] - off[k] : 0u;
   }
+  // kWide: most cuts of any word (every word of ic has at most max_len + 1)
+  // and each word's last cut (a word beyond ic reads cut 0 of word 0)
+  const uint32_t qn = a.max_len + 1;
+  uint32_t last[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) last[k] = off[k] + (cnt[k] ? cnt[k] - 1 : 0u);
 
   for (uint32_t xi = wave; xi < nx; xi += 4) {
     const uint64_t i = x0 + xi;
     const uint64_t* xr = Xs + (size_t)xi * W;
     // bit q of m[k]: x contains the prefix of cut q of word 64k+lane
     uint32_t m[W];
-    if constexpr (kShort) {
+    if constexpr (kShort && kWide) {
+#pragma unroll
+      for (int k = 0; k < W; ++k) m[k] = 0;
+      for (uint32_t q = 0; q < qn; ++q) {
+        uint32_t u[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) u[k] = gp[min(off[k] + q, last[k])] >> 16;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          const uint32_t bit = (uint32_t)((xr[u[k] >> 6] >> (u[k] & 63)) & 1ull);
+          m[k] |= (q < cnt[k] ? bit : 0u) << q;
+        }
+      }
+    } else if constexpr (kShort) {
 #pragma unroll
       for (int k = 0; k < W; ++k) {
         uint32_t mm = 0;
-        for (uint32_t q = 0; q < cnt[k]; ++q) {
-          const uint32_t u = gp[off[k] + q] >> 16;
-          mm |= (uint32_t)((xr[u >> 6] >> (u & 63)) & 1ull) << q;
+        for (uint32_t q0 = 0; q0 < cnt[k]; q0 += 4) {
+          // four cuts at a time: their reads overlap
+          uint32_t u[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) u[t] = (q0 + t < cnt[k]) ? gp[off[k] + q0 + t] >> 16 : 0u;
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (q0 + t < cnt[k]) mm |= (uint32_t)((xr[u[t] >> 6] >> (u[t] & 63)) & 1ull) << (q0 + t);
         }
         m[k] = mm;
       }
@@ -189,6 +233,23 @@ __global__ __launch_bounds__(256) void gen_concat(GenArgs a, uint32_t yt_per_wg,
     for (uint32_t tq = 0; tq < nt; ++tq) {
       const uint64_t* Y = Yt + (size_t)tq * 64 * W;
       uint64_t key[W];
+      if constexpr (kShort && kWide) {
+        uint64_t acc[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) acc[k] = 0;
+        for (uint32_t q = 0; q < qn; ++q) {
+          uint32_t v[W];
+#pragma unroll
+          for (int k = 0; k < W; ++k) v[k] = gp[min(off[k] + q, last[k])] & 0xFFFFu;
+#pragma unroll
+          for (int k = 0; k < W; ++k) {
+            const uint64_t y = Y[v[k]];
+            acc[k] |= ((m[k] >> q) & 1u) ? y : 0ull;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < W; ++k) key[k] = transpose64(acc[k]);
+      } else {
 #pragma unroll
       for (int k = 0; k < W; ++k) {
         uint64_t acc = 0;
@@ -205,6 +266,7 @@ __global__ __launch_bounds__(256) void gen_concat(GenArgs a, uint32_t yt_per_wg,
           }
         }
         key[k] = transpose64(acc);
+      }
       }
       const uint64_t j = (t0 + tq) * 64 + lane;
       const uint64_t e = i * nR + j;
@@ -520,11 +582,20 @@ __global__ __launch_bounds__(1024) void finalize_small(ChunkArgs a) {
     s_over = ~0u;
   }
   __syncthreads();
-  for (uint32_t sid = t; sid < ns; sid += 1024) {
-    const uint32_t e = a.se[sid];
-    if (table_is_winner<kInl>(a.slots, a.sref, a.spos[sid], new_ref(e, sid)))
-      atomicOr(&bm[e >> 5], 1u << (e & 31));
+  // four survivors per thread and round, their reads issued together
+  auto mark = [&](uint32_t sid, uint32_t e, uint64_t pos) {
+    if (table_is_winner<kInl>(a.slots, a.sref, pos, new_ref(e, sid))) atomicOr(&bm[e >> 5], 1u << (e & 31));
+  };
+  uint32_t sid = t;
+  for (; sid + 3 * 1024 < ns; sid += 4 * 1024) {
+    const uint32_t e0 = a.se[sid], e1 = a.se[sid + 1024], e2 = a.se[sid + 2048], e3 = a.se[sid + 3072];
+    const uint64_t p0 = a.spos[sid], p1 = a.spos[sid + 1024], p2 = a.spos[sid + 2048], p3 = a.spos[sid + 3072];
+    mark(sid, e0, p0);
+    mark(sid + 1024, e1, p1);
+    mark(sid + 2048, e2, p2);
+    mark(sid + 3072, e3, p3);
   }
+  for (; sid < ns; sid += 1024) mark(sid, a.se[sid], a.spos[sid]);
   __syncthreads();
   if (t < 64) {
     const uint32_t tot = wave_popc_scan<kSmallWords / 64>(bm, pre, words);
@@ -534,19 +605,27 @@ __global__ __launch_bounds__(1024) void finalize_small(ChunkArgs a) {
   const uint32_t total = s_total;
   const uint64_t row_base = a.st->total_rows;
   const uint64_t room = a.st->row_cap > row_base ? a.st->row_cap - row_base : 0;
-  for (uint32_t sid = t; sid < ns; sid += 1024) {
-    const uint32_t e = a.se[sid];
+  auto place = [&](uint32_t sid, uint32_t e) {
     const uint32_t word = bm[e >> 5];
     const uint32_t bit = 1u << (e & 31);
-    if (!(word & bit)) continue;  // e is unique per survivor: the bit marks this one
+    if (!(word & bit)) return;  // e is unique per survivor: the bit marks this one
     const uint32_t rank = pre[e >> 5] + (uint32_t)__popc(word & (bit - 1));
     if (e == ans) s_rank = rank;
-    if (ans != ~0u && e >= ans) continue;  // the answer and later ones are not stored
+    if (ans != ~0u && e >= ans) return;  // the answer and later ones are not stored
     if (rank < room)
       store_winner<W, kInl>(a, sid, e, row_base + rank);
     else if (rank == room)
       s_over = e;
+  };
+  sid = t;
+  for (; sid + 3 * 1024 < ns; sid += 4 * 1024) {
+    const uint32_t e0 = a.se[sid], e1 = a.se[sid + 1024], e2 = a.se[sid + 2048], e3 = a.se[sid + 3072];
+    place(sid, e0);
+    place(sid + 1024, e1);
+    place(sid + 2048, e2);
+    place(sid + 3072, e3);
   }
+  for (; sid < ns; sid += 1024) place(sid, a.se[sid]);
   __syncthreads();
   if (t == 0) account_chunk(a, ans, s_rank, total, s_over);
 }
@@ -725,18 +804,31 @@ hipError_t launch_concat_w(const GenArgs& a, hipStream_t s) {
   if (gx * gy > 0x7fffffffull) return hipErrorInvalidConfiguration;
   const dim3 grid((uint32_t)(gx * gy));
   const bool shrt = a.max_len < 32;
-  if (shrt && gt_lds)
-    launch_timed(gen_concat<W, true, kInl, true>, grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
-                       (uint32_t)gx);
+  // the cut-outer fold for launches with fewer waves than the device holds
+  // at once (latency-bound), the word-outer fold for larger ones
+  static const int wide_mode = [] {
+    const char* e = std::getenv("REI_CONCAT_WIDE");
+    return e ? std::atoi(e) : 0;  // 0 by launch size, 1 never, 2 always
+  }();
+  const bool wide = shrt && (wide_mode == 2 || (wide_mode == 0 && gx * gy * 4 <= kConcatWideWaves));
+  if (wide && gt_lds)
+    launch_timed(gen_concat<W, true, kInl, true, true>, grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
+                 (uint32_t)gx);
+  else if (wide)
+    launch_timed(gen_concat<W, true, kInl, false, true>, grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
+                 (uint32_t)gx);
+  else if (shrt && gt_lds)
+    launch_timed(gen_concat<W, true, kInl, true, false>, grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
+                 (uint32_t)gx);
   else if (shrt)
-    launch_timed(gen_concat<W, true, kInl, false>, grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
-                       (uint32_t)gx);
+    launch_timed(gen_concat<W, true, kInl, false, false>, grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
+                 (uint32_t)gx);
   else if (gt_lds)
-    launch_timed(gen_concat<W, false, kInl, true>, grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
-                       (uint32_t)gx);
+    launch_timed(gen_concat<W, false, kInl, true, false>, grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
+                 (uint32_t)gx);
   else
-    launch_timed(gen_concat<W, false, kInl, false>, grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
-                       (uint32_t)gx);
+    launch_timed(gen_concat<W, false, kInl, false, false>, grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
+                 (uint32_t)gx);
   return hipGetLastError();
 }
 
@@ -840,6 +932,8 @@ hipError_t launch_gen_pieces(int W, const GenArgs& a, const PieceArgs& p, hipStr
     case 2: launch_timed(gen_pieces<2, false>, dim3(grid), dim3(256), 0, s, a, p); break;
     case 4: launch_timed(gen_pieces<4, false>, dim3(grid), dim3(256), 0, s, a, p); break;
     case 8: launch_timed(gen_pieces<8, false>, dim3(grid), dim3(256), 0, s, a, p); break;
+    case 16: launch_timed(gen_pieces<16, false>, dim3(grid), dim3(256), 0, s, a, p); break;
+    case 32: launch_timed(gen_pieces<32, false>, dim3(grid), dim3(256), 0, s, a, p); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -65,10 +65,12 @@ def percentiles(lat: Sequence[float]):
 
 
 def run_served(rei, handles, arrivals, budget: int, max_batch: int = 64, n_streams: int = 4,
-               n_workers: int = 4):
+               n_workers: int = 4, queue: bool = True):
     """Submits handles[i] at arrivals[i] seconds; returns results, latencies and
-    instances per second (requests / time from first arrival to last completion)."""
-    srv = rei.Server(budget, max_batch, n_streams, n_workers)
+    instances per second (requests / time from first arrival to last completion).
+    queue: the server's queue mode (persistent launches fed while they run)
+    or its launch mode (one batched launch per admitted group)."""
+    srv = rei.Server(budget, max_batch, n_streams, n_workers, queue=queue)
     t0 = time.perf_counter()
     tickets, submit_at = [], []
     for h, ta in zip(handles, arrivals):
@@ -123,19 +125,23 @@ def sweep(rei, n: int, fractions=(0.25, 0.5, 0.75, 1.0), seed: int = 2024, budge
     for h in hs:
         h.solve(stream)
     capacity = n / (time.perf_counter() - t)
-    run_served(rei, hs, base / (4 * capacity), budget)  # warm the server path (untimed)
+    run_served(rei, hs, base / (4 * capacity), budget)  # warm the server paths (untimed)
+    run_served(rei, hs, base / (4 * capacity), budget, queue=False)
     points = []
     for f in fractions:
         qps = capacity * f
         arr = base / qps
         res, lat, ips = run_served(rei, hs, arr, budget)
+        lres, llat, lips = run_served(rei, hs, arr, budget, queue=False)
         sres, slat, sips = run_sequential(rei, hs, arr, stream)
         points.append({"load": f, "qps": round(qps, 2),
-                       "served": {"instances_per_sec": round(ips, 2),
+                       "served": {"mode": "queue", "instances_per_sec": round(ips, 2),
                                   **{k: round(v, 3) for k, v in percentiles(lat).items()}},
+                       "served_launch_mode": {"instances_per_sec": round(lips, 2),
+                                              **{k: round(v, 3) for k, v in percentiles(llat).items()}},
                        "sequential": {"instances_per_sec": round(sips, 2),
                                       **{k: round(v, 3) for k, v in percentiles(slat).items()}},
-                       "identical_results": all(same(a, b) for a, b in zip(res, seq_res))})
+                       "identical_results": all(same(a, b) and same(a, c) for a, b, c in zip(res, seq_res, lres))})
     kinds = {k: sum(1 for s in specs if s[0] == k) for k in ("plain", "large", "single")}
     for h in hs:
         h.close()

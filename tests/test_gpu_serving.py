@@ -20,18 +20,20 @@ def oracle_of(specs):
     return solve_many([(i.alphabet, i.pos, i.neg, i.costs, i.max_cost, cache) for _, i, cache in specs])
 
 
+@pytest.mark.parametrize("queue", [True, False])
 @pytest.mark.parametrize("budget,qps", [(64 << 30, 2000.0), (256 << 20, 300.0)])
-def test_served_results_equal_oracle(rei, budget, qps):
+def test_served_results_equal_oracle(rei, budget, qps, queue):
     """Fresh (never solved) instances are served first, so nothing a served
     request reports can come from an earlier solve; the large share runs to
     its target's cost (one of its seeds ends out of memory at its 1 GiB
-    cache, which is compared like any other outcome)."""
+    cache, which is compared like any other outcome).  Both server modes:
+    persistent launches fed from a ring, and one launch per group."""
     specs = with_trivial(serving.request_mix(7, 60))
-    print(f"\nserving {len(specs)} requests, budget {budget}, qps {qps}", flush=True)
+    print(f"\nserving {len(specs)} requests, budget {budget}, qps {qps}, queue {queue}", flush=True)
     want = oracle_of(specs)
     hs = serving.stage(rei, specs)
     arrivals = serving.poisson_arrivals(7, len(hs), qps)
-    res, lat, ips = serving.run_served(rei, hs, arrivals, budget)
+    res, lat, ips = serving.run_served(rei, hs, arrivals, budget, queue=queue)
     for k, (g, o) in enumerate(zip(res, want)):
         assert mismatch(g, o, specs[k][1].max_cost) is None, (k, specs[k][0], mismatch(g, o, specs[k][1].max_cost))
     assert all(l > 0 for l in lat)
@@ -39,7 +41,7 @@ def test_served_results_equal_oracle(rei, budget, qps):
     for k, (g, o) in enumerate(zip(alone, want)):
         assert mismatch(g, o, specs[k][1].max_cost) is None, (k, "alone", mismatch(g, o, specs[k][1].max_cost))
     # served again, now that every instance holds an earlier search's state
-    res2, _, _ = serving.run_served(rei, hs, arrivals, budget)
+    res2, _, _ = serving.run_served(rei, hs, arrivals, budget, queue=queue)
     for k, (a, b) in enumerate(zip(res2, alone)):
         assert serving.same(a, b), (k, specs[k][0], a, b)
     for h in hs:
@@ -62,4 +64,29 @@ def test_fresh_wide_and_trivial_requests(rei):
         assert mismatch(g, o, specs[k][1].max_cost) is None, (k, mismatch(g, o, specs[k][1].max_cost))
     for k, h in enumerate(hs):
         assert serving.same(h.solve(), served[k]), k
+        h.close()
+
+
+def test_queue_mode_relaunches_and_fills_rings(rei):
+    """Queue mode across launch boundaries: a burst, then a pause longer than
+    the launches' idle time (they end; the next request starts new ones),
+    then a burst larger than one group's ring (a full ring is closed and the
+    rest published in the next launch); every result equals the oracle's."""
+    import time
+    specs = [("plain", instances.plain_instance(s), 64 << 20) for s in range(4200)]
+    specs += [("batched", i, 1 << 30) for i in instances.batched_instances(3, 300)]
+    want = oracle_of(specs)
+    hs = serving.stage(rei, specs)
+    srv = rei.Server(64 << 30, 64, 2, 2, queue=True)
+    print(f"\nqueue mode: {len(hs)} requests in two bursts", flush=True)
+    tickets = [srv.submit(h) for h in hs[:100]]
+    got = {t: srv.wait(t)[0] for t in tickets}
+    time.sleep(0.05)  # every launch has ended
+    tickets2 = [srv.submit(h) for h in hs[100:]]
+    for t in tickets2:
+        got[t] = srv.wait(t)[0]
+    srv.close()
+    for k, t in enumerate(tickets + tickets2):
+        assert mismatch(got[t], want[k], specs[k][1].max_cost) is None, (k, mismatch(got[t], want[k], specs[k][1].max_cost))
+    for h in hs:
         h.close()
