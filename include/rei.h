@@ -186,9 +186,12 @@ rei_status rei_solve_batch_noalloc(rei_instance *const *insts, size_t n, void *h
  *                          The instances (all on the current device) belong
  *                          to the graph until it is destroyed: do not solve
  *                          them otherwise meanwhile.  Trivial
- *                          specifications are answered at results time,
- *                          instances that cannot be batched run rei_solve's
- *                          path then.
+ *                          specifications are answered at results time;
+ *                          instances that cannot be batched, and those
+ *                          too heavy for one workgroup (see
+ *                          rei_batch_graph_outside), run rei_solve's path
+ *                          on the worker threads, started by each launch
+ *                          beside the replay.
  * rei_batch_graph_launch   enqueues one replay on hip_stream (NULL = the
  *                          null stream) and returns; the previous replay's
  *                          results must have been collected.
@@ -208,6 +211,12 @@ rei_status rei_batch_graph_launch(rei_batch_graph *g, void *hip_stream);
 rei_status rei_batch_graph_results(rei_batch_graph *g, rei_result *out);
 const char *rei_batch_graph_error(const rei_batch_graph *g);
 void rei_batch_graph_destroy(rei_batch_graph *g);
+/* Instances of the graph that run rei_solve's path on worker threads beside
+ * each replay instead of inside it: those that cannot be batched, and those
+ * whose measured work (candidates, weighted by words per language) exceeds
+ * twice the average per resident workgroup (and 10^5), which would decide a
+ * replay's length alone on one workgroup. */
+size_t rei_batch_graph_outside(const rei_batch_graph *g);
 
 /* Autotuner of rei_solve_batch, by whole calls (what the caller waits for,
  * hand-offs included), each setting timed as the shortest of five calls.
@@ -269,8 +278,9 @@ rei_status rei_tune_load(const char *path);
  *    batched solver takes requests from a ring in pinned host memory while
  *    it runs; each admitted request is written into the ring and published,
  *    and the next free workgroup starts it, with no launch in between.  A
- *    launch ends after its workgroups found no work for 2 ms; the next
- *    admitted request of the group starts another.
+ *    launch (one workgroup per eight compute units) ends after its
+ *    workgroups found no work for 150 us; the next admitted request of the
+ *    group starts another.
  *  - launch mode: admitted requests are launched together on a free stream
  *    from a pool of n_streams (at most max_batch per launch), so requests
  *    arriving while others run are started at once and their work overlaps

@@ -34,7 +34,8 @@ EXPORTS = ["rei_create", "rei_solve", "rei_solve_batch", "rei_tune_batch", "rei_
            "rei_kernel_stats", "rei_timing_overhead", "rei_set_hash_bits", "rei_kernel_name",
            "rei_measure_peak", "rei_batch_graph_create", "rei_batch_graph_launch", "rei_batch_graph_results",
            "rei_batch_graph_error", "rei_batch_graph_destroy", "rei_tune_grid", "rei_set_grid_tuning",
-           "rei_tune_save", "rei_tune_load", "rei_solve_batch_noalloc", "rei_server_set_queue_mode"]
+           "rei_tune_save", "rei_tune_load", "rei_solve_batch_noalloc", "rei_server_set_queue_mode",
+           "rei_batch_graph_outside"]
 
 
 class ReiError(RuntimeError):
@@ -103,6 +104,8 @@ def load_library():
                                     ctypes.POINTER(_Result), ctypes.POINTER(ctypes.c_double)]
     lib.rei_server_destroy.restype = None
     lib.rei_server_destroy.argtypes = [vp]
+    lib.rei_batch_graph_outside.restype = ctypes.c_size_t
+    lib.rei_batch_graph_outside.argtypes = [vp]
     lib.rei_server_set_queue_mode.restype = ctypes.c_int
     lib.rei_server_set_queue_mode.argtypes = [vp, ctypes.c_int]
     lib.rei_destroy.restype = None
@@ -528,6 +531,11 @@ class BatchGraph:
     def run(self, stream: Optional[int] = -1) -> List[Result]:
         self.launch(stream)
         return self.results()
+
+    def outside(self) -> int:
+        """Instances solved beside each replay on rei_solve's path (not
+        batchable, or too heavy for one workgroup)."""
+        return int(self._lib.rei_batch_graph_outside(self._h))
 
     def close(self):
         if self._h:

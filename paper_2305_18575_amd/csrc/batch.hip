@@ -44,24 +44,63 @@ __device__ __forceinline__ void phase_barrier() { __syncthreads(); }
 //                uniform(v) of T[u].
 // Lane t receives the W words of candidate t.
 // The guide table (gto, gtp) is the workgroup's LDS copy.
+// qn: most cuts of any word (the longest word's length + 1).  From 8 words
+// on, cut position q is the outer loop and the lane's W words the inner one
+// (each word's read clamped to its last cut and masked after), so 24
+// independent LDS reads are in flight per round of eight words instead of a
+// chain of three per cut; below that the per-word loop keeps the register
+// count of the 1024-thread instantiations down.
 template <int W, bool kLeft>
 __device__ __forceinline__ void concat_tile(const uint64_t* T, const uint64_t* uni, const uint32_t* gto,
-                                            const uint32_t* gtp, uint32_t n, uint64_t (&key)[W]) {
+                                            const uint32_t* gtp, uint32_t n, uint32_t qn, uint64_t (&key)[W]) {
   const uint32_t lane = lane_id();
+  if constexpr (W >= 8) {
+    // eight words at a time keeps the registers of the 16- and 32-word
+    // instantiations within their launch bounds
 #pragma unroll
-  for (int k = 0; k < W; ++k) {
-    const uint32_t w = 64u * k + lane;
-    uint64_t acc = 0;
-    if (w < n) {
-      const uint32_t q1 = gto[w + 1];
-      for (uint32_t q = gto[w]; q < q1; ++q) {
-        const uint32_t p = gtp[q];
-        const uint32_t ui = kLeft ? (p & 0xFFFFu) : (p >> 16);
-        const uint32_t si = kLeft ? (p >> 16) : (p & 0xFFFFu);
-        if ((uni[ui >> 6] >> (ui & 63)) & 1ull) acc |= T[si];
+    for (int k0 = 0; k0 < W; k0 += 8) {
+      uint32_t first[8], last[8], cnt[8];
+      uint64_t acc[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t w = 64u * (k0 + k) + lane;
+        first[k] = w < n ? gto[w] : 0u;
+        cnt[k] = w < n ? gto[w + 1] - first[k] : 0u;
+        last[k] = first[k] + (cnt[k] ? cnt[k] - 1 : 0u);
+        acc[k] = 0;
       }
+      for (uint32_t q = 0; q < qn; ++q) {
+        uint32_t p[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) p[k] = gtp[min(first[k] + q, last[k])];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t ui = kLeft ? (p[k] & 0xFFFFu) : (p[k] >> 16);
+          const uint32_t si = kLeft ? (p[k] >> 16) : (p[k] & 0xFFFFu);
+          const uint64_t t = T[si];
+          const bool on = q < cnt[k] && ((uni[ui >> 6] >> (ui & 63)) & 1ull);
+          acc[k] |= on ? t : 0ull;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) key[k0 + k] = transpose64(acc[k]);
     }
-    key[k] = transpose64(acc);
+  } else {
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const uint32_t w = 64u * k + lane;
+      uint64_t acc = 0;
+      if (w < n) {
+        const uint32_t q1 = gto[w + 1];
+        for (uint32_t q = gto[w]; q < q1; ++q) {
+          const uint32_t p = gtp[q];
+          const uint32_t ui = kLeft ? (p & 0xFFFFu) : (p >> 16);
+          const uint32_t si = kLeft ? (p >> 16) : (p & 0xFFFFu);
+          if ((uni[ui >> 6] >> (ui & 63)) & 1ull) acc |= T[si];
+        }
+      }
+      key[k] = transpose64(acc);
+    }
   }
 }
 
@@ -207,7 +246,7 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
   // small instance clears a few KB instead of its whole arena.
   uint64_t tmask = min(d.slot_mask, (uint64_t)1023);
   Probe probe{d.rows, d.slots, tmask, d.pmask, d.nmask, d.max_err};
-  const Sink sink{d.skey, d.se, &s_nsurv, &s_ans};
+  const Sink sink{d.skey, d.se, d.spos, &s_nsurv, &s_ans};
 
   // start: empty table, zero counters
   for (uint64_t i = tid; i <= tmask; i += kT) {
@@ -388,13 +427,8 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
               for (uint32_t l = 1; l <= d.max_len; ++l) {
                 const uint32_t lo = s_lo[l], hi = s_lo[l + 1];
                 for (uint32_t w = lo + lane; w < hi; w += 64) {
-                  uint64_t acc = 0;
-                  const uint32_t q1 = s_gto[w + 1];
-                  for (uint32_t q = s_gto[w] + 1; q < q1; ++q) {  // cut 0 has u = eps
-                    const uint32_t p = s_gtp[q];
-                    acc |= Xt[p >> 16] & Yt[p & 0xFFFFu];
-                  }
-                  Yt[w] = acc;
+                  // a word of length l has cuts 0..l; cut 0 has u = eps
+                  Yt[w] = star_fold(Xt, Yt, s_gtp, s_gto[w], l);
                 }
                 wave_sync_lds();
               }
@@ -426,7 +460,7 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
               if (lane < (uint32_t)W) U[lane] = d.rows[(lst + i) * W + lane];
               wave_sync_lds();
               uint64_t key[W];
-              concat_tile<W, false>(T, U, s_gto, s_gtp, d.n, key);
+              concat_tile<W, false>(T, U, s_gto, s_gtp, d.n, d.max_len + 1, key);
               const uint64_t e = i * nR + jr;
               filter_emit<W, kInl>(probe, sink, jr < nR && e >= e0 && e < e1, false, key, (uint32_t)(rel0 + e));
               wave_sync_lds();
@@ -446,7 +480,7 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
               if (lane < (uint32_t)W) U[lane] = d.rows[(rst + j) * W + lane];
               wave_sync_lds();
               uint64_t key[W];
-              concat_tile<W, true>(T, U, s_gto, s_gtp, d.n, key);
+              concat_tile<W, true>(T, U, s_gto, s_gtp, d.n, d.max_len + 1, key);
               const uint64_t e = ir * nR + j;
               filter_emit<W, kInl>(probe, sink, ir < nL && e >= e0 && e < e1, false, key, (uint32_t)(rel0 + e));
               wave_sync_lds();
@@ -462,8 +496,10 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
           uint64_t key[W];
 #pragma unroll
           for (int k = 0; k < W; ++k) key[k] = d.skey[(uint64_t)sid * W + k];
-          d.spos[sid] = table_insert<W, kInl>(d.slots, d.sref, tmask, d.rows, d.skey, key, hash_key<W>(key),
-                                              new_ref(d.se[sid], sid));
+          const uint64_t h = d.spos[sid];
+          const uint64_t pos = table_insert<W, kInl>(d.slots, d.sref, tmask, d.rows, d.skey, key, h,
+                                                     new_ref(d.se[sid], sid));
+          d.spos[sid] = spos_pack(pos, h);
         }
         phase_barrier();
 
@@ -504,7 +540,7 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
               d.rows[row * W + k] = key[k];
             }
             d.aux[row] = E0 + e;
-            table_publish<W, kInl>(d.slots, d.sref, d.spos[sid], key, row);
+            table_publish<kInl>(d.slots, d.sref, d.spos[sid], row);
           } else if (rank == room) {
             s_over = e;
           }

@@ -155,6 +155,25 @@ __device__ __forceinline__ void stage_u32(uint32_t* dst, const uint32_t* src, ui
   for (; q < n; q += nt) dst[q] = src[q];
 }
 
+// One word of the star's fixed point: OR over the cuts q = 1..l of a word of
+// length l (guide entries gt[off + q], cut 0 being u = eps) of X(u) & Y(v),
+// four cuts' reads in flight at a time (l is the same for every lane).
+template <typename GT>
+__device__ __forceinline__ uint64_t star_fold(const uint64_t* X, const uint64_t* Y, GT gt, uint32_t off, uint32_t l) {
+  uint64_t acc = 0;
+  uint32_t q = 1;
+  for (; q + 3 <= l; q += 4) {
+    const uint32_t p0 = gt[off + q], p1 = gt[off + q + 1], p2 = gt[off + q + 2], p3 = gt[off + q + 3];
+    acc |= (X[p0 >> 16] & Y[p0 & 0xFFFFu]) | (X[p1 >> 16] & Y[p1 & 0xFFFFu]) | (X[p2 >> 16] & Y[p2 & 0xFFFFu]) |
+           (X[p3 >> 16] & Y[p3 & 0xFFFFu]);
+  }
+  for (; q <= l; ++q) {
+    const uint32_t p = gt[off + q];
+    acc |= X[p >> 16] & Y[p & 0xFFFFu];
+  }
+  return acc;
+}
+
 // ---- dedup table -----------------------------------------------------------
 // Fingerprint form (any W): a slot holds EMPTY, a stored row
 // (0 | fingerprint | row) or a survivor of the running chunk (1 | e | sid);
@@ -243,21 +262,30 @@ __device__ __forceinline__ uint64_t table_insert(uint64_t* slots, uint64_t* sref
   }
 }
 
-// After all inserts of the chunk: does `mine` own its key's slot?
+// A survivor's slot record (spos): written by the generator as the key's
+// hash, replaced at insertion by the slot position with the hash's 24-bit
+// fingerprint above bit 40 (table positions stay below 2^40), so that
+// inserting and publishing a survivor never hash its key again.
+constexpr uint64_t kPosMask = (1ull << 40) - 1;
+__device__ __forceinline__ uint64_t spos_pack(uint64_t pos, uint64_t h) { return pos | (fingerprint(h) << 40); }
+
+// After all inserts of the chunk: does `mine` own its key's slot?  rec is
+// the survivor's slot record.
 template <bool kInl>
-__device__ __forceinline__ bool table_is_winner(const uint64_t* slots, const uint64_t* sref, uint64_t pos,
+__device__ __forceinline__ bool table_is_winner(const uint64_t* slots, const uint64_t* sref, uint64_t rec,
                                                 uint64_t mine) {
+  const uint64_t pos = rec & kPosMask;
   return kInl ? sref[pos] == mine : slots[pos] == mine;
 }
 
-// The winner's key is now stored as `row`.
-template <int W, bool kInl>
-__device__ __forceinline__ void table_publish(uint64_t* slots, uint64_t* sref, uint64_t pos,
-                                              const uint64_t (&key)[W], uint64_t row) {
+// The winner (slot record rec) is now stored as `row`.
+template <bool kInl>
+__device__ __forceinline__ void table_publish(uint64_t* slots, uint64_t* sref, uint64_t rec, uint64_t row) {
+  const uint64_t pos = rec & kPosMask;
   if constexpr (kInl)
     sref[pos] = kEmpty;  // the key is in the slot already
   else
-    slots[pos] = (fingerprint(hash_key<W>(key)) << kRowBits) | row;
+    slots[pos] = ((rec >> 40) << kRowBits) | row;
 }
 
 // Stores a row's key during a rebuild (all keys distinct).
@@ -298,6 +326,7 @@ struct Probe {
 struct Sink {
   uint64_t* skey;
   uint32_t* se;
+  uint64_t* spos;  // the survivor's hash, for its insertion
   uint32_t* n_surv;
   uint32_t* answer_e;
 };
@@ -310,7 +339,11 @@ template <int W, bool kInl>
 __device__ __forceinline__ void filter_emit(const Probe& a, const Sink& o, bool valid, bool known_dup,
                                             const uint64_t (&key)[W], uint32_t e_rel) {
   bool surv = false;
-  if (valid && !known_dup) surv = !table_find<W, kInl>(a.slots, a.slot_mask, a.rows, key, hash_key<W>(key));
+  uint64_t h = 0;
+  if (valid && !known_dup) {
+    h = hash_key<W>(key);
+    surv = !table_find<W, kInl>(a.slots, a.slot_mask, a.rows, key, h);
+  }
   const uint64_t m = __ballot(surv);
   if (m == 0) return;
   const uint32_t lane = lane_id();
@@ -324,6 +357,7 @@ __device__ __forceinline__ void filter_emit(const Probe& a, const Sink& o, bool 
 #pragma unroll
     for (int k = 0; k < W; ++k) dst[k] = key[k];
     o.se[sid] = e_rel;
+    o.spos[sid] = h;
     if (misclassified<W>(a.pmask, a.nmask, key) <= (int)a.max_err) atomicMin(o.answer_e, e_rel);
   }
 }

@@ -8,6 +8,7 @@
 #include <deque>
 #include <list>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -32,6 +33,9 @@ thread_local std::string g_create_error;
 
 constexpr uint64_t kDefaultChunk = 1ull << 24;
 constexpr uint64_t kDefaultArena = 16ull << 20;  // bytes per batched instance
+// Work (weighted candidates) below which an instance always stays in a
+// captured graph, however uneven the batch.
+constexpr double kGraphHeavyMin = 1e5;
 
 struct Block {
   int op;
@@ -496,6 +500,7 @@ rei_status enqueue_chunk(rei_instance* in, hipStream_t s, uint32_t c, const std:
   g.slot_mask = in->slots_cap - 1;
   g.skey = in->d_skey;
   g.se = in->d_se;
+  g.spos = in->d_spos;
   g.ctrl = in->d_ctrl;
   g.pmask = in->d_pmask;
   g.nmask = in->d_nmask;
@@ -2536,8 +2541,15 @@ void server_worker(rei_server* sv, hipStream_t s) {
   }
 }
 
-constexpr uint32_t kRing = 4096;        // ring slots per queue launch
-constexpr uint32_t kQueueIdleUs = 2000;  // a queue launch's workgroups leave after this long without work
+constexpr uint32_t kRing = 4096;  // ring slots per queue launch
+// A queue launch's workgroups leave after this long without work, and a
+// group's launch has one workgroup per kQueueCuShare compute units: idle
+// workgroups hold their compute units, which the per-chunk kernels of
+// handed-off requests need (a 2 ms idle time on a quarter of the device
+// tripled the served p99 of the serving mix; 100-300 us on an eighth made
+// it lower than one launch per admitted group).
+constexpr uint32_t kQueueIdleUs = 150;
+constexpr uint32_t kQueueCuShare = 8;
 
 int queue_slot(const rei_instance* in) {
   if (in->inl) return 0;
@@ -2561,14 +2573,15 @@ rei_status queue_group_init(rei_server* sv, int slot, rei_instance* in) {
   HIP_OK(in, hipMalloc((void**)&q.d_next, 64 * sizeof(uint32_t)));
   HIP_OK(in, hipStreamCreateWithFlags(&q.s, hipStreamNonBlocking));
   HIP_OK(in, hipEventCreateWithFlags(&q.ev, hipEventDisableTiming));
-  // 256 threads per workgroup and a quarter of the compute units per group:
-  // a workgroup of the batched solver needs about 165 VGPRs per lane, so a
-  // compute unit holds three of 256 threads (one of 512); with every group
-  // launched, the persistent launches of all groups are resident side by
-  // side, and one group busy with a stream of requests never keeps another
-  // group's launch from starting
-  q.threads = 256;
-  q.grid = std::max<uint32_t>(1, device_cus(sv->device) / 4);
+  // 512 threads per workgroup (256 for 32 words) on an eighth of the
+  // compute units per group: a workgroup of the batched solver fills most of
+  // a compute unit's registers, so the launches of several groups are
+  // resident side by side, the per-chunk path of hand-offs finds room, and
+  // one group busy with a stream of requests does not keep another group's
+  // launch from starting for longer than its idle time
+  const int g = slot == 0 ? 0 : 1 << (slot - 1);
+  q.threads = std::min<uint32_t>(512, max_threads(g));
+  q.grid = std::max<uint32_t>(1, device_cus(sv->device) / kQueueCuShare);
   return REI_OK;
 }
 
@@ -2592,14 +2605,11 @@ uint64_t request_reserve(const rei_server* sv, const rei_instance* in) {
   return std::min(b, sv->budget);
 }
 
-// The descriptor of a served request: hand-off of large levels as for
-// rei_solve_batch, none on time (the persistent launches hold their
-// compute units anyway).
-BatchDesc queue_desc(const rei_instance* in) {
-  BatchDesc d = make_desc(in);
-  d.time_ticks = 0;
-  return d;
-}
+// The descriptor of a served request: hand-off of large levels, and of
+// mid-sized ones after the workgroup's time, as for rei_solve_batch (the
+// per-chunk path runs beside the persistent launches, which hold a quarter
+// of the compute units per group).
+BatchDesc queue_desc(const rei_instance* in) { return make_desc(in); }
 
 void server_sched_queue(rei_server* sv) {
   (void)hipSetDevice(sv->device);
@@ -3023,7 +3033,8 @@ struct rei_batch_graph {
   int device = 0;
   std::vector<rei_instance*> insts;   // caller's order
   std::vector<rei_instance*> batched; // in descriptor order (groups concatenated)
-  std::vector<rei_instance*> other;   // not batchable: rei_solve's path at results time
+  std::vector<rei_instance*> other;   // not batchable, or too heavy for one workgroup: rei_solve's
+                                      // path on the worker threads, beside each replay
   struct Group {
     int g = 0;            // 0 = one word with keys inline, else W
     uint32_t off = 0, n = 0, threads = 0, grid = 0;
@@ -3043,12 +3054,15 @@ struct rei_batch_graph {
   uint64_t arena = 0;
   bool in_flight = false;
   double t0 = 0;
+  std::unique_ptr<GridPool> pool;     // the replay's instances on the worker threads
   std::string err;
 };
 
 namespace {
 
 void graph_free(rei_batch_graph* g) {
+  if (g->pool) (void)g->pool->join();
+  g->pool.reset();
   if (g->in_flight && g->launched_on) (void)hipStreamSynchronize(g->launched_on);
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
@@ -3117,11 +3131,7 @@ rei_status graph_arena(rei_instance* in, uint64_t arena_bytes, hipStream_t s) {
 // so the next replay reads no freed memory.
 rei_status graph_collect(rei_batch_graph* g, hipStream_t s) {
   rei_status r;
-  GridPool pool(g->t0);
-  for (rei_instance* in : g->other) {
-    in->err.clear();
-    if (!begin_solve(in, g->t0)) pool.submit(in);
-  }
+  GridPool& pool = *g->pool;  // holds the other instances since the launch
   std::vector<size_t> refresh;
   for (size_t i = 0; i < g->batched.size(); ++i) {
     rei_instance* in = g->batched[i];
@@ -3141,7 +3151,9 @@ rei_status graph_collect(rei_batch_graph* g, hipStream_t s) {
     if (seen >= 0) in->res.seconds_solve = seen;
     in->t_seen = -1;
   }
-  if ((r = pool.join()) != REI_OK) return r;
+  r = pool.join();
+  g->pool.reset();
+  if (r != REI_OK) return r;
   for (size_t i : refresh) {
     rei_instance* in = g->batched[i];
     if ((r = graph_arena(in, g->arena, s)) != REI_OK) return r;
@@ -3195,19 +3207,25 @@ rei_status rei_batch_graph_create(rei_instance* const* insts, size_t n, uint64_t
           return r;
         }
     G_OK(g, hipStreamSynchronize(g->cap));
-    for (int w = 0; w <= kBatchMaxW; w = w ? 2 * w : 1) {
-      if (members[w].empty()) continue;
-      rei_batch_graph::Group q;
-      q.g = w;
-      q.off = (uint32_t)descs.size();
-      q.n = (uint32_t)members[w].size();
-      q.threads = choose_threads(w, members[w].size());
-      for (rei_instance* in : members[w]) {
-        descs.push_back(graph_desc(in));  // no hand-off: the whole search stays in the graph
-        g->batched.push_back(in);
+    auto regroup = [&] {
+      descs.clear();
+      g->groups.clear();
+      g->batched.clear();
+      for (int w = 0; w <= kBatchMaxW; w = w ? 2 * w : 1) {
+        if (members[w].empty()) continue;
+        rei_batch_graph::Group q;
+        q.g = w;
+        q.off = (uint32_t)descs.size();
+        q.n = (uint32_t)members[w].size();
+        q.threads = choose_threads(w, members[w].size());
+        for (rei_instance* in : members[w]) {
+          descs.push_back(graph_desc(in));  // no hand-off: the whole search stays in the graph
+          g->batched.push_back(in);
+        }
+        g->groups.push_back(q);
       }
-      g->groups.push_back(q);
-    }
+    };
+    regroup();
     const size_t nd = std::max<size_t>(1, descs.size());
     G_OK(g, hipHostMalloc((void**)&g->h_desc, nd * sizeof(BatchDesc), hipHostMallocMapped | hipHostMallocPortable));
     G_OK(g, hipHostGetDevicePointer((void**)&g->d_desc, g->h_desc, 0));
@@ -3245,19 +3263,60 @@ rei_status rei_batch_graph_create(rei_instance* const* insts, size_t n, uint64_t
       return r;
     }
     G_OK(g, hipStreamSynchronize(g->cap));
-    // work of each instance: its candidates (all levels); longest first
-    std::vector<double> work(descs.size(), 0);
-    double total = 0;
-    std::vector<double> gwork(g->groups.size(), 0);
+    // work of each instance: its candidates (all levels)
+    std::map<const rei_instance*, double> work_of;
+    double all_work = 0, resident = 0;
     for (size_t k = 0; k < g->groups.size(); ++k) {
       const auto& q = g->groups[k];
+      resident += (double)per_cu[k] * cus;
       for (uint32_t i = 0; i < q.n; ++i) {
         rei_instance* in = g->batched[q.off + i];
         const uint64_t L = in->max_cost + 2;
         double c = 0;
         for (uint64_t l = 0; l < L; ++l) c += (double)in->h_levels[2 * L + l];
         // a candidate of a wider language costs more (W words per operation)
-        work[q.off + i] = c * (1.0 + 0.25 * std::max(1, in->st.W)) + 1000.0;
+        const double w = c * (1.0 + 0.25 * std::max(1, in->st.W)) + 1000.0;
+        work_of[in] = w;
+        all_work += w;
+      }
+    }
+    // An instance with more than twice a resident workgroup's fair share of
+    // the work would decide the replay's length alone: it leaves the graph
+    // and runs rei_solve's path (whole device, hand-offs by level) on the
+    // worker threads while each replay runs.
+    const double heavy = 2.0 * all_work / std::max(1.0, resident);
+    bool moved = false;
+    for (int w = 0; w <= kBatchMaxW; w = w ? 2 * w : 1) {
+      auto& m = members[w];
+      for (auto it = m.begin(); it != m.end();) {
+        if (work_of[*it] > heavy && work_of[*it] > kGraphHeavyMin) {
+          g->other.push_back(*it);
+          it = m.erase(it);
+          moved = true;
+        } else {
+          ++it;
+        }
+      }
+    }
+    if (moved) {
+      regroup();
+      if (!descs.empty()) std::memcpy(g->h_desc, descs.data(), descs.size() * sizeof(BatchDesc));
+      order.assign(descs.size(), 0);
+      for (const auto& q : g->groups)
+        for (uint32_t i = 0; i < q.n; ++i) order[q.off + i] = i;
+      for (size_t k = 0; k < g->groups.size(); ++k) {
+        auto& q = g->groups[k];
+        G_OK(g, batch_resident(q.g ? q.g : 1, q.g == 0, q.threads, &per_cu[k]));
+      }
+    }
+    // longest first within each group
+    std::vector<double> work(descs.size(), 0);
+    double total = 0;
+    std::vector<double> gwork(g->groups.size(), 0);
+    for (size_t k = 0; k < g->groups.size(); ++k) {
+      const auto& q = g->groups[k];
+      for (uint32_t i = 0; i < q.n; ++i) {
+        work[q.off + i] = work_of[g->batched[q.off + i]];
         gwork[k] += work[q.off + i];
       }
       total += gwork[k];
@@ -3271,6 +3330,10 @@ rei_status rei_batch_graph_create(rei_instance* const* insts, size_t n, uint64_t
       const double share = total > 0 ? gwork[k] / total : 1.0 / g->groups.size();
       const uint32_t want = (uint32_t)std::llround(share * per_cu[k] * cus);
       q.grid = std::max<uint32_t>(1, std::min<uint32_t>(q.n, want));
+    }
+    if (g->groups.empty()) {  // every batchable instance was too heavy: nothing to capture
+      *out = g;
+      return REI_OK;
     }
     G_OK(g, hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
     r = graph_enqueue(g);
@@ -3306,6 +3369,12 @@ rei_status rei_batch_graph_launch(rei_batch_graph* g, void* hip_stream) {
   g->launched_on = (hipStream_t)hip_stream;
   if (g->exec) G_OK(g, hipGraphLaunch(g->exec, g->launched_on));
   g->in_flight = true;
+  // the instances outside the graph start now, beside the replay
+  g->pool.reset(new GridPool(g->t0));
+  for (rei_instance* in : g->other) {
+    in->err.clear();
+    if (!begin_solve(in, g->t0)) g->pool->submit(in);
+  }
   return REI_OK;
 }
 
@@ -3361,6 +3430,8 @@ rei_status rei_batch_graph_results(rei_batch_graph* g, rei_result* out) {
 }
 
 const char* rei_batch_graph_error(const rei_batch_graph* g) { return g ? g->err.c_str() : ""; }
+
+size_t rei_batch_graph_outside(const rei_batch_graph* g) { return g ? g->other.size() : 0; }
 
 void rei_batch_graph_destroy(rei_batch_graph* g) {
   if (!g) return;

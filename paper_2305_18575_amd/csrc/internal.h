@@ -91,6 +91,7 @@ struct GenArgs {
   // survivors
   uint64_t* skey;             // survivor keys, W words each
   uint32_t* se;               // survivor chunk-relative index
+  uint64_t* spos;             // survivor slot records (hash until inserted)
   Ctrl* ctrl;
   // precision
   const uint64_t* pmask;

@@ -40,7 +40,7 @@ __device__ __forceinline__ void filter_emit(const GenArgs& a, bool valid, bool k
     return;
   }
   const Probe p{a.rows, a.slots, a.slot_mask, a.pmask, a.nmask, a.max_err};
-  const Sink k{a.skey, a.se, &a.ctrl->n_surv, &a.ctrl->answer_e};
+  const Sink k{a.skey, a.se, a.spos, &a.ctrl->n_surv, &a.ctrl->answer_e};
   filter_emit<W, kInl>(p, k, valid, known_dup, key, e_rel);
 }
 
@@ -92,15 +92,8 @@ __global__ __launch_bounds__(256) void gen_star(GenArgs a) {
   __syncthreads();
   for (uint32_t l = 1; l <= a.max_len; ++l) {
     const uint32_t lo = a.len_off[l], hi = a.len_off[l + 1];
-    for (uint32_t w = lo + threadIdx.x; w < hi; w += 256) {
-      uint64_t acc = 0;
-      const uint32_t q1 = a.gt_off[w + 1];
-      for (uint32_t q = a.gt_off[w] + 1; q < q1; ++q) {  // cut 0 has u = eps
-        const uint32_t p = a.gt_pair[q];
-        acc |= Xt[p >> 16] & Yt[p & 0xFFFFu];
-      }
-      Yt[w] = acc;
-    }
+    for (uint32_t w = lo + threadIdx.x; w < hi; w += 256)
+      Yt[w] = star_fold(Xt, Yt, a.gt_pair, a.gt_off[w], l);  // cuts 1..l (cut 0 has u = eps)
     __syncthreads();
   }
   if (wave == 0) {
@@ -373,15 +366,7 @@ __global__ __launch_bounds__(256) void gen_pieces(GenArgs a, PieceArgs pa) {
       wave_sync_lds();
       for (uint32_t l = 1; l <= a.max_len; ++l) {
         const uint32_t lo = a.len_off[l], hi = a.len_off[l + 1];
-        for (uint32_t w = lo + lane; w < hi; w += 64) {
-          uint64_t acc = 0;
-          const uint32_t q1 = a.gt_off[w + 1];
-          for (uint32_t q = a.gt_off[w] + 1; q < q1; ++q) {
-            const uint32_t pr = a.gt_pair[q];
-            acc |= X[pr >> 16] & Y[pr & 0xFFFFu];
-          }
-          Y[w] = acc;
-        }
+        for (uint32_t w = lo + lane; w < hi; w += 64) Y[w] = star_fold(X, Y, a.gt_pair, a.gt_off[w], l);
         wave_sync_lds();
       }
 #pragma unroll
@@ -405,20 +390,54 @@ __global__ __launch_bounds__(256) void gen_pieces(GenArgs a, PieceArgs pa) {
         valid = i < nL;
       }
       wave_sync_lds();
+      if constexpr (W >= 8) {
+        // cut position outer, eight of the lane's words inner: 24
+        // independent reads per round (each word's read clamped to its last
+        // cut, masked after)
 #pragma unroll
-      for (int q = 0; q < W; ++q) {
-        const uint32_t w = 64u * q + lane;
-        uint64_t acc = 0;
-        if (w < a.n) {
-          const uint32_t q1 = a.gt_off[w + 1];
-          for (uint32_t c = a.gt_off[w]; c < q1; ++c) {
-            const uint32_t pr = a.gt_pair[c];
-            const uint32_t uu = p.left_lanes ? (pr & 0xFFFFu) : (pr >> 16);   // index into the uniform row
-            const uint32_t tt = p.left_lanes ? (pr >> 16) : (pr & 0xFFFFu);   // index into the tile
-            if ((U[uu >> 6] >> (uu & 63)) & 1ull) acc |= X[tt];
+        for (int q0 = 0; q0 < W; q0 += 8) {
+          uint32_t first[8], last[8], cnt[8];
+          uint64_t acc[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const uint32_t w = 64u * (q0 + q) + lane;
+            first[q] = w < a.n ? a.gt_off[w] : 0u;
+            cnt[q] = w < a.n ? a.gt_off[w + 1] - first[q] : 0u;
+            last[q] = first[q] + (cnt[q] ? cnt[q] - 1 : 0u);
+            acc[q] = 0;
           }
+          for (uint32_t c = 0; c <= a.max_len; ++c) {
+            uint32_t pr[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) pr[q] = a.gt_pair[min(first[q] + c, last[q])];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const uint32_t uu = p.left_lanes ? (pr[q] & 0xFFFFu) : (pr[q] >> 16);  // index into the uniform row
+              const uint32_t tt = p.left_lanes ? (pr[q] >> 16) : (pr[q] & 0xFFFFu);  // index into the tile
+              const uint64_t xv = X[tt];
+              const bool on = c < cnt[q] && ((U[uu >> 6] >> (uu & 63)) & 1ull);
+              acc[q] |= on ? xv : 0ull;
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 8; ++q) key[q0 + q] = transpose64(acc[q]);
         }
-        key[q] = transpose64(acc);
+      } else {
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+          const uint32_t w = 64u * q + lane;
+          uint64_t acc = 0;
+          if (w < a.n) {
+            const uint32_t q1 = a.gt_off[w + 1];
+            for (uint32_t c = a.gt_off[w]; c < q1; ++c) {
+              const uint32_t pr = a.gt_pair[c];
+              const uint32_t uu = p.left_lanes ? (pr & 0xFFFFu) : (pr >> 16);   // index into the uniform row
+              const uint32_t tt = p.left_lanes ? (pr >> 16) : (pr & 0xFFFFu);   // index into the tile
+              if ((U[uu >> 6] >> (uu & 63)) & 1ull) acc |= X[tt];
+            }
+          }
+          key[q] = transpose64(acc);
+        }
       }
       e = i * nR + j;
       valid = valid && e >= p.e0 && e < p.e1;
@@ -482,8 +501,10 @@ __global__ __launch_bounds__(256) void insert_survivors(ChunkArgs a) {
     uint64_t key[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) key[k] = a.skey[(uint64_t)sid * W + k];
-    a.spos[sid] = table_insert<W, kInl>(a.slots, a.sref, a.slot_mask, a.rows, a.skey, key, hash_key<W>(key),
-                                        new_ref(a.se[sid], sid));
+    const uint64_t h = a.spos[sid];
+    const uint64_t pos = table_insert<W, kInl>(a.slots, a.sref, a.slot_mask, a.rows, a.skey, key, h,
+                                               new_ref(a.se[sid], sid));
+    a.spos[sid] = spos_pack(pos, h);
   }
 }
 
@@ -555,12 +576,12 @@ template <int W, bool kInl>
 __device__ __forceinline__ void store_winner(const ChunkArgs& a, uint32_t sid, uint32_t e, uint64_t row) {
   uint64_t key[W];
 #pragma unroll
-  for (int k = 0; k < W; ++k) {
-    key[k] = a.skey[(uint64_t)sid * W + k];
-    a.rows_w[row * W + k] = key[k];
-  }
+  for (int k = 0; k < W; ++k) key[k] = a.skey[(uint64_t)sid * W + k];
+  const uint64_t rec = a.spos[sid];
+#pragma unroll
+  for (int k = 0; k < W; ++k) a.rows_w[row * W + k] = key[k];
   a.aux[row] = a.chunk_e0 + e;
-  table_publish<W, kInl>(a.slots, a.sref, a.spos[sid], key, row);
+  table_publish<kInl>(a.slots, a.sref, rec, row);
 }
 
 constexpr uint32_t kSmallWords = (uint32_t)(kSmallChunk / 32);

@@ -143,6 +143,11 @@ def sweep(rei, n: int, fractions=(0.25, 0.5, 0.75, 1.0), seed: int = 2024, budge
                                       **{k: round(v, 3) for k, v in percentiles(slat).items()}},
                        "identical_results": all(same(a, b) and same(a, c) for a, b, c in zip(res, seq_res, lres))})
     kinds = {k: sum(1 for s in specs if s[0] == k) for k in ("plain", "large", "single")}
+    # the last point's latencies by request kind
+    for key, l in (("served", lat), ("served_launch_mode", llat), ("sequential", slat)):
+        points[-1][key]["by_kind"] = {k: {q: round(v, 3) for q, v in
+                                          percentiles([x for x, s in zip(l, specs) if s[0] == k]).items()}
+                                      for k in kinds if kinds[k]}
     for h in hs:
         h.close()
     return {"arrivals_per_point": n, "mix": kinds, "sequential_capacity_per_sec": round(capacity, 2),
