@@ -46,7 +46,10 @@ PROBE_BYTES = 64
 # by (workload, kernel class); stored, since a counter run is a separate
 # profiler invocation.  The profile each figure comes from is named beside it.
 # An entry is removed when its kernel changes.
-TRAFFIC = {}
+TRAFFIC = {
+    ("large", "solve_batch"): (2796638, "profiles/large_workload_kernels.md (mean of the 16- and 8-word launches)"),
+    ("row1", "gen_concat"): (311234867, "profiles/table1_row1_kernels.md"),
+}
 
 
 def infix_closure(strings):
@@ -369,7 +372,12 @@ def main():
         step()
     tuned = None
     if not args.sequential and args.warmup and not args.no_tune:
-        tuned = rei.tune_batch(handles, stream)  # launch shapes chosen by measurement (untimed)
+        # launch shapes chosen by measurement (untimed): the per-chunk path's
+        # chunk sizes and concatenation shape per word width (timed on at
+        # most 16 of the instances: the tuner solves each one 57 times), then
+        # the batched solver's threads per instance and hand-off size
+        tuned = {"grid": rei.tune_grid(handles[:16], stream)}
+        tuned.update(rei.tune_batch(handles, stream))
     # Python's cyclic collector scans every object torch created at import;
     # a full pass inside the timed region costs tens of milliseconds that
     # belong to no step.  Objects made so far are moved out of its reach.

@@ -212,10 +212,11 @@ rei_status rei_batch_graph_results(rei_batch_graph *g, rei_result *out);
 const char *rei_batch_graph_error(const rei_batch_graph *g);
 void rei_batch_graph_destroy(rei_batch_graph *g);
 /* Instances of the graph that run rei_solve's path on worker threads beside
- * each replay instead of inside it: those that cannot be batched, and those
+ * each replay instead of inside it: those that cannot be batched, those
  * whose measured work (candidates, weighted by words per language) exceeds
  * twice the average per resident workgroup (and 10^5), which would decide a
- * replay's length alone on one workgroup. */
+ * replay's length alone on one workgroup, and those with a level larger
+ * than rei_solve_batch's hand-off size (tuned, else 2^16 candidates). */
 size_t rei_batch_graph_outside(const rei_batch_graph *g);
 
 /* Autotuner of rei_solve_batch, by whole calls (what the caller waits for,

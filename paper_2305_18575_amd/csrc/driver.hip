@@ -3263,8 +3263,9 @@ rei_status rei_batch_graph_create(rei_instance* const* insts, size_t n, uint64_t
       return r;
     }
     G_OK(g, hipStreamSynchronize(g->cap));
-    // work of each instance: its candidates (all levels)
+    // work of each instance: its candidates (all levels), and its largest level
     std::map<const rei_instance*, double> work_of;
+    std::map<const rei_instance*, uint64_t> widest_of;
     double all_work = 0, resident = 0;
     for (size_t k = 0; k < g->groups.size(); ++k) {
       const auto& q = g->groups[k];
@@ -3273,23 +3274,30 @@ rei_status rei_batch_graph_create(rei_instance* const* insts, size_t n, uint64_t
         rei_instance* in = g->batched[q.off + i];
         const uint64_t L = in->max_cost + 2;
         double c = 0;
-        for (uint64_t l = 0; l < L; ++l) c += (double)in->h_levels[2 * L + l];
+        uint64_t widest = 0;
+        for (uint64_t l = 0; l < L; ++l) {
+          c += (double)in->h_levels[2 * L + l];
+          widest = std::max(widest, in->h_levels[2 * L + l]);
+        }
         // a candidate of a wider language costs more (W words per operation)
         const double w = c * (1.0 + 0.25 * std::max(1, in->st.W)) + 1000.0;
         work_of[in] = w;
+        widest_of[in] = widest;
         all_work += w;
       }
     }
     // An instance with more than twice a resident workgroup's fair share of
-    // the work would decide the replay's length alone: it leaves the graph
-    // and runs rei_solve's path (whole device, hand-offs by level) on the
-    // worker threads while each replay runs.
+    // the work would decide the replay's length alone, and one with a level
+    // larger than rei_solve_batch's hand-off size is, there, solved from that
+    // level by the whole device: either leaves the graph and runs
+    // rei_solve's path on the worker threads while each replay runs.
     const double heavy = 2.0 * all_work / std::max(1.0, resident);
+    const uint64_t level_cap = tuned_level_max();
     bool moved = false;
     for (int w = 0; w <= kBatchMaxW; w = w ? 2 * w : 1) {
       auto& m = members[w];
       for (auto it = m.begin(); it != m.end();) {
-        if (work_of[*it] > heavy && work_of[*it] > kGraphHeavyMin) {
+        if ((work_of[*it] > heavy && work_of[*it] > kGraphHeavyMin) || widest_of[*it] > level_cap) {
           g->other.push_back(*it);
           it = m.erase(it);
           moved = true;
