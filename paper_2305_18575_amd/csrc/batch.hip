@@ -28,6 +28,21 @@ struct BlockD {
   uint64_t count;
 };
 
+// Work items of block b's candidates [e0, e1) in the current chunk: 64
+// consecutive candidates each, or one 64-candidate concatenation tile (64
+// right operands of one left operand, or 64 left operands of one right
+// operand when the right level is small and shorter than the left).
+__device__ inline uint64_t block_items(const BlockD& b, uint64_t e0, uint64_t e1, uint64_t nL, uint64_t nR) {
+  if (b.op != OP_CONCAT) return (e1 - e0 + 63) / 64;
+  if (nR >= 64 || nR >= nL) {
+    const uint64_t nT = (nR + 63) / 64;
+    const uint64_t f0 = (e0 / nR) * nT + (e0 % nR) / 64;
+    const uint64_t f1 = ((e1 - 1) / nR) * nT + ((e1 - 1) % nR) / 64;
+    return f1 - f0 + 1;
+  }
+  return ((e1 - 1) / nR / 64 - (e0 / nR) / 64 + 1) * nR;
+}
+
 // Barrier between phases whose global-memory effects later phases read.  An
 // instance's buffers are touched by its own workgroup only, and all waves of
 // a workgroup run on one CU, so workgroup scope suffices: the barrier makes
@@ -192,6 +207,7 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
   __shared__ uint64_t s_uniq[kBatchMaxCost + 2], s_cand[kBatchMaxCost + 2];
   __shared__ BlockD s_blk[kMaxBlocks];
   __shared__ uint64_t s_bstart[kMaxBlocks + 1];  // level index of each block's first candidate
+  __shared__ uint32_t s_item0[kMaxBlocks + 1];   // each block's first work item in the current chunk
   __shared__ uint32_t s_nblk;
   __shared__ uint32_t s_nsurv, s_ans, s_rank, s_over, s_stop, s_resume;
   __shared__ uint64_t s_total;
@@ -349,22 +365,86 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
         s_over = ~0u;
       }
       __syncthreads();
+      // Star blocks first, one at a time: they pair the waves and need the
+      // workgroup barriers around them.
       for (uint32_t bi = 0; bi < nblk; ++bi) {
         const uint64_t bs = s_bstart[bi], be = s_bstart[bi + 1];
         if (be <= E0) continue;
         if (bs >= E1) break;
         const BlockD blk = s_blk[bi];
-        const uint64_t lst = s_lstart[blk.L], lct = s_lcount[blk.L];
-        const uint64_t rst = s_lstart[blk.R], rct = s_lcount[blk.R];
+        if (blk.op != OP_STAR) continue;
+        const uint64_t lst = s_lstart[blk.L];
         // block-local candidate range of this chunk; candidate e of the block
         // has chunk-relative index bs + e - E0
         const uint64_t e0 = max(E0, bs) - bs, e1 = min(E1, be) - bs;
         const uint64_t rel0 = bs - E0;  // modulo 2^64: rel0 + e >= 0 for e >= e0
-
-        // ---- generate and probe
-        if (blk.op == OP_CHAR || blk.op == OP_QUESTION || blk.op == OP_UNION) {
-          for (uint64_t base = e0 + 64 * wave; base < e1; base += kT) {
-            const uint64_t e = base + lane;
+        // r* for 64 rows per wave pair: the even wave of each pair owns
+        // the pair's two tiles (Xt = its own, Yt = its partner's), so
+        // kWaves/2 groups of rows run at once with wave-level syncs only.
+        // The workgroup barriers around the block keep the partner's tile
+        // out of the neighbouring blocks' per-wave use.
+        __syncthreads();
+        if ((wave & 1u) == 0) {
+          uint64_t* Xt = s_tile[wave];
+          uint64_t* Yt = s_tile[wave + 1];
+          constexpr uint32_t kPairs = kWaves / 2;
+          for (uint64_t g0 = e0 + 64 * (uint64_t)(wave >> 1); g0 < e1; g0 += 64 * (uint64_t)kPairs) {
+            const uint64_t e = g0 + lane;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+              const uint64_t v = (e < e1) ? d.rows[(lst + e) * W + k] : 0ull;
+              Xt[64 * k + lane] = transpose64(v);
+            }
+            for (uint32_t w = lane; w < 64u * W; w += 64) Yt[w] = (w == 0) ? ~0ull : 0ull;
+            wave_sync_lds();
+            // Y(eps) = 1; by increasing length, Y(w) = OR over cuts w = u v
+            // with u non-empty of X(u) & Y(v) (v is shorter)
+            for (uint32_t l = 1; l <= d.max_len; ++l) {
+              const uint32_t lo = s_lo[l], hi = s_lo[l + 1];
+              for (uint32_t w = lo + lane; w < hi; w += 64) {
+                // a word of length l has cuts 0..l; cut 0 has u = eps
+                Yt[w] = star_fold(Xt, Yt, s_gtp, s_gto[w], l);
+              }
+              wave_sync_lds();
+            }
+            uint64_t key[W];
+#pragma unroll
+            for (int k = 0; k < W; ++k) key[k] = transpose64(Yt[64 * k + lane]);
+            filter_emit<W, kInl>(probe, sink, e < e1, false, key, (uint32_t)(rel0 + e));
+            wave_sync_lds();  // the tiles are rewritten by the next group
+          }
+        }
+        __syncthreads();
+      }
+      // Every other block's work items (64 consecutive candidates, or one
+      // concatenation tile) are dealt to the waves together, so a chunk that
+      // spans many small blocks keeps every wave busy.
+      if (tid == 0) {
+        uint32_t n = 0;
+        for (uint32_t bi = 0; bi < nblk; ++bi) {
+          s_item0[bi] = n;
+          const uint64_t bs = s_bstart[bi], be = s_bstart[bi + 1];
+          const BlockD blk = s_blk[bi];
+          if (be > E0 && bs < E1 && blk.op != OP_STAR)
+            n += (uint32_t)block_items(blk, max(E0, bs) - bs, min(E1, be) - bs, s_lcount[blk.L], s_lcount[blk.R]);
+        }
+        s_item0[nblk] = n;
+      }
+      __syncthreads();
+      {
+        const uint32_t n_items = s_item0[nblk];
+        uint32_t bi = 0;
+        for (uint32_t it = wave; it < n_items; it += kWaves) {
+          while (s_item0[bi + 1] <= it) ++bi;  // blocks with no items here are skipped
+          const uint32_t li = it - s_item0[bi];
+          const uint64_t bs = s_bstart[bi], be = s_bstart[bi + 1];
+          const BlockD blk = s_blk[bi];
+          const uint64_t lst = s_lstart[blk.L], lct = s_lcount[blk.L];
+          const uint64_t rst = s_lstart[blk.R], rct = s_lcount[blk.R];
+          const uint64_t e0 = max(E0, bs) - bs, e1 = min(E1, be) - bs;
+          const uint64_t rel0 = bs - E0;
+          if (blk.op != OP_CONCAT) {
+            const uint64_t e = e0 + 64 * (uint64_t)li + lane;
             const bool valid = e < e1;
             uint64_t key[W];
             bool dup = false;
@@ -401,90 +481,46 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
               dup = eqx || eqy;
             }
             filter_emit<W, kInl>(probe, sink, valid, dup, key, (uint32_t)(rel0 + e));
+            continue;
           }
-        } else if (blk.op == OP_STAR) {
-          // r* for 64 rows per wave pair: the even wave of each pair owns
-          // the pair's two tiles (Xt = its own, Yt = its partner's), so
-          // kWaves/2 groups of rows run at once with wave-level syncs only.
-          // The workgroup barriers around the block keep the partner's tile
-          // out of the neighbouring blocks' per-wave use.
-          __syncthreads();
-          if ((wave & 1u) == 0) {
-            uint64_t* Xt = s_tile[wave];
-            uint64_t* Yt = s_tile[wave + 1];
-            constexpr uint32_t kPairs = kWaves / 2;
-            for (uint64_t g0 = e0 + 64 * (uint64_t)(wave >> 1); g0 < e1; g0 += 64 * (uint64_t)kPairs) {
-              const uint64_t e = g0 + lane;
-#pragma unroll
-              for (int k = 0; k < W; ++k) {
-                const uint64_t v = (e < e1) ? d.rows[(lst + e) * W + k] : 0ull;
-                Xt[64 * k + lane] = transpose64(v);
-              }
-              for (uint32_t w = lane; w < 64u * W; w += 64) Yt[w] = (w == 0) ? ~0ull : 0ull;
-              wave_sync_lds();
-              // Y(eps) = 1; by increasing length, Y(w) = OR over cuts w = u v
-              // with u non-empty of X(u) & Y(v) (v is shorter)
-              for (uint32_t l = 1; l <= d.max_len; ++l) {
-                const uint32_t lo = s_lo[l], hi = s_lo[l + 1];
-                for (uint32_t w = lo + lane; w < hi; w += 64) {
-                  // a word of length l has cuts 0..l; cut 0 has u = eps
-                  Yt[w] = star_fold(Xt, Yt, s_gtp, s_gto[w], l);
-                }
-                wave_sync_lds();
-              }
-              uint64_t key[W];
-#pragma unroll
-              for (int k = 0; k < W; ++k) key[k] = transpose64(Yt[64 * k + lane]);
-              filter_emit<W, kInl>(probe, sink, e < e1, false, key, (uint32_t)(rel0 + e));
-              wave_sync_lds();  // the tiles are rewritten by the next group
-            }
-          }
-          __syncthreads();
-        } else {  // OP_CONCAT
           uint64_t* T = s_tile[wave];
           uint64_t* U = s_uni[wave];
           const uint64_t nL = lct, nR = rct;
-          const uint64_t i_lo = e0 / nR, i_hi = (e1 - 1) / nR;
           if (nR >= 64 || nR >= nL) {
-            // right operands across the lanes
+            // right operands across the lanes: tile f = i * nT + jt holds
+            // candidates i * nR + 64 * jt + lane; the block's items are the
+            // tiles from the one holding e0 to the one holding e1 - 1
             const uint64_t nT = (nR + 63) / 64;
-            const uint64_t items = (i_hi - i_lo + 1) * nT;
-            for (uint64_t it = wave; it < items; it += kWaves) {
-              const uint64_t i = i_lo + it / nT, jt = it % nT;
-              const uint64_t ef = i * nR + 64 * jt, el = i * nR + min(64 * jt + 64, nR);
-              if (el <= e0 || ef >= e1) continue;
-              const uint64_t jr = 64 * jt + lane;
+            const uint64_t f = (e0 / nR) * nT + (e0 % nR) / 64 + li;
+            const uint64_t i = f / nT, jt = f - i * nT;
+            const uint64_t jr = 64 * jt + lane;
 #pragma unroll
-              for (int k = 0; k < W; ++k)
-                T[64 * k + lane] = transpose64(jr < nR ? d.rows[(rst + jr) * W + k] : 0ull);
-              if (lane < (uint32_t)W) U[lane] = d.rows[(lst + i) * W + lane];
-              wave_sync_lds();
-              uint64_t key[W];
-              concat_tile<W, false>(T, U, s_gto, s_gtp, d.n, d.max_len + 1, key);
-              const uint64_t e = i * nR + jr;
-              filter_emit<W, kInl>(probe, sink, jr < nR && e >= e0 && e < e1, false, key, (uint32_t)(rel0 + e));
-              wave_sync_lds();
-            }
+            for (int k = 0; k < W; ++k)
+              T[64 * k + lane] = transpose64(jr < nR ? d.rows[(rst + jr) * W + k] : 0ull);
+            if (lane < (uint32_t)W) U[lane] = d.rows[(lst + i) * W + lane];
+            wave_sync_lds();
+            uint64_t key[W];
+            concat_tile<W, false>(T, U, s_gto, s_gtp, d.n, d.max_len + 1, key);
+            const uint64_t e = i * nR + jr;
+            filter_emit<W, kInl>(probe, sink, jr < nR && e >= e0 && e < e1, false, key, (uint32_t)(rel0 + e));
+            wave_sync_lds();
           } else {
-            // left operands across the lanes (the right level is small)
-            const uint64_t it_lo = i_lo / 64, it_hi = i_hi / 64;
-            const uint64_t items = (it_hi - it_lo + 1) * nR;
-            for (uint64_t it = wave; it < items; it += kWaves) {
-              const uint64_t xt = it_lo + it / nR, j = it % nR;
-              const uint64_t ef = (64 * xt) * nR + j, el = (64 * xt + 63) * nR + j;
-              if (el < e0 || ef >= e1) continue;
-              const uint64_t ir = 64 * xt + lane;
+            // left operands across the lanes (the right level is small):
+            // item li is (left tile xt, right operand j)
+            const uint64_t xt = (e0 / nR) / 64 + li / nR, j = li % nR;
+            const uint64_t ef = (64 * xt) * nR + j, el = (64 * xt + 63) * nR + j;
+            if (el < e0 || ef >= e1) continue;
+            const uint64_t ir = 64 * xt + lane;
 #pragma unroll
-              for (int k = 0; k < W; ++k)
-                T[64 * k + lane] = transpose64(ir < nL ? d.rows[(lst + ir) * W + k] : 0ull);
-              if (lane < (uint32_t)W) U[lane] = d.rows[(rst + j) * W + lane];
-              wave_sync_lds();
-              uint64_t key[W];
-              concat_tile<W, true>(T, U, s_gto, s_gtp, d.n, d.max_len + 1, key);
-              const uint64_t e = ir * nR + j;
-              filter_emit<W, kInl>(probe, sink, ir < nL && e >= e0 && e < e1, false, key, (uint32_t)(rel0 + e));
-              wave_sync_lds();
-            }
+            for (int k = 0; k < W; ++k)
+              T[64 * k + lane] = transpose64(ir < nL ? d.rows[(lst + ir) * W + k] : 0ull);
+            if (lane < (uint32_t)W) U[lane] = d.rows[(rst + j) * W + lane];
+            wave_sync_lds();
+            uint64_t key[W];
+            concat_tile<W, true>(T, U, s_gto, s_gtp, d.n, d.max_len + 1, key);
+            const uint64_t e = ir * nR + j;
+            filter_emit<W, kInl>(probe, sink, ir < nL && e >= e0 && e < e1, false, key, (uint32_t)(rel0 + e));
+            wave_sync_lds();
           }
         }
       }
