@@ -521,6 +521,27 @@ rei_status enqueue_chunk(rei_instance* in, hipStream_t s, uint32_t c, const std:
   // small pieces (W <= kPiecesMaxW) share gen_pieces launches of up to
   // kMaxPieces pieces; larger ones get their constructor's kernel
   PieceArgs pa{};
+  // large concatenation blocks share gen_concat launches of up to
+  // kMaxConcatParts blocks
+  ConcatSet cset{};
+  uint64_t cset_cand = 0;
+  auto flush_concat = [&]() -> rei_status {
+    if (!cset.n) return REI_OK;
+    LAUNCH(in, s, REI_K_GEN_CONCAT, cset_cand, launch_concat_set(W, g, cset, s));
+    cset = ConcatSet{};
+    cset_cand = 0;
+    return REI_OK;
+  };
+  // large union blocks share gen_union launches likewise
+  UnionSet uset{};
+  uint64_t uset_cand = 0;
+  auto flush_union = [&]() -> rei_status {
+    if (!uset.n) return REI_OK;
+    LAUNCH(in, s, REI_K_GEN_UNION, uset_cand, launch_union_set(W, g, uset, s));
+    uset = UnionSet{};
+    uset_cand = 0;
+    return REI_OK;
+  };
   auto flush_pieces = [&]() -> rei_status {
     if (!pa.n) return REI_OK;
     GenArgs gp = g;  // pieces carry their own ranges; characters index from the table's start
@@ -574,6 +595,26 @@ rei_status enqueue_chunk(rei_instance* in, hipStream_t s, uint32_t c, const std:
       if (++pa.n == kMaxPieces && (r = flush_pieces()) != REI_OK) return r;
       continue;
     }
+    if (b.op == OP_CONCAT) {
+      ConcatPart& cp = cset.p[cset.n];
+      cp = ConcatPart{};
+      cp.lstart = in->lstart[b.L];
+      cp.rstart = in->lstart[b.R];
+      cp.rcount = in->lcount[b.R];
+      cp.e0 = p.e0;
+      cp.e1 = p.e1;
+      cp.rel0 = (uint32_t)(p.e_base + p.e0 - chunk_e0);
+      cset_cand += p.e1 - p.e0;
+      if (++cset.n == (uint32_t)kMaxConcatParts && (r = flush_concat()) != REI_OK) return r;
+      continue;
+    }
+    if (b.op == OP_UNION) {
+      uset.p[uset.n] = UnionPart{in->lstart[b.L], in->lcount[b.L], in->lstart[b.R], in->lcount[b.R], p.e0, p.e1,
+                                 (uint32_t)(p.e_base + p.e0 - chunk_e0), b.same ? 1u : 0u, 0, 0};
+      uset_cand += p.e1 - p.e0;
+      if (++uset.n == (uint32_t)kMaxUnionParts && (r = flush_union()) != REI_OK) return r;
+      continue;
+    }
     g.e0 = p.e0;
     g.e1 = p.e1;
     g.rel0 = (uint32_t)(p.e_base + p.e0 - chunk_e0);
@@ -595,6 +636,8 @@ rei_status enqueue_chunk(rei_instance* in, hipStream_t s, uint32_t c, const std:
     LAUNCH(in, s, REI_K_GEN_CHAR + b.op, p.e1 - p.e0, launch_gen(W, b.op, g, b.same, s));
   }
   if ((r = flush_pieces()) != REI_OK) return r;
+  if ((r = flush_concat()) != REI_OK) return r;
+  if ((r = flush_union()) != REI_OK) return r;
 
   ChunkArgs ca{};
   ca.rows = in->d_rows;

@@ -235,6 +235,41 @@ struct PieceArgs {
 };
 hipError_t launch_gen_pieces(int W, const GenArgs& a, const PieceArgs& p, hipStream_t s);
 
+// Several large concatenation blocks of one chunk in one gen_concat launch,
+// so that blocks too small to fill the device run side by side: each part
+// has its own operand levels and candidate range; the launcher gives each a
+// tile shape and a range of workgroups.
+constexpr int kMaxConcatParts = 16;
+struct ConcatPart {
+  uint64_t lstart, rstart, rcount;  // left level's first row; right level's first row and size
+  uint64_t e0, e1;                  // block-local candidate range
+  uint64_t i_lo, i_hi;              // left rows of the range (set by the launcher)
+  uint32_t rel0;                    // chunk-relative index of candidate e0
+  uint32_t yt, xi, gx;              // right tiles and left rows per workgroup, tile groups (launcher)
+  uint32_t wg0, pad;                // first workgroup of this part (launcher)
+};
+struct ConcatSet {
+  uint32_t n, pad;
+  ConcatPart p[kMaxConcatParts];
+};
+hipError_t launch_concat_set(int W, const GenArgs& a, const ConcatSet& cs, hipStream_t s);
+
+// Several large union blocks of one chunk in one gen_union launch (one
+// thread per candidate; the launcher gives each part its workgroups).
+constexpr int kMaxUnionParts = 16;
+struct UnionPart {
+  uint64_t lstart, lcount, rstart, rcount;  // operand levels: first row, number of rows
+  uint64_t e0, e1;                          // block-local candidate range
+  uint32_t rel0;                            // chunk-relative index of candidate e0
+  uint32_t same;                            // both operands from one level: pairs x < y
+  uint32_t wg0, pad;                        // first workgroup of this part (launcher)
+};
+struct UnionSet {
+  uint32_t n, pad;
+  UnionPart p[kMaxUnionParts];
+};
+hipError_t launch_union_set(int W, const GenArgs& a, const UnionSet& us, hipStream_t s);
+
 // ---- batched solver: one workgroup runs the whole search of one instance --
 constexpr uint32_t kBatchChunk = 8192;   // candidates per chunk
 constexpr uint32_t kBatchMaxCost = 63;   // largest max_cost handled in a batch

@@ -128,10 +128,22 @@ constexpr uint64_t kConcatWideWaves = 256 * 8;  // waves below which the cut-out
 // reads are in flight per round instead of one: fewer rounds of latency
 // for small launches, more LDS instructions for large ones.
 template <int W, bool kShort, bool kInl, bool kGtLds, bool kWide>
-__global__ __launch_bounds__(256) void gen_concat(GenArgs a, uint32_t yt_per_wg, uint32_t xi_per_wg,
-                                                  uint64_t i_lo, uint64_t i_hi, uint32_t n_tile_groups) {
+__global__ __launch_bounds__(256) void gen_concat(GenArgs a, ConcatSet cs) {
   extern __shared__ uint64_t lds[];
   if (a.st->stop) return;
+  // this workgroup's part (block) and its place in the part's grid
+  uint32_t part = 0;
+  while (part + 1 < cs.n && cs.p[part + 1].wg0 <= blockIdx.x) ++part;
+  const ConcatPart& cp = cs.p[part];
+  a.lstart = cp.lstart;
+  a.rstart = cp.rstart;
+  a.rcount = cp.rcount;
+  a.e0 = cp.e0;
+  a.e1 = cp.e1;
+  a.rel0 = cp.rel0;
+  const uint32_t yt_per_wg = cp.yt, xi_per_wg = cp.xi, n_tile_groups = cp.gx;
+  const uint64_t i_lo = cp.i_lo, i_hi = cp.i_hi;
+  const uint32_t bid = blockIdx.x - cp.wg0;
   uint64_t* Yt = lds;                                        // [yt_per_wg][64W]
   uint64_t* Xs = Yt + (size_t)yt_per_wg * 64 * W;            // [xi_per_wg][W]
   uint32_t* G = (uint32_t*)(Xs + (size_t)xi_per_wg * W);     // guide pairs (if gt_lds)
@@ -139,9 +151,9 @@ __global__ __launch_bounds__(256) void gen_concat(GenArgs a, uint32_t yt_per_wg,
   const uint64_t nR = a.rcount;
   const uint64_t nT = (nR + 63) / 64;
   // flat grid: workgroup -> (group of right tiles, group of left rows)
-  const uint64_t t0 = (uint64_t)(blockIdx.x % n_tile_groups) * yt_per_wg;
+  const uint64_t t0 = (uint64_t)(bid % n_tile_groups) * yt_per_wg;
   const uint32_t nt = (uint32_t)min<uint64_t>(yt_per_wg, nT - t0);
-  const uint64_t x0 = i_lo + (uint64_t)(blockIdx.x / n_tile_groups) * xi_per_wg;
+  const uint64_t x0 = i_lo + (uint64_t)(bid / n_tile_groups) * xi_per_wg;
   const uint32_t nx = (uint32_t)min<uint64_t>(xi_per_wg, i_hi + 1 - x0);
 
   // stage right tiles (transposed), left rows and guide table; every load
@@ -269,22 +281,29 @@ __global__ __launch_bounds__(256) void gen_concat(GenArgs a, uint32_t yt_per_wg,
   }
 }
 
-template <int W, bool kSame, bool kInl>
-__global__ __launch_bounds__(256) void gen_union(GenArgs a) {
+// One thread per candidate x + y; several union blocks of a chunk share a
+// launch (UnionSet), each workgroup in one block.
+template <int W, bool kInl>
+__global__ __launch_bounds__(256) void gen_union(GenArgs a, UnionSet us) {
   if (a.st->stop) return;
-  const uint64_t e = a.e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = e < a.e1;
+  uint32_t part = 0;
+  while (part + 1 < us.n && us.p[part + 1].wg0 <= blockIdx.x) ++part;
+  const UnionPart& up = us.p[part];
+  a.e0 = up.e0;
+  a.rel0 = up.rel0;
+  const uint64_t e = up.e0 + (uint64_t)(blockIdx.x - up.wg0) * blockDim.x + threadIdx.x;
+  const bool valid = e < up.e1;
   uint64_t i = 0, j = 0;
   if (valid) {
-    if (kSame) {
-      tri_decode(e, a.lcount, &i, &j);
+    if (up.same) {
+      tri_decode(e, up.lcount, &i, &j);
     } else {
-      i = e / a.rcount;
-      j = e - i * a.rcount;
+      i = e / up.rcount;
+      j = e - i * up.rcount;
     }
   }
-  const uint64_t* x = a.rows + (a.lstart + i) * W;
-  const uint64_t* y = a.rows + (a.rstart + j) * W;
+  const uint64_t* x = a.rows + (up.lstart + i) * W;
+  const uint64_t* y = a.rows + (up.rstart + j) * W;
   uint64_t key[W];
   bool eqx = true, eqy = true;
 #pragma unroll
@@ -802,28 +821,42 @@ inline uint32_t grid_for(uint64_t n, uint32_t block, uint32_t cap = 0x7fffffffu)
 }
 
 template <int W, bool kInl>
-hipError_t launch_concat_w(const GenArgs& a, hipStream_t s) {
-  const uint64_t nR = a.rcount;
-  const uint64_t i_lo = a.e0 / nR, i_hi = (a.e1 - 1) / nR;
-  const uint64_t rowsx = i_hi - i_lo + 1;
-  const uint64_t nT = (nR + 63) / 64;
+hipError_t launch_concat_w(const GenArgs& a, ConcatSet cs, hipStream_t s) {
+  if (cs.n == 0 || cs.n > (uint32_t)kMaxConcatParts) return hipErrorInvalidValue;
   // right tiles in LDS: at most 32 KB
   const uint32_t yt_cap = (uint32_t)std::max(1, std::min(kConcatYT, 32768 / (512 * W)));
-  uint32_t yt = (uint32_t)std::min<uint64_t>(yt_cap, nT);
-  // left rows per workgroup: at most concat_xi (16 by default), fewer (down
-  // to 4), then fewer right tiles, while the grid has under concat_wg
-  // workgroups (2048 by default)
+  // per part: left rows per workgroup at most concat_xi (16 by default),
+  // fewer (down to 4), then fewer right tiles, while its grid has under
+  // concat_wg workgroups (2048 by default)
   const uint64_t target = a.concat_wg ? a.concat_wg : 2048;
-  uint32_t xi = a.concat_xi ? std::min<uint32_t>(a.concat_xi, 64) : 16;
-  auto wgs = [&](uint32_t y, uint32_t x) { return ((nT + y - 1) / y) * ((rowsx + x - 1) / x); };
-  while (xi > 4 && wgs(yt, xi) < target) xi /= 2;
-  while (yt > 1 && wgs(yt, xi) < target) yt /= 2;
-  size_t lds = (size_t)yt * 64 * W * 8 + (size_t)xi * W * 8;
+  const uint32_t xi_max = a.concat_xi ? std::min<uint32_t>(a.concat_xi, 64) : 16;
+  size_t lds = 0;
+  uint64_t wgs_total = 0;
+  for (uint32_t k = 0; k < cs.n; ++k) {
+    ConcatPart& p = cs.p[k];
+    const uint64_t nR = p.rcount;
+    if (nR == 0 || p.e1 <= p.e0) return hipErrorInvalidValue;
+    p.i_lo = p.e0 / nR;
+    p.i_hi = (p.e1 - 1) / nR;
+    const uint64_t rowsx = p.i_hi - p.i_lo + 1;
+    const uint64_t nT = (nR + 63) / 64;
+    uint32_t yt = (uint32_t)std::min<uint64_t>(yt_cap, nT);
+    uint32_t xi = xi_max;
+    auto wgs = [&](uint32_t y, uint32_t x) { return ((nT + y - 1) / y) * ((rowsx + x - 1) / x); };
+    while (xi > 4 && wgs(yt, xi) < target) xi /= 2;
+    while (yt > 1 && wgs(yt, xi) < target) yt /= 2;
+    lds = std::max(lds, (size_t)yt * 64 * W * 8 + (size_t)xi * W * 8);
+    const uint64_t gx = (nT + yt - 1) / yt, gy = (rowsx + xi - 1) / xi;
+    p.yt = yt;
+    p.xi = xi;
+    p.gx = (uint32_t)gx;
+    p.wg0 = (uint32_t)wgs_total;
+    wgs_total += gx * gy;
+    if (wgs_total > 0x7fffffffull) return hipErrorInvalidConfiguration;
+  }
   const uint32_t gt_lds = (lds + (size_t)a.n_pairs * 4 <= 60 * 1024) ? 1u : 0u;
   if (gt_lds) lds += (size_t)a.n_pairs * 4;
-  const uint64_t gx = (nT + yt - 1) / yt, gy = (rowsx + xi - 1) / xi;
-  if (gx * gy > 0x7fffffffull) return hipErrorInvalidConfiguration;
-  const dim3 grid((uint32_t)(gx * gy));
+  const dim3 grid((uint32_t)wgs_total);
   const bool shrt = a.max_len < 32;
   // the cut-outer fold for launches with fewer waves than the device holds
   // at once (latency-bound), the word-outer fold for larger ones
@@ -831,25 +864,48 @@ hipError_t launch_concat_w(const GenArgs& a, hipStream_t s) {
     const char* e = std::getenv("REI_CONCAT_WIDE");
     return e ? std::atoi(e) : 0;  // 0 by launch size, 1 never, 2 always
   }();
-  const bool wide = shrt && (wide_mode == 2 || (wide_mode == 0 && gx * gy * 4 <= kConcatWideWaves));
+  const bool wide = shrt && (wide_mode == 2 || (wide_mode == 0 && wgs_total * 4 <= kConcatWideWaves));
   if (wide && gt_lds)
-    launch_timed(gen_concat<W, true, kInl, true, true>, grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
-                 (uint32_t)gx);
+    launch_timed(gen_concat<W, true, kInl, true, true>, grid, dim3(256), lds, s, a, cs);
   else if (wide)
-    launch_timed(gen_concat<W, true, kInl, false, true>, grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
-                 (uint32_t)gx);
+    launch_timed(gen_concat<W, true, kInl, false, true>, grid, dim3(256), lds, s, a, cs);
   else if (shrt && gt_lds)
-    launch_timed(gen_concat<W, true, kInl, true, false>, grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
-                 (uint32_t)gx);
+    launch_timed(gen_concat<W, true, kInl, true, false>, grid, dim3(256), lds, s, a, cs);
   else if (shrt)
-    launch_timed(gen_concat<W, true, kInl, false, false>, grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
-                 (uint32_t)gx);
+    launch_timed(gen_concat<W, true, kInl, false, false>, grid, dim3(256), lds, s, a, cs);
   else if (gt_lds)
-    launch_timed(gen_concat<W, false, kInl, true, false>, grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
-                 (uint32_t)gx);
+    launch_timed(gen_concat<W, false, kInl, true, false>, grid, dim3(256), lds, s, a, cs);
   else
-    launch_timed(gen_concat<W, false, kInl, false, false>, grid, dim3(256), lds, s, a, yt, xi, i_lo, i_hi,
-                 (uint32_t)gx);
+    launch_timed(gen_concat<W, false, kInl, false, false>, grid, dim3(256), lds, s, a, cs);
+  return hipGetLastError();
+}
+
+// One block of candidates [a.e0, a.e1) as a one-part set.
+template <int W, bool kInl>
+hipError_t launch_concat_one(const GenArgs& a, hipStream_t s) {
+  ConcatSet cs{};
+  cs.n = 1;
+  cs.p[0].lstart = a.lstart;
+  cs.p[0].rstart = a.rstart;
+  cs.p[0].rcount = a.rcount;
+  cs.p[0].e0 = a.e0;
+  cs.p[0].e1 = a.e1;
+  cs.p[0].rel0 = a.rel0;
+  return launch_concat_w<W, kInl>(a, cs, s);
+}
+
+template <int W, bool kInl>
+hipError_t launch_union_w(const GenArgs& a, UnionSet us, hipStream_t s) {
+  if (us.n == 0 || us.n > (uint32_t)kMaxUnionParts) return hipErrorInvalidValue;
+  uint64_t wgs = 0;
+  for (uint32_t k = 0; k < us.n; ++k) {
+    UnionPart& p = us.p[k];
+    if (p.e1 <= p.e0 || p.lcount == 0 || (!p.same && p.rcount == 0)) return hipErrorInvalidValue;
+    p.wg0 = (uint32_t)wgs;
+    wgs += (p.e1 - p.e0 + 255) / 256;
+    if (wgs > 0x7fffffffull) return hipErrorInvalidConfiguration;
+  }
+  launch_timed(gen_union<W, kInl>, dim3((uint32_t)wgs), dim3(256), 0, s, a, us);
   return hipGetLastError();
 }
 
@@ -867,13 +923,13 @@ hipError_t launch_gen_w(int op, const GenArgs& a, bool same_level, hipStream_t s
       launch_timed(gen_star<W, kInl>, dim3(grid_for(cnt, 64)), dim3(256), 0, s, a);
       break;
     case OP_CONCAT:
-      return launch_concat_w<W, kInl>(a, s);
-    case OP_UNION:
-      if (same_level)
-        launch_timed(gen_union<W, true, kInl>, dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
-      else
-        launch_timed(gen_union<W, false, kInl>, dim3(grid_for(cnt, 256)), dim3(256), 0, s, a);
-      break;
+      return launch_concat_one<W, kInl>(a, s);
+    case OP_UNION: {
+      UnionSet us{};
+      us.n = 1;
+      us.p[0] = UnionPart{a.lstart, a.lcount, a.rstart, a.rcount, a.e0, a.e1, a.rel0, same_level ? 1u : 0u, 0, 0};
+      return launch_union_w<W, kInl>(a, us, s);
+    }
     default:
       return hipErrorInvalidValue;
   }
@@ -926,6 +982,20 @@ hipError_t launch_rehash(int W, bool inl, const uint64_t* rows, uint64_t nrows, 
 hipError_t launch_gen(int W, int op, const GenArgs& a, bool same_level, hipStream_t s) {
   if (a.e1 <= a.e0) return hipSuccess;
   REI_DISPATCH_WI(W, a.inl, return (launch_gen_w<kW, kI>(op, a, same_level, s)));
+  return hipGetLastError();
+}
+
+hipError_t launch_union_set(int W, const GenArgs& a, const UnionSet& us, hipStream_t s) {
+  if (us.n == 0) return hipSuccess;
+  if (!a.rows || !a.st || !a.ctrl) return hipErrorInvalidValue;
+  REI_DISPATCH_WI(W, a.inl, return (launch_union_w<kW, kI>(a, us, s)));
+  return hipGetLastError();
+}
+
+hipError_t launch_concat_set(int W, const GenArgs& a, const ConcatSet& cs, hipStream_t s) {
+  if (cs.n == 0) return hipSuccess;
+  if (!a.rows || !a.gt_off || !a.gt_pair || !a.st || !a.ctrl) return hipErrorInvalidValue;
+  REI_DISPATCH_WI(W, a.inl, return (launch_concat_w<kW, kI>(a, cs, s)));
   return hipGetLastError();
 }
 
