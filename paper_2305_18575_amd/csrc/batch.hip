@@ -214,6 +214,8 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
   __shared__ uint32_t s_bm[kWords], s_pre[kWords];
   __shared__ uint32_t s_winners;
   __shared__ uint64_t s_tile[kWaves][64 * W];
+  static_assert(W < 8 || sizeof(s_tile) >= kBatchChunk * sizeof(uint16_t), "ranks of a chunk fit the tiles");
+  static_assert(kBatchChunk <= 0xFFFFu, "ranks of a chunk fit 16 bits");
   __shared__ uint64_t s_uni[kWaves][W];
   __shared__ uint32_t s_gto[kIc + 1], s_gtp[kPairs], s_lo[kIc + 2];
   __shared__ uint32_t s_item;
@@ -559,26 +561,47 @@ __global__ __launch_bounds__(kT) void solve_batch(const BatchDesc* descs, uint32
         const uint64_t room = d.row_cap > total ? d.row_cap - total : 0;
         const uint64_t alloc_room = d.rows_alloc > total ? d.rows_alloc - total : 0;
         const uint32_t ans = s_ans;
-        for (uint32_t sid = tid; sid < ns; sid += kT) {
-          const uint32_t e = d.se[sid];
+        // each survivor's rank among the stored rows (kNotStored: not stored)
+        constexpr uint32_t kNotStored = 0xFFFFu;  // ranks are below kBatchChunk
+        auto place = [&](uint32_t sid, uint32_t e) -> uint32_t {
           const uint32_t word = s_bm[e >> 5];
           const uint32_t bit = 1u << (e & 31);
-          if (!(word & bit)) continue;
+          if (!(word & bit)) return kNotStored;
           const uint32_t rank = s_pre[e >> 5] + (uint32_t)__popc(word & (bit - 1));
           if (e == ans) s_rank = rank;
-          if (ans != ~0u && e >= ans) continue;
-          if (rank < room && rank < alloc_room) {
+          if (ans != ~0u && e >= ans) return kNotStored;
+          if (rank < room && rank < alloc_room) return rank;
+          if (rank == room) s_over = e;
+          return kNotStored;
+        };
+        if constexpr (W < 8) {
+          for (uint32_t sid = tid; sid < ns; sid += kT) {
+            const uint32_t e = d.se[sid];
+            const uint32_t rank = place(sid, e);
+            if (rank == kNotStored) continue;
             const uint64_t row = total + rank;
-            uint64_t key[W];
 #pragma unroll
-            for (int k = 0; k < W; ++k) {
-              key[k] = d.skey[(uint64_t)sid * W + k];
-              d.rows[row * W + k] = key[k];
-            }
+            for (int k = 0; k < W; ++k) d.rows[row * W + k] = d.skey[(uint64_t)sid * W + k];
             d.aux[row] = E0 + e;
             table_publish<kInl>(d.slots, d.sref, d.spos[sid], row);
-          } else if (rank == room) {
-            s_over = e;
+          }
+        } else {
+          // wide rows: ranks into LDS (over the tiles, idle in this phase),
+          // then W consecutive lanes copy one row, whole rows per wave
+          uint16_t* s_dst = reinterpret_cast<uint16_t*>(&s_tile[0][0]);
+          for (uint32_t sid = tid; sid < ns; sid += kT) s_dst[sid] = (uint16_t)place(sid, d.se[sid]);
+          __syncthreads();
+          constexpr uint32_t kPer = kT / W;  // rows per round
+          const uint32_t k = tid % W;
+          for (uint32_t q = tid / W; q < ns; q += kPer) {
+            const uint32_t rank = s_dst[q];
+            if (rank == kNotStored) continue;
+            const uint64_t row = total + rank;
+            d.rows[row * W + k] = d.skey[(uint64_t)q * W + k];
+            if (k == 0) {
+              d.aux[row] = E0 + d.se[q];
+              table_publish<kInl>(d.slots, d.sref, d.spos[q], row);
+            }
           }
         }
         __syncthreads();

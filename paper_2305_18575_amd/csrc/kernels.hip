@@ -604,6 +604,8 @@ __device__ __forceinline__ void store_winner(const ChunkArgs& a, uint32_t sid, u
 }
 
 constexpr uint32_t kSmallWords = (uint32_t)(kSmallChunk / 32);
+constexpr uint64_t kSmallCopyWords = 1ull << 16;
+static_assert(kSmallChunk <= 0xFFFFu, "survivor ranks of a small chunk fit 16 bits");
 
 // Whole finalization of a small chunk in one workgroup: winner bitmap in LDS,
 // its prefix scan, ordered append, accounting.
@@ -612,6 +614,8 @@ __global__ __launch_bounds__(1024) void finalize_small(ChunkArgs a) {
   __shared__ uint32_t bm[kSmallWords];
   __shared__ uint32_t pre[kSmallWords];
   __shared__ uint32_t s_rank, s_over, s_total;
+  __shared__ uint16_t dst[W <= 2 ? 1 : kSmallChunk];  // wide rows: each survivor's rank
+  constexpr uint32_t kNotStored = 0xFFFFu;             // ranks are below kSmallChunk
   if (a.st->stop) return;
   const uint32_t t = threadIdx.x;
   const uint32_t ns = a.ctrl->n_surv, ans = a.ctrl->answer_e;
@@ -645,27 +649,60 @@ __global__ __launch_bounds__(1024) void finalize_small(ChunkArgs a) {
   const uint32_t total = s_total;
   const uint64_t row_base = a.st->total_rows;
   const uint64_t room = a.st->row_cap > row_base ? a.st->row_cap - row_base : 0;
-  auto place = [&](uint32_t sid, uint32_t e) {
+  // each survivor's rank among the stored rows (kNotStored: not stored)
+  auto place = [&](uint32_t sid, uint32_t e) -> uint32_t {
     const uint32_t word = bm[e >> 5];
     const uint32_t bit = 1u << (e & 31);
-    if (!(word & bit)) return;  // e is unique per survivor: the bit marks this one
+    if (!(word & bit)) return kNotStored;  // e is unique per survivor: the bit marks this one
     const uint32_t rank = pre[e >> 5] + (uint32_t)__popc(word & (bit - 1));
     if (e == ans) s_rank = rank;
-    if (ans != ~0u && e >= ans) return;  // the answer and later ones are not stored
-    if (rank < room)
-      store_winner<W, kInl>(a, sid, e, row_base + rank);
-    else if (rank == room)
-      s_over = e;
+    if (ans != ~0u && e >= ans) return kNotStored;  // the answer and later ones are not stored
+    if (rank < room) return rank;
+    if (rank == room) s_over = e;
+    return kNotStored;
   };
-  sid = t;
-  for (; sid + 3 * 1024 < ns; sid += 4 * 1024) {
-    const uint32_t e0 = a.se[sid], e1 = a.se[sid + 1024], e2 = a.se[sid + 2048], e3 = a.se[sid + 3072];
-    place(sid, e0);
-    place(sid + 1024, e1);
-    place(sid + 2048, e2);
-    place(sid + 3072, e3);
+  if constexpr (W <= 2) {
+    sid = t;
+    for (; sid + 3 * 1024 < ns; sid += 4 * 1024) {
+      const uint32_t e0 = a.se[sid], e1 = a.se[sid + 1024], e2 = a.se[sid + 2048], e3 = a.se[sid + 3072];
+      const uint32_t r0 = place(sid, e0), r1 = place(sid + 1024, e1), r2 = place(sid + 2048, e2),
+                     r3 = place(sid + 3072, e3);
+      if (r0 != kNotStored) store_winner<W, kInl>(a, sid, e0, row_base + r0);
+      if (r1 != kNotStored) store_winner<W, kInl>(a, sid + 1024, e1, row_base + r1);
+      if (r2 != kNotStored) store_winner<W, kInl>(a, sid + 2048, e2, row_base + r2);
+      if (r3 != kNotStored) store_winner<W, kInl>(a, sid + 3072, e3, row_base + r3);
+    }
+    for (; sid < ns; sid += 1024) {
+      const uint32_t e = a.se[sid];
+      const uint32_t r = place(sid, e);
+      if (r != kNotStored) store_winner<W, kInl>(a, sid, e, row_base + r);
+    }
+  } else {
+    // wide rows: ranks first, then W consecutive lanes copy one row, so
+    // that each wave reads and writes whole rows (coalesced)
+    sid = t;
+    for (; sid + 3 * 1024 < ns; sid += 4 * 1024) {
+      const uint32_t e0 = a.se[sid], e1 = a.se[sid + 1024], e2 = a.se[sid + 2048], e3 = a.se[sid + 3072];
+      dst[sid] = (uint16_t)place(sid, e0);
+      dst[sid + 1024] = (uint16_t)place(sid + 1024, e1);
+      dst[sid + 2048] = (uint16_t)place(sid + 2048, e2);
+      dst[sid + 3072] = (uint16_t)place(sid + 3072, e3);
+    }
+    for (; sid < ns; sid += 1024) dst[sid] = (uint16_t)place(sid, a.se[sid]);
+    __syncthreads();
+    constexpr uint32_t kPer = 1024 / W;  // rows per round
+    const uint32_t k = t % W;
+    for (uint32_t q = t / W; q < ns; q += kPer) {
+      const uint32_t r = dst[q];
+      if (r == kNotStored) continue;
+      const uint64_t row = row_base + r;
+      a.rows_w[row * W + k] = a.skey[(uint64_t)q * W + k];
+      if (k == 0) {
+        a.aux[row] = a.chunk_e0 + a.se[q];
+        table_publish<kInl>(a.slots, a.sref, a.spos[q], row);
+      }
+    }
   }
-  for (; sid < ns; sid += 1024) place(sid, a.se[sid]);
   __syncthreads();
   if (t == 0) account_chunk(a, ans, s_rank, total, s_over);
 }
@@ -1037,7 +1074,9 @@ hipError_t launch_insert(int W, const ChunkArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_finalize(int W, const ChunkArgs& a, hipStream_t s) {
-  if (a.len <= kSmallChunk) {
+  // one workgroup moves at most kSmallCopyWords words of rows: a chunk
+  // with more is finalized by the grid kernels, spread over the device
+  if (a.len <= kSmallChunk && a.len * (uint64_t)W <= kSmallCopyWords) {
     REI_DISPATCH_WI(W, a.inl, hipLaunchKernelGGL((finalize_small<kW, kI>), dim3(1), dim3(1024), 0, s, a));
     return hipGetLastError();
   }
