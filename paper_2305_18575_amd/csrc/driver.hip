@@ -448,11 +448,9 @@ bool make_blocks(const rei_instance* in, uint32_t c, std::vector<Block>* out, bo
   return true;
 }
 
-// Waits for the stream and reads the device search state.
+// Waits for the stream; the search state is then in the host mirrors
+// (h_state, h_levels), which every kernel that advances it writes as well.
 rei_status sync_state(rei_instance* in, hipStream_t s) {
-  const uint64_t L = in->max_cost + 2;
-  HIP_OK(in, hipMemcpyAsync(in->h_state, in->d_state, sizeof(DevState), hipMemcpyDeviceToHost, s));
-  HIP_OK(in, hipMemcpyAsync(in->h_levels, in->d_levels, 3 * L * 8, hipMemcpyDeviceToHost, s));
   HIP_OK(in, hipStreamSynchronize(s));
   in->known_rows = in->h_state->total_rows;
   in->pending = 0;
@@ -663,6 +661,10 @@ rei_status enqueue_chunk(rei_instance* in, hipStream_t s, uint32_t c, const std:
   ca.cost = c;
   ca.chunk_e0 = chunk_e0;
   ca.len = len;
+  ca.hst = in->v_state;
+  ca.hlev = in->v_levels;
+  ca.nlev = L;
+  ca.clear_words = finalize_in_one_workgroup(W, len) ? 0u : (uint32_t)words;
   if (otf_level) {
     LAUNCH(in, s, REI_K_COMPACT, len, launch_account(ca, s));
     return REI_OK;
@@ -990,6 +992,18 @@ rei_status search_levels(rei_instance* in, hipStream_t s) {
     // of its preallocated rows and left some behind)
     in->known_rows = 0;
     LAUNCH(in, s, REI_K_OTHER, 3 * L, launch_fill(in->d_levels, 3 * L, 0, s));
+    // the host mirrors of the state just reset (the stream has no earlier
+    // work of this instance that writes them)
+    std::memset(in->h_levels, 0, 3 * L * 8);
+    DevState* hs = in->h_state;
+    hs->total_rows = 0;
+    hs->row_cap = in->row_cap;
+    hs->stop = STOP_NONE;
+    hs->answer_cost = 0;
+    hs->answer_e = 0;
+    hs->resume_level = 0;
+    hs->otf_on = in->otf_on ? 1u : 0u;
+    hs->otf = 0;
     if ((r = ensure_table(in, 1024, s, true)) != REI_OK) return r;
   }
   std::vector<Block> blocks;

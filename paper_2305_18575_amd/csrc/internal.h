@@ -151,7 +151,16 @@ struct ChunkArgs {
   uint32_t cost;              // level being built
   uint64_t chunk_e0;          // level enumeration index of chunk-relative 0
   uint64_t len;               // candidates in the chunk
+  // host-visible mirrors of *st and of the three per-level counters (same
+  // layout: lcount, uniq, cand, nlev each), written with them
+  DevState* hst;
+  uint64_t* hlev;
+  uint64_t nlev;
+  uint32_t clear_words;       // bitmap words insert_survivors clears (the grid finalize path)
 };
+// Whether a chunk is finalized by one workgroup (else by the grid kernels,
+// which need the bitmap cleared by insert_survivors).
+bool finalize_in_one_workgroup(int W, uint64_t len);
 
 // Events of this thread's next timed kernel launch (set by the library's
 // profiler).  launch_timed hands them to the launch itself, which records

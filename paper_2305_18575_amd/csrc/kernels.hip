@@ -515,6 +515,9 @@ __global__ __launch_bounds__(256) void rehash_rows(const uint64_t* rows, uint64_
 template <int W, bool kInl>
 __global__ __launch_bounds__(256) void insert_survivors(ChunkArgs a) {
   if (a.st->stop) return;
+  // the winner bitmap of the grid finalize path starts empty
+  for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < a.clear_words; w += gridDim.x * blockDim.x)
+    a.bitmap[w] = 0;
   const uint32_t ns = a.ctrl->n_surv;
   for (uint32_t sid = blockIdx.x * blockDim.x + threadIdx.x; sid < ns; sid += gridDim.x * blockDim.x) {
     uint64_t key[W];
@@ -589,6 +592,19 @@ __device__ void account_chunk(const ChunkArgs& a, uint32_t ans, uint32_t answer_
   st->total_rows += stored;
   a.lcount[c] += stored;
   ctrl_clear(a.ctrl);
+  // the host reads these at level boundaries without a copy
+  DevState* h = a.hst;
+  h->total_rows = st->total_rows;
+  h->row_cap = st->row_cap;
+  h->stop = st->stop;
+  h->answer_cost = st->answer_cost;
+  h->answer_e = st->answer_e;
+  h->resume_level = st->resume_level;
+  h->otf_on = st->otf_on;
+  h->otf = st->otf;
+  a.hlev[c] = a.lcount[c];
+  a.hlev[a.nlev + c] = a.uniq[c];
+  a.hlev[2 * a.nlev + c] = a.cand[c];
 }
 
 template <int W, bool kInl>
@@ -1073,15 +1089,19 @@ hipError_t launch_insert(int W, const ChunkArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(int W, const ChunkArgs& a, hipStream_t s) {
+bool finalize_in_one_workgroup(int W, uint64_t len) {
   // one workgroup moves at most kSmallCopyWords words of rows: a chunk
   // with more is finalized by the grid kernels, spread over the device
-  if (a.len <= kSmallChunk && a.len * (uint64_t)W <= kSmallCopyWords) {
+  return len <= kSmallChunk && len * (uint64_t)W <= kSmallCopyWords;
+}
+
+hipError_t launch_finalize(int W, const ChunkArgs& a, hipStream_t s) {
+  if (finalize_in_one_workgroup(W, a.len)) {
     REI_DISPATCH_WI(W, a.inl, hipLaunchKernelGGL((finalize_small<kW, kI>), dim3(1), dim3(1024), 0, s, a));
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(fill_u32, dim3(grid_for(a.n_bitmap_words, 256, 4096)), dim3(256), 0, s, a.bitmap,
-                     (uint64_t)a.n_bitmap_words, 0u);
+  // the bitmap was cleared by insert_survivors
+  if (a.clear_words != a.n_bitmap_words) return hipErrorInvalidValue;
   const uint32_t g = grid_for(a.len, 256, 8192);
   if (a.inl)
     hipLaunchKernelGGL(mark_winners<true>, dim3(g), dim3(256), 0, s, a);
