@@ -216,7 +216,8 @@ void rei_batch_graph_destroy(rei_batch_graph *g);
  * whose measured work (candidates, weighted by words per language) exceeds
  * twice the average per resident workgroup (and 10^5), which would decide a
  * replay's length alone on one workgroup, and those with a level larger
- * than rei_solve_batch's hand-off size (tuned, else 2^16 candidates). */
+ * than rei_solve_batch's hand-off size (tuned per word width, else 2^16
+ * candidates). */
 size_t rei_batch_graph_outside(const rei_batch_graph *g);
 
 /* Autotuner of rei_solve_batch, by whole calls (what the caller waits for,
@@ -227,16 +228,20 @@ size_t rei_batch_graph_outside(const rei_batch_graph *g);
  * is kept, for each group present, for groups of its size (by power-of-two
  * size class) in a table of the process that later rei_solve_batch calls on
  * any thread use.  Without an entry, a group gets enough waves per instance
- * to fill the device's wave slots.  Then the hand-off level size (for
- * instances that did not set rei_set_batch_level): 2^13 .. 2^19 candidates,
- * the fastest becomes the process default (2^16 until then).  Other
- * rei_solve_batch calls running meanwhile also take the shape being timed.
- * Results do not depend on either choice.  threads_out (NULL or 7 entries,
- * for W = 1 with keys in the table slots, then W = 1, 2, 4, 8, 16, 32)
- * receives the
- * chosen sizes, 0 for groups without instances; level_max_out (NULL or 1
- * entry) the level size.  The instances end up solved, as by
- * rei_solve_batch. */
+ * to fill the device's wave slots.  Then the hand-off level size per group
+ * present (for instances that did not set rei_set_batch_level), widest group
+ * first with the others at their current value: 0 (the group's instances
+ * take rei_solve's path from the start; tried only for groups of at most 8
+ * instances, as many as run on that path at once), 2^8, 2^10, 2^12, then
+ * 2^13 .. 2^19 candidates; a size replaces the group's current one (2^16
+ * until tuned) only if it is at least 3 % faster, and becomes the process
+ * default for that word width.  Other rei_solve_batch calls running meanwhile also
+ * take the setting being timed.  Results do not depend on either choice.
+ * threads_out (NULL or 7 entries, for W = 1 with keys in the table slots,
+ * then W = 1, 2, 4, 8, 16, 32) receives the chosen sizes, 0 for groups
+ * without instances; level_max_out (NULL or 7 entries, same order) the
+ * chosen level sizes, UINT64_MAX for groups without instances.  The
+ * instances end up solved, as by rei_solve_batch. */
 rei_status rei_tune_batch(rei_instance *const *insts, size_t n, void *hip_stream, uint64_t arena_bytes,
                           uint32_t *threads_out, uint64_t *level_max_out);
 
@@ -361,8 +366,9 @@ rei_status rei_row_regex(rei_instance *inst, uint32_t cost, uint64_t i, char *bu
  * do not depend on it; tests vary it to check that. */
 rei_status rei_set_chunk(rei_instance *inst, uint64_t max_candidates);
 /* Largest level, in candidates, that rei_solve_batch searches inside its
- * one-workgroup solver (0 = the process default: 2^16, or what
- * rei_tune_batch chose).  At a larger level the instance,
+ * one-workgroup solver (0 = the process default for the instance's word
+ * width: 2^16, or what rei_tune_batch chose, where 0 means rei_solve's path
+ * from the start).  At a larger level the instance,
  * with every lower level kept, continues on rei_solve's path.  Results do not
  * depend on it. */
 rei_status rei_set_batch_level(rei_instance *inst, uint64_t max_candidates);

@@ -382,22 +382,24 @@ def solve_batch_noalloc(instances: Sequence["Instance"], stream: Optional[int] =
 def tune_batch(instances: Sequence["Instance"], stream: Optional[int] = -1,
                arena_bytes: int = 0) -> dict:
     """``rei_tune_batch``: pick and remember the fastest workgroup size per
-    word-width group for batches like this one, then the hand-off level size;
-    returns {"threads_per_instance": {group: threads}, "level_max": n}."""
+    word-width group for batches like this one, then each group's hand-off
+    level size (0: rei_solve's path from the start); returns
+    {"threads_per_instance": {group: threads}, "level_max": {group: n}}."""
     lib = load_library()
     if stream == -1:
         stream = current_stream_handle()
     n = len(instances)
     hs = (ctypes.c_void_p * n)(*[i._h for i in instances])
     out = (ctypes.c_uint32 * 7)()
-    lm = ctypes.c_uint64()
-    st = lib.rei_tune_batch(hs, n, ctypes.c_void_p(stream or 0), int(arena_bytes), out, ctypes.byref(lm))
+    lm = (ctypes.c_uint64 * 7)()
+    st = lib.rei_tune_batch(hs, n, ctypes.c_void_p(stream or 0), int(arena_bytes), out, lm)
     if st != 0:
         msg = "; ".join(sorted({lib.rei_last_error(i._h).decode() for i in instances} - {""}))
         raise ReiError(st, msg)
     names = ["W1-inline", "W1", "W2", "W4", "W8", "W16", "W32"]
     shape = {names[k]: int(out[k]) for k in range(7) if out[k]}
-    return {"threads_per_instance": shape, "level_max": int(lm.value)}
+    levels = {names[k]: int(lm[k]) for k in range(7) if lm[k] != (1 << 64) - 1}
+    return {"threads_per_instance": shape, "level_max": levels}
 
 
 def tune_grid(instances: Sequence["Instance"], stream: Optional[int] = -1) -> dict:

@@ -1182,16 +1182,31 @@ std::mutex g_tune_mu;
 std::map<std::pair<int, int>, uint32_t> g_tuned;  // (group, size class) -> threads
 int g_cus = 0;
 
-// Hand-off level size of instances that leave it at the default: the
-// tuner's choice, else kBatchLevelMax.
-std::atomic<uint64_t> g_level_max{0};
+// Hand-off level size of instances that leave it at the default, per word
+// width group (slot 0: one word with keys in the table slots, then 1 + log2
+// W): the tuner's choice + 1, or 0 for none (then kBatchLevelMax).  A size
+// of 0 sends the group's instances to rei_solve's path at once.
+constexpr int kSlots = 7;
+std::atomic<uint64_t> g_level_max[kSlots];
 // Threads per instance forced on every group while the tuner times a shape.
 std::atomic<uint32_t> g_force_threads{0};
 
-uint64_t tuned_level_max() {
-  const uint64_t v = g_level_max.load();
-  return v ? v : kBatchLevelMax;
+int width_slot(int g) { return g == 0 ? 0 : 1 + __builtin_ctz((unsigned)g); }
+int group_of(const rei_instance* in) { return in->inl ? 0 : in->st.W; }
+
+uint64_t tuned_level_max(int slot) {
+  const uint64_t v = g_level_max[slot].load();
+  return v ? v - 1 : kBatchLevelMax;
 }
+
+// The instance's hand-off level size (its own setting, else its group's).
+uint64_t level_max_of(const rei_instance* in) {
+  return in->batch_level_max ? in->batch_level_max : tuned_level_max(width_slot(group_of(in)));
+}
+
+// Whether rei_solve_batch (and the server) start the instance in the
+// one-workgroup solver: it fits there, and its hand-off size is not 0.
+bool batch_path(const rei_instance* in) { return batchable(in) && level_max_of(in) > 0; }
 
 int size_class(size_t n) {
   int k = 0;
@@ -1275,7 +1290,7 @@ BatchDesc make_desc(const rei_instance* in) {
   d.slots = in->d_slots;
   d.sref = in->d_sref;
   d.inl = in->inl ? 1u : 0u;
-  d.level_max = in->batch_level_max ? in->batch_level_max : tuned_level_max();
+  d.level_max = level_max_of(in);
   const int64_t us = in->batch_time_us < 0 ? kBatchTimeUs : in->batch_time_us;
   d.time_ticks = us ? (uint64_t)us * wall_ticks_per_us(in->device) : 0;
   d.slot_mask = in->slots_cap - 1;
@@ -1312,7 +1327,7 @@ rei_status batch_launch(rei_instance* const* insts, size_t n, hipStream_t s, uin
       run->finished.push_back(in);
       continue;
     }
-    if (!batchable(in)) {
+    if (!batch_path(in)) {
       run->grid.push_back(in);
       continue;
     }
@@ -1451,6 +1466,8 @@ rei_status batch_collect(BatchRun* run, const std::vector<rei_instance*>* taken 
   return REI_OK;
 }
 
+constexpr int kGridWorkers = 8;
+
 // Worker threads that run the per-chunk path for instances handed to them
 // while a batched launch still runs: 8 threads for the whole process, each
 // driving its own pooled stream per device, started on first use and kept
@@ -1487,7 +1504,7 @@ class Workers {
   }
 
  private:
-  static constexpr int kThreads = 8;
+  static constexpr int kThreads = kGridWorkers;
   struct Job {
     Group* g;
     rei_instance* in;
@@ -1647,7 +1664,7 @@ rei_status create_device(rei_instance* in) {
 }
 
 // Reads a tuning file as rei_tune_save writes it: objects of integer
-// fields under "batch_threads" and "grid", and "batch_level_max".  Entries
+// fields under "batch_threads", "batch_level_max" and "grid".  Entries
 // with values out of range are rejected as a whole (nothing is applied).
 bool tune_parse(const std::string& text) {
   auto section = [&](const char* key, std::string* out) -> bool {
@@ -1682,7 +1699,7 @@ bool tune_parse(const std::string& text) {
   };
   std::map<std::pair<int, int>, uint32_t> bt;
   std::map<int, GridTune> gr;
-  uint64_t lm = 0;
+  uint64_t lm[kSlots] = {0};
   std::string arr;
   if (section("batch_threads", &arr))
     for (const std::string& o : objects(arr)) {
@@ -1704,14 +1721,13 @@ bool tune_parse(const std::string& text) {
         return false;
       gr[(int)w] = GridTune{fc, cm, (uint32_t)wg, (uint32_t)xi};
     }
-  {
-    const size_t k = text.find("\"batch_level_max\"");
-    if (k != std::string::npos) {
-      size_t c = text.find(':', k);
-      if (c == std::string::npos) return false;
-      lm = std::strtoull(text.c_str() + c + 1, nullptr, 10);
+  if (section("batch_level_max", &arr))
+    for (const std::string& o : objects(arr)) {
+      uint64_t g = 0, v = 0;
+      if (!field(o, "group", &g) || !field(o, "level_max", &v)) return false;
+      if (g > (uint64_t)kBatchMaxW || (g & (g - 1)) || v > (1ull << 40)) return false;
+      lm[width_slot((int)g)] = v + 1;
     }
-  }
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (auto& kv : bt) g_tuned[kv.first] = kv.second;
@@ -1720,7 +1736,8 @@ bool tune_parse(const std::string& text) {
     std::lock_guard<std::mutex> lk(g_grid_mu);
     for (auto& kv : gr) g_grid_tuned[kv.first] = kv.second;
   }
-  if (lm) g_level_max.store(lm);
+  for (int k = 0; k < kSlots; ++k)
+    if (lm[k]) g_level_max[k].store(lm[k]);
   return true;
 }
 
@@ -2063,34 +2080,50 @@ rei_status rei_tune_batch(rei_instance* const* insts, size_t n, void* hip_stream
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
       for (int g = 0; g <= kBatchMaxW; g = g ? 2 * g : 1) {
-        const int slot = g == 0 ? 0 : 1 + __builtin_ctz((unsigned)g);  // W1-inline, W1, W2, W4, ..., W32
+        const int slot = width_slot(g);  // W1-inline, W1, W2, W4, ..., W32
         const uint32_t t = group_n[g] ? std::min(cand[bq], max_threads(g)) : 0u;
         if (t) g_tuned[{g, size_class(group_n[g])}] = t;
         if (threads_out) threads_out[slot] = t;
       }
     }
-    // Hand-off level size (instances left at the default): whole calls with
-    // the shape just chosen, 2^13 .. 2^19, the shortest wins.
-    double best_s = 1e300;
-    uint64_t best_l = kBatchLevelMax;
-    for (int k = 13; k <= 19; ++k) {
-      g_level_max.store(1ull << k);
-      double t = 1e300;
-      if ((r = time_calls(&t)) != REI_OK) {
-        g_level_max.store(0);
-        return r;
+    // Hand-off level size per group present (instances left at the
+    // default), widest group first, the others at their current choice:
+    // whole calls with the shape just chosen.  Sizes: 0 (the group's
+    // instances take rei_solve's path from the start; only for a group no
+    // larger than the worker pool, which runs that many at once), 2^8, 2^10,
+    // 2^12, then 2^13 .. 2^19.  A size replaces the current one only if it
+    // is at least 3 % faster (timing noise must not move a group).
+    static const uint64_t sizes[] = {0, 1u << 8, 1u << 10, 1u << 12, 1u << 13, 1u << 14, 1u << 15,
+                                     1u << 16, 1u << 17, 1u << 18, 1u << 19};
+    if (level_max_out) std::fill(level_max_out, level_max_out + kSlots, ~0ull);
+    for (int g = kBatchMaxW; g >= 0; g = g > 1 ? g / 2 : g - 1) {
+      if (!group_n[g]) continue;
+      const int slot = width_slot(g);
+      const uint64_t keep = g_level_max[slot].load();
+      uint64_t best_l = tuned_level_max(slot);
+      double best_s = 1e300;
+      auto timed = [&](uint64_t l, double* t) -> rei_status {
+        g_level_max[slot].store(l + 1);
+        rei_status st = time_calls(t);
+        if (st != REI_OK) g_level_max[slot].store(keep);
+        return st;
+      };
+      if ((r = timed(best_l, &best_s)) != REI_OK) return r;
+      for (uint64_t l : sizes) {
+        if (l == best_l || (l == 0 && group_n[g] > (size_t)kGridWorkers)) continue;
+        double t = 1e300;
+        if ((r = timed(l, &t)) != REI_OK) return r;
+        if (t < 0.97 * best_s) {
+          best_s = t;
+          best_l = l;
+        }
       }
-      if (t < best_s) {
-        best_s = t;
-        best_l = 1ull << k;
-      }
+      g_level_max[slot].store(best_l + 1);
+      if (level_max_out) level_max_out[slot] = best_l;
     }
-    g_level_max.store(best_l);
-    if (level_max_out) *level_max_out = best_l;
     return REI_OK;
   } catch (const std::bad_alloc&) {
     g_force_threads.store(0);
-    g_level_max.store(0);
     return REI_ERR_HOST_ALLOC;
   }
 }
@@ -2200,7 +2233,18 @@ rei_status rei_tune_save(const char* path) {
       first = false;
     }
   }
-  js += "\n  ],\n  \"batch_level_max\": " + std::to_string(g_level_max.load()) + ",\n  \"grid\": [";
+  js += "\n  ],\n  \"batch_level_max\": [";
+  {
+    bool first = true;
+    for (int g = 0; g <= kBatchMaxW; g = g ? 2 * g : 1) {
+      const uint64_t v = g_level_max[width_slot(g)].load();
+      if (!v) continue;
+      js += std::string(first ? "" : ",") + "\n    {\"group\": " + std::to_string(g) +
+            ", \"level_max\": " + std::to_string(v - 1) + "}";
+      first = false;
+    }
+  }
+  js += "\n  ],\n  \"grid\": [";
   {
     std::lock_guard<std::mutex> lk(g_grid_mu);
     bool first = true;
@@ -2657,7 +2701,7 @@ rei_status queue_launch(rei_server* sv, int slot, rei_instance* in) {
 }
 
 uint64_t request_reserve(const rei_server* sv, const rei_instance* in) {
-  uint64_t b = batchable(in) ? batch_reserve(in, sv->arena)
+  uint64_t b = batch_path(in) ? batch_reserve(in, sv->arena)
                              : in->cache_bytes + pow2_at_least(4 * (in->row_cap + 1)) * 8;
   return std::min(b, sv->budget);
 }
@@ -2754,7 +2798,7 @@ void server_sched_queue(rei_server* sv) {
       if (sv->in_use + rq.reserve > sv->budget) break;
       sv->in_use += rq.reserve;
       sv->queue.pop_front();
-      if (batchable(rq.in)) {
+      if (batch_path(rq.in)) {
         adm.push_back({t, rq.in, rq.t_submit, false, REI_OK});
       } else {
         sv->grid_queue.push_back(t);
@@ -2903,7 +2947,7 @@ void server_sched(rei_server* sv) {
       const uint64_t t = sv->queue.front();
       auto& q = sv->reqs[t];
       if (sv->in_use + q.reserve > sv->budget) break;
-      if (batchable(q.in)) {
+      if (batch_path(q.in)) {
         if (free_stream < 0 || take.size() >= sv->max_batch) break;
         take.push_back(t);
       } else {
@@ -3248,7 +3292,7 @@ rei_status rei_batch_graph_create(rei_instance* const* insts, size_t n, uint64_t
         return REI_ERR_INVALID_ARG;
       }
       if (begin_solve(in, t0)) continue;  // trivial: answered at results time
-      if (!batchable(in)) {
+      if (!batch_path(in)) {
         g->other.push_back(in);
         continue;
       }
@@ -3349,12 +3393,11 @@ rei_status rei_batch_graph_create(rei_instance* const* insts, size_t n, uint64_t
     // level by the whole device: either leaves the graph and runs
     // rei_solve's path on the worker threads while each replay runs.
     const double heavy = 2.0 * all_work / std::max(1.0, resident);
-    const uint64_t level_cap = tuned_level_max();
     bool moved = false;
     for (int w = 0; w <= kBatchMaxW; w = w ? 2 * w : 1) {
       auto& m = members[w];
       for (auto it = m.begin(); it != m.end();) {
-        if ((work_of[*it] > heavy && work_of[*it] > kGraphHeavyMin) || widest_of[*it] > level_cap) {
+        if ((work_of[*it] > heavy && work_of[*it] > kGraphHeavyMin) || widest_of[*it] > level_max_of(*it)) {
           g->other.push_back(*it);
           it = m.erase(it);
           moved = true;

@@ -108,7 +108,7 @@ def test_tuning_file_round_trip(tmp_path):
     device work); a file with an entry out of range is rejected whole."""
     good = tmp_path / "tune.json"
     good.write_text('{"batch_threads": [{"group": 16, "size_class": 2, "threads": 512}],\n'
-                    ' "batch_level_max": 32768,\n'
+                    ' "batch_level_max": [{"group": 16, "level_max": 32768}, {"group": 2, "level_max": 0}],\n'
                     ' "grid": [{"words": 16, "first_chunk": 16384, "chunk_max": 4194304, '
                     '"concat_wg": 4096, "concat_xi": 8}]}\n')
     rei.tune_load(str(good))
@@ -117,7 +117,8 @@ def test_tuning_file_round_trip(tmp_path):
     import json
     saved = json.loads(out.read_text())
     assert {"group": 16, "size_class": 2, "threads": 512} in saved["batch_threads"]
-    assert saved["batch_level_max"] == 32768
+    assert {"group": 16, "level_max": 32768} in saved["batch_level_max"]
+    assert {"group": 2, "level_max": 0} in saved["batch_level_max"]
     assert {"words": 16, "first_chunk": 16384, "chunk_max": 4194304, "concat_wg": 4096,
             "concat_xi": 8} in saved["grid"]
     bad = tmp_path / "bad.json"
@@ -125,6 +126,9 @@ def test_tuning_file_round_trip(tmp_path):
     with pytest.raises(rei.ReiError):
         rei.tune_load(str(bad))
     bad.write_text('{"batch_threads": [{"group": 32, "size_class": 1, "threads": 1024}]}')
+    with pytest.raises(rei.ReiError):
+        rei.tune_load(str(bad))
+    bad.write_text('{"batch_level_max": [{"group": 3, "level_max": 4096}]}')
     with pytest.raises(rei.ReiError):
         rei.tune_load(str(bad))
     with pytest.raises(rei.ReiError):
