@@ -228,15 +228,15 @@ size_t rei_batch_graph_outside(const rei_batch_graph *g);
  * is kept, for each group present, for groups of its size (by power-of-two
  * size class) in a table of the process that later rei_solve_batch calls on
  * any thread use.  Without an entry, a group gets enough waves per instance
- * to fill the device's wave slots.  Then the hand-off level size per group
- * present (for instances that did not set rei_set_batch_level), widest group
- * first with the others at their current value: 0 (the group's instances
- * take rei_solve's path from the start; tried only for groups of at most 8
- * instances, as many as run on that path at once), 2^8, 2^10, 2^12, then
- * 2^13 .. 2^19 candidates; a size replaces the group's current one (2^16
- * until tuned) only if it is at least 3 % faster, and becomes the process
- * default for that word width.  Other rei_solve_batch calls running meanwhile also
- * take the setting being timed.  Results do not depend on either choice.
+ * to fill the device's wave slots.  Then the hand-off level size (for
+ * instances that did not set rei_set_batch_level): one size for every group
+ * present, 2^8, 2^10, 2^12, then 2^13 .. 2^19 candidates, the fastest kept;
+ * then, widest first, each group of at most 8 instances (as many as run on
+ * rei_solve's path at once) tries 0, its instances taking rei_solve's path
+ * from the start, kept only if at least 3 % faster.  The sizes become the
+ * process defaults per word width (2^16 until tuned).  Other
+ * rei_solve_batch calls running meanwhile also take the setting being
+ * timed.  Results do not depend on either choice.
  * threads_out (NULL or 7 entries, for W = 1 with keys in the table slots,
  * then W = 1, 2, 4, 8, 16, 32) receives the chosen sizes, 0 for groups
  * without instances; level_max_out (NULL or 7 entries, same order) the

@@ -2086,40 +2086,56 @@ rei_status rei_tune_batch(rei_instance* const* insts, size_t n, void* hip_stream
         if (threads_out) threads_out[slot] = t;
       }
     }
-    // Hand-off level size per group present (instances left at the
-    // default), widest group first, the others at their current choice:
-    // whole calls with the shape just chosen.  Sizes: 0 (the group's
-    // instances take rei_solve's path from the start; only for a group no
-    // larger than the worker pool, which runs that many at once), 2^8, 2^10,
-    // 2^12, then 2^13 .. 2^19.  A size replaces the current one only if it
-    // is at least 3 % faster (timing noise must not move a group).
-    static const uint64_t sizes[] = {0, 1u << 8, 1u << 10, 1u << 12, 1u << 13, 1u << 14, 1u << 15,
+    // Hand-off level size (instances left at the default), whole calls with
+    // the shape just chosen.  First one size for every group present: 2^8,
+    // 2^10, 2^12, then 2^13 .. 2^19, the shortest wins.  Then, widest group
+    // first, each group no larger than the worker pool (which runs that many
+    // at once) tries 0: its instances take rei_solve's path from the start;
+    // kept only if at least 3 % faster (timing noise must not move a group).
+    static const uint64_t sizes[] = {1u << 8, 1u << 10, 1u << 12, 1u << 13, 1u << 14, 1u << 15,
                                      1u << 16, 1u << 17, 1u << 18, 1u << 19};
-    if (level_max_out) std::fill(level_max_out, level_max_out + kSlots, ~0ull);
-    for (int g = kBatchMaxW; g >= 0; g = g > 1 ? g / 2 : g - 1) {
-      if (!group_n[g]) continue;
-      const int slot = width_slot(g);
-      const uint64_t keep = g_level_max[slot].load();
-      uint64_t best_l = tuned_level_max(slot);
-      double best_s = 1e300;
-      auto timed = [&](uint64_t l, double* t) -> rei_status {
-        g_level_max[slot].store(l + 1);
-        rei_status st = time_calls(t);
-        if (st != REI_OK) g_level_max[slot].store(keep);
-        return st;
-      };
-      if ((r = timed(best_l, &best_s)) != REI_OK) return r;
-      for (uint64_t l : sizes) {
-        if (l == best_l || (l == 0 && group_n[g] > (size_t)kGridWorkers)) continue;
-        double t = 1e300;
-        if ((r = timed(l, &t)) != REI_OK) return r;
-        if (t < 0.97 * best_s) {
-          best_s = t;
-          best_l = l;
-        }
+    uint64_t keep[kSlots];
+    for (int k = 0; k < kSlots; ++k) keep[k] = g_level_max[k].load();
+    auto set_all = [&](uint64_t l) {
+      for (int g = 0; g <= kBatchMaxW; g = g ? 2 * g : 1)
+        if (group_n[g]) g_level_max[width_slot(g)].store(l + 1);
+    };
+    auto restore = [&] {
+      for (int k = 0; k < kSlots; ++k) g_level_max[k].store(keep[k]);
+    };
+    double best_s = 1e300;
+    uint64_t best_l = kBatchLevelMax;
+    for (uint64_t l : sizes) {
+      set_all(l);
+      double t = 1e300;
+      if ((r = time_calls(&t)) != REI_OK) {
+        restore();
+        return r;
       }
-      g_level_max[slot].store(best_l + 1);
-      if (level_max_out) level_max_out[slot] = best_l;
+      if (t < best_s) {
+        best_s = t;
+        best_l = l;
+      }
+    }
+    set_all(best_l);
+    for (int g = kBatchMaxW; g >= 0; g = g > 1 ? g / 2 : g - 1) {
+      if (!group_n[g] || group_n[g] > (size_t)kGridWorkers) continue;
+      const int slot = width_slot(g);
+      g_level_max[slot].store(0 + 1);
+      double t = 1e300;
+      if ((r = time_calls(&t)) != REI_OK) {
+        restore();
+        return r;
+      }
+      if (t < 0.97 * best_s)
+        best_s = t;
+      else
+        g_level_max[slot].store(best_l + 1);
+    }
+    if (level_max_out) {
+      std::fill(level_max_out, level_max_out + kSlots, ~0ull);
+      for (int g = 0; g <= kBatchMaxW; g = g ? 2 * g : 1)
+        if (group_n[g]) level_max_out[width_slot(g)] = tuned_level_max(width_slot(g));
     }
     return REI_OK;
   } catch (const std::bad_alloc&) {

@@ -492,6 +492,7 @@ def test_tuned_launch_shapes_give_identical_results(rei):
     assert shape and all(t in (256, 512, 1024) for t in shape.values())
     assert set(tuned["level_max"]) == set(shape)
     assert all(v in (0, 1 << 8, 1 << 10) or 1 << 12 <= v <= 1 << 19 for v in tuned["level_max"].values())
+    assert len({v for v in tuned["level_max"].values() if v}) <= 1  # one size, or 0 for small groups
     after = rei.solve_batch(hs)
     key = lambda r: (r.status, r.cost, r.regex, r.unique, r.candidates)
     assert [key(r) for r in before] == [key(r) for r in after]
