@@ -141,6 +141,7 @@ struct rei_instance {
   uint32_t otf_level = 0;
   bool otf_blocked = false;
   uint64_t pending = 0;
+  uint32_t chunks_enq = 0;  // chunks enqueued on the per-chunk path since the state was reset
 
   // levels, indexed by cost
   std::vector<uint64_t> lstart, lcount;
@@ -448,10 +449,25 @@ bool make_blocks(const rei_instance* in, uint32_t c, std::vector<Block>* out, bo
   return true;
 }
 
-// Waits for the stream; the search state is then in the host mirrors
-// (h_state, h_levels), which every kernel that advances it writes as well.
+// Waits until every chunk enqueued so far is accounted; the search state is
+// then in the host mirrors (h_state, h_levels), which the accounting writes
+// with the device state, its chunk count last.  The host watches that count
+// (a few microseconds sooner than the stream's completion) for at most
+// kSpinUs; a search that stopped (whose later chunks account nothing), or
+// one still running then, waits for the stream.
+constexpr double kSpinUs = 2000;
 rei_status sync_state(rei_instance* in, hipStream_t s) {
-  HIP_OK(in, hipStreamSynchronize(s));
+  const double t0 = now_s();
+  bool seen = false;
+  for (;;) {
+    const uint32_t got = __atomic_load_n(&in->h_state->chunks, __ATOMIC_ACQUIRE);
+    if (got == in->chunks_enq && !__atomic_load_n(&in->h_state->stop, __ATOMIC_ACQUIRE)) {
+      seen = true;
+      break;
+    }
+    if (__atomic_load_n(&in->h_state->stop, __ATOMIC_ACQUIRE) || (now_s() - t0) * 1e6 > kSpinUs) break;
+  }
+  if (!seen) HIP_OK(in, hipStreamSynchronize(s));
   in->known_rows = in->h_state->total_rows;
   in->pending = 0;
   return REI_OK;
@@ -667,10 +683,12 @@ rei_status enqueue_chunk(rei_instance* in, hipStream_t s, uint32_t c, const std:
   ca.clear_words = finalize_in_one_workgroup(W, len) ? 0u : (uint32_t)words;
   if (otf_level) {
     LAUNCH(in, s, REI_K_COMPACT, len, launch_account(ca, s));
+    ++in->chunks_enq;
     return REI_OK;
   }
   LAUNCH(in, s, REI_K_INSERT, len, launch_insert(W, ca, s));
   LAUNCH(in, s, REI_K_COMPACT, len, launch_finalize(W, ca, s));
+  ++in->chunks_enq;
   in->pending += len;
   return REI_OK;
 }
@@ -961,6 +979,7 @@ rei_status search_levels(rei_instance* in, hipStream_t s) {
   in->otf_level = 0;
   in->otf_blocked = false;
   LAUNCH(in, s, REI_K_OTHER, 1, launch_state_reset(in->d_ctrl, in->d_state, in->row_cap, in->otf_on, s));
+  in->chunks_enq = 0;
   if (c_from > c1) {
     // The batched solver stored every level below c_from (rows and
     // back-pointers) and wrote its state and counters to the pinned mirrors:
@@ -983,6 +1002,7 @@ rei_status search_levels(rei_instance* in, hipStream_t s) {
     hs->answer_cost = 0;
     hs->answer_e = 0;
     hs->resume_level = 0;
+    hs->chunks = 0;
     HIP_OK(in, hipMemcpyAsync(in->d_state, hs, sizeof(DevState), hipMemcpyHostToDevice, s));
     HIP_OK(in, hipMemcpyAsync(in->d_levels, in->h_levels, 3 * L * 8, hipMemcpyHostToDevice, s));
     // the batched solver used a prefix of the table: rebuild it at full size
@@ -1004,6 +1024,7 @@ rei_status search_levels(rei_instance* in, hipStream_t s) {
     hs->resume_level = 0;
     hs->otf_on = in->otf_on ? 1u : 0u;
     hs->otf = 0;
+    hs->chunks = 0;
     if ((r = ensure_table(in, 1024, s, true)) != REI_OK) return r;
   }
   std::vector<Block> blocks;

@@ -77,7 +77,7 @@ struct DevState {
   uint32_t otf_on;          // OnTheFly mode allowed when the cache fills
   uint32_t otf;             // OnTheFly mode active: no storage, precision only
   uint32_t done;            // batched solver: set last, once this state is final
-  uint32_t pad32;
+  uint32_t chunks;          // per-chunk path: chunks accounted (the host mirror's is written last)
   uint64_t pad[1];
 };
 

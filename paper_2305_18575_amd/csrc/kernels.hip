@@ -498,6 +498,7 @@ __global__ void state_reset(Ctrl* c, DevState* st, uint64_t row_cap, uint32_t ot
   st->resume_level = 0;
   st->otf_on = otf_on;
   st->otf = 0;
+  st->chunks = 0;
 }
 
 template <int W, bool kInl>
@@ -605,6 +606,9 @@ __device__ void account_chunk(const ChunkArgs& a, uint32_t ans, uint32_t answer_
   a.hlev[c] = a.lcount[c];
   a.hlev[a.nlev + c] = a.uniq[c];
   a.hlev[2 * a.nlev + c] = a.cand[c];
+  // the count last: a host that sees it sees everything above
+  st->chunks += 1;
+  __hip_atomic_store(&h->chunks, st->chunks, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 template <int W, bool kInl>
