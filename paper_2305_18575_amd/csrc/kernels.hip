@@ -113,7 +113,6 @@ __global__ __launch_bounds__(256) void gen_star(GenArgs a) {
 // (Algorithm 2, the fold over the guide table, done for 64 candidates at once).
 // A wave transpose then gives lane t the W words of candidate (x, y_t).
 constexpr int kConcatYT = 8;
-constexpr uint64_t kConcatWideWaves = 256 * 8;  // waves below which the cut-outer fold is used
 
 // kShort: every word has at most 32 cuts (length <= 31), so the cuts whose
 // prefix is in x fit one 32-bit mask per output word; otherwise the prefix
@@ -122,12 +121,7 @@ constexpr uint64_t kConcatWideWaves = 256 * 8;  // waves below which the cut-out
 // time so that every access has a fixed address space: reading LDS through a
 // generic pointer (chosen at run time between LDS and global memory) gave
 // wrong prefix bits now and then on gfx950.
-// kWide (with kShort): the prefix masks and the fold visit cut position q
-// in the outer loop and the lane's W words inside, every word's read issued
-// each round (clamped to its last cut, masked after), so W independent LDS
-// reads are in flight per round instead of one: fewer rounds of latency
-// for small launches, more LDS instructions for large ones.
-template <int W, bool kShort, bool kInl, bool kGtLds, bool kWide>
+template <int W, bool kShort, bool kInl, bool kGtLds>
 __global__ __launch_bounds__(256) void gen_concat(GenArgs a, ConcatSet cs) {
   extern __shared__ uint64_t lds[];
   if (a.st->stop) return;
@@ -194,32 +188,13 @@ __global__ __launch_bounds__(256) void gen_concat(GenArgs a, ConcatSet cs) {
     off[k] = (w < a.n) ? a.gt_off[w] : 0u;
     cnt[k] = (w < a.n) ? a.gt_off[w + 1] - off[k] : 0u;
   }
-  // kWide: most cuts of any word (every word of ic has at most max_len + 1)
-  // and each word's last cut (a word beyond ic reads cut 0 of word 0)
-  const uint32_t qn = a.max_len + 1;
-  uint32_t last[W];
-#pragma unroll
-  for (int k = 0; k < W; ++k) last[k] = off[k] + (cnt[k] ? cnt[k] - 1 : 0u);
 
   for (uint32_t xi = wave; xi < nx; xi += 4) {
     const uint64_t i = x0 + xi;
     const uint64_t* xr = Xs + (size_t)xi * W;
     // bit q of m[k]: x contains the prefix of cut q of word 64k+lane
     uint32_t m[W];
-    if constexpr (kShort && kWide) {
-#pragma unroll
-      for (int k = 0; k < W; ++k) m[k] = 0;
-      for (uint32_t q = 0; q < qn; ++q) {
-        uint32_t u[W];
-#pragma unroll
-        for (int k = 0; k < W; ++k) u[k] = gp[min(off[k] + q, last[k])] >> 16;
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-          const uint32_t bit = (uint32_t)((xr[u[k] >> 6] >> (u[k] & 63)) & 1ull);
-          m[k] |= (q < cnt[k] ? bit : 0u) << q;
-        }
-      }
-    } else if constexpr (kShort) {
+    if constexpr (kShort) {
 #pragma unroll
       for (int k = 0; k < W; ++k) {
         uint32_t mm = 0;
@@ -238,23 +213,6 @@ __global__ __launch_bounds__(256) void gen_concat(GenArgs a, ConcatSet cs) {
     for (uint32_t tq = 0; tq < nt; ++tq) {
       const uint64_t* Y = Yt + (size_t)tq * 64 * W;
       uint64_t key[W];
-      if constexpr (kShort && kWide) {
-        uint64_t acc[W];
-#pragma unroll
-        for (int k = 0; k < W; ++k) acc[k] = 0;
-        for (uint32_t q = 0; q < qn; ++q) {
-          uint32_t v[W];
-#pragma unroll
-          for (int k = 0; k < W; ++k) v[k] = gp[min(off[k] + q, last[k])] & 0xFFFFu;
-#pragma unroll
-          for (int k = 0; k < W; ++k) {
-            const uint64_t y = Y[v[k]];
-            acc[k] |= ((m[k] >> q) & 1u) ? y : 0ull;
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < W; ++k) key[k] = transpose64(acc[k]);
-      } else {
 #pragma unroll
       for (int k = 0; k < W; ++k) {
         uint64_t acc = 0;
@@ -271,7 +229,6 @@ __global__ __launch_bounds__(256) void gen_concat(GenArgs a, ConcatSet cs) {
           }
         }
         key[k] = transpose64(acc);
-      }
       }
       const uint64_t j = (t0 + tq) * 64 + lane;
       const uint64_t e = i * nR + j;
@@ -915,25 +872,14 @@ hipError_t launch_concat_w(const GenArgs& a, ConcatSet cs, hipStream_t s) {
   if (gt_lds) lds += (size_t)a.n_pairs * 4;
   const dim3 grid((uint32_t)wgs_total);
   const bool shrt = a.max_len < 32;
-  // the cut-outer fold for launches with fewer waves than the device holds
-  // at once (latency-bound), the word-outer fold for larger ones
-  static const int wide_mode = [] {
-    const char* e = std::getenv("REI_CONCAT_WIDE");
-    return e ? std::atoi(e) : 0;  // 0 by launch size, 1 never, 2 always
-  }();
-  const bool wide = shrt && (wide_mode == 2 || (wide_mode == 0 && wgs_total * 4 <= kConcatWideWaves));
-  if (wide && gt_lds)
-    launch_timed(gen_concat<W, true, kInl, true, true>, grid, dim3(256), lds, s, a, cs);
-  else if (wide)
-    launch_timed(gen_concat<W, true, kInl, false, true>, grid, dim3(256), lds, s, a, cs);
-  else if (shrt && gt_lds)
-    launch_timed(gen_concat<W, true, kInl, true, false>, grid, dim3(256), lds, s, a, cs);
+  if (shrt && gt_lds)
+    launch_timed(gen_concat<W, true, kInl, true>, grid, dim3(256), lds, s, a, cs);
   else if (shrt)
-    launch_timed(gen_concat<W, true, kInl, false, false>, grid, dim3(256), lds, s, a, cs);
+    launch_timed(gen_concat<W, true, kInl, false>, grid, dim3(256), lds, s, a, cs);
   else if (gt_lds)
-    launch_timed(gen_concat<W, false, kInl, true, false>, grid, dim3(256), lds, s, a, cs);
+    launch_timed(gen_concat<W, false, kInl, true>, grid, dim3(256), lds, s, a, cs);
   else
-    launch_timed(gen_concat<W, false, kInl, false, false>, grid, dim3(256), lds, s, a, cs);
+    launch_timed(gen_concat<W, false, kInl, false>, grid, dim3(256), lds, s, a, cs);
   return hipGetLastError();
 }
 
