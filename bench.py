@@ -5,13 +5,16 @@ Default workload (the large configuration): four seeded specifications
 strings of length 0..10 drawn from a target expression of cost 14..18, cost
 function (1,1,1,1,1), searched up to the target's cost with a 200 GB
 language-cache budget.  A step solves the four with one rei_solve_batch call
-on the current stream (specifications with more than 8 words per language
-run the per-chunk grid path, concurrently); the specifications are staged
+on the current stream (word-width groups that the batched solver's tuner
+sends to the per-chunk path run there, concurrently); the specifications are staged
 (rei_create: host staging + upload) before the timed region, so their tables
 are resident in HBM when timing starts.
 
 value = unique languages enumerated in a step (sum over the instances and
-their levels) / wall time of the step, over the timed steps.
+their levels) / wall time of the step, over the timed steps (no timing
+events on any launch).  The dominant kernel class's launch durations come
+from as many steps again, run right after with HIP events on that class's
+launches.
 
 The JSON line also carries, per instance, the per-level unique and candidate
 counts and the time to the minimal expression (rei_create + rei_solve, the
@@ -47,8 +50,8 @@ PROBE_BYTES = 64
 # profiler invocation.  The profile each figure comes from is named beside it.
 # An entry is removed when its kernel changes.
 TRAFFIC = {
-    ("large", "solve_batch"): (2796638, "profiles/large_workload_kernels.md (mean of the 16- and 8-word launches)"),
-    ("row1", "gen_concat"): (311234867, "profiles/table1_row1_kernels.md"),
+    ("large", "gen_pieces"): (3284378, "profiles/large_workload_kernels.md (16-word launches of the timed steps)"),
+    ("row1", "gen_concat"): (369399411, "profiles/table1_row1_kernels.md (launches of the timed steps)"),
 }
 
 
@@ -212,11 +215,15 @@ def timed(step, k):
     return out, time.perf_counter() - t
 
 
-def roofline(rei, handles, insts, dom, peaks, workload_name, max_errors):
-    """Figures of the dominant kernel class over the timed steps (HIP events
-    the library records at each launch's own start and end)."""
+def roofline(rei, handles, insts, dom, peaks, workload_name, max_errors, overhead_us):
+    """Figures of the dominant kernel class over the event steps (HIP events
+    the library records at each of its launches' own start and end)."""
     d = kernel_classes(rei, handles)[dom]
-    avg_s = d["ms"] / max(1, d["launches"]) * 1e-3
+    # the events' own span (an empty kernel's, measured in the same run) is
+    # taken off each launch's: what is left agrees with the kernel trace
+    overhead_s = overhead_us * 1e-6
+    avg_events_s = d["ms"] / max(1, d["launches"]) * 1e-3
+    avg_s = max(avg_events_s - overhead_s, 0.5 * avg_events_s)
     cand = d["units"] / max(1, d["launches"])
     bytes_per_launch = PROBE_BYTES * cand
     achieved = bytes_per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
@@ -225,7 +232,8 @@ def roofline(rei, handles, insts, dom, peaks, workload_name, max_errors):
            "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": tr[0] if tr else None,
            "traffic_source": tr[1] if tr else None,
            "algorithmic_bytes_per_launch": round(bytes_per_launch), "candidates_per_launch": round(cand, 1),
-           "avg_launch_us": round(avg_s * 1e6, 3), "launches": d["launches"],
+           "avg_launch_us": round(avg_s * 1e6, 3), "avg_launch_us_with_events": round(avg_events_s * 1e6, 3),
+           "launches": d["launches"],
            "probes_per_sec": round(cand / avg_s, 1) if avg_s > 0 else 0.0}
     if peaks:
         out["frac_of_measured_copy"] = round(achieved / peaks["copy_GBps"], 4)
@@ -320,6 +328,9 @@ def main():
                     help="time rei_solve per instance as the step instead of rei_solve_batch")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the batched solver's tuning (profiling runs: every launch the same kind)")
+    ap.add_argument("--tune-save", default="",
+                    help="after tuning, write the process's tuning tables to this JSON file (rei_tune_save); "
+                         "a later run with REI_TUNE_FILE set to it and --no-tune repeats the same launch settings")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before timing, copy this many MiB device to device once: a kernel of "
                          "known traffic that calibrates FETCH_SIZE / WRITE_SIZE counter runs")
@@ -378,6 +389,8 @@ def main():
         # the batched solver's threads per instance and hand-off size
         tuned = {"grid": rei.tune_grid(handles[:16], stream)}
         tuned.update(rei.tune_batch(handles, stream))
+        if args.tune_save:
+            rei.tune_save(args.tune_save)
     # Python's cyclic collector scans every object torch created at import;
     # a full pass inside the timed region costs tens of milliseconds that
     # belong to no step.  Objects made so far are moved out of its reach.
@@ -395,8 +408,18 @@ def main():
     gen = {k: v for k, v in classes.items() if k.startswith("gen_") or k == "solve_batch"}
     dom = max(gen, key=lambda k: gen[k]["ms"])
     for h in handles:
-        h.set_profiling_class(dom)
+        h.set_profiling(False)
+    # the events' own cost, measured on an empty kernel (its launches are
+    # the last before the timed steps in a kernel trace of this run)
+    event_overhead_us = rei.timing_overhead_us()
     results, elapsed = timed(step, args.steps)
+    # The dominant class's launch durations: the same number of steps again,
+    # with HIP events that each of its launches records at its own start and
+    # end (on the launch's stream).  Events cost a launch several
+    # microseconds, so the steps that give the headline carry none.
+    for h in handles:
+        h.set_profiling_class(dom)
+    timed(step, args.steps)
     for h in handles:
         h.set_profiling(False)
 
@@ -418,8 +441,8 @@ def main():
                         for it, r in zip(insts, last)]
 
     peaks = None if args.no_peaks else measured_peaks(rei)
-    roof = roofline(rei, handles, insts, dom, peaks, args.workload, args.max_errors)
-    roof["event_overhead_us"] = round(rei.timing_overhead_us(), 3)
+    roof = roofline(rei, handles, insts, dom, peaks, args.workload, args.max_errors, event_overhead_us)
+    roof["event_overhead_us"] = round(event_overhead_us, 3)
     if peaks:
         roof["measured_peaks"] = peaks
 
