@@ -842,3 +842,38 @@ def test_grid_tuner_runs_and_keeps_results(rei, tmp_path):
         g = h.solve()
         assert mismatch(g, o, specs[k].max_cost) is None, (k, mismatch(g, o, specs[k].max_cost))
         h.close()
+
+
+def test_width_sent_to_per_chunk_path_equals_oracle(rei, tmp_path):
+    """A word width whose tuned hand-off size is 0 skips the one-workgroup
+    solver: rei_solve_batch and the server run its instances on the
+    per-chunk path from the start (the tuning file sets it, as rei_tune_batch
+    would); every result equals the oracle's.  The default sizes are put back
+    afterwards."""
+    from paper_2305_18575_amd import serving
+    specs = batch_specs()[::3]
+    hs = [rei.Instance(a, p, n, c, m) for (a, p, n, c, m) in specs]
+    widths = sorted({h.solve().cs_words for h in hs})
+    print(f"\nwidths {widths}, {len(hs)} instances", flush=True)
+    groups = [0] + [w for w in widths]  # group 0: one word with keys in the table slots
+    zero = tmp_path / "zero.json"
+    zero.write_text('{"batch_level_max": [' + ", ".join(f'{{"group": {g}, "level_max": 0}}' for g in groups)
+                    + ']}\n')
+    back = tmp_path / "back.json"
+    back.write_text('{"batch_level_max": [' + ", ".join(f'{{"group": {g}, "level_max": 65536}}' for g in groups)
+                    + ']}\n')
+    rei.tune_load(str(zero))
+    try:
+        got = rei.solve_batch(hs)
+        for r, spec in zip(got, specs):
+            check_against_oracle(r, spec)
+        srv = rei.Server(64 << 30, 64, 2, 2)
+        tickets = [srv.submit(h) for h in hs]
+        served = [srv.wait(t)[0] for t in tickets]
+        srv.close()
+        for k, (a, b) in enumerate(zip(served, got)):
+            assert serving.same(a, b), (k, a, b)
+    finally:
+        rei.tune_load(str(back))
+    for h in hs:
+        h.close()
