@@ -278,148 +278,231 @@ __global__ __launch_bounds__(256) void gen_union(GenArgs a, UnionSet us) {
 // candidates, so a level's small constructor blocks cost one launch.  The
 // constructors are those of the kernels above, at wave scale; the guide
 // table is read through the caches.
-template <int W, bool kInl>
+
+// An item of 64 candidates of a CHAR, QUESTION, UNION or STAR piece (the
+// star with the wave's tiles X and Y): lane t's candidate key.
+template <int W>
+__device__ __forceinline__ void piece_simple(const GenArgs& a, const PieceD& p, uint64_t li, uint32_t lane,
+                                             uint64_t* X, uint64_t* Y, uint64_t (&key)[W], bool* valid,
+                                             bool* dup, uint64_t* e_out) {
+  const uint64_t e = p.e0 + 64 * li + lane;
+  *valid = e < p.e1;
+  *dup = false;
+  *e_out = e;
+  if (p.op == OP_CHAR) {
+    const int idx = *valid ? a.char_index[p.char_off + e] : -1;
+#pragma unroll
+    for (int q = 0; q < W; ++q) key[q] = (idx >= 0 && (idx >> 6) == q) ? (1ull << (idx & 63)) : 0ull;
+  } else if (p.op == OP_QUESTION) {
+    const uint64_t* src = a.rows + (p.lstart + (*valid ? e : 0)) * W;
+#pragma unroll
+    for (int q = 0; q < W; ++q) key[q] = *valid ? src[q] : 0ull;
+    *dup = (key[0] & 1ull) != 0;
+    key[0] |= 1ull;
+  } else if (p.op == OP_UNION) {
+    uint64_t i = 0, j = 0;
+    if (*valid) {
+      if (p.same) {
+        tri_decode(e, p.lcount, &i, &j);
+      } else {
+        i = e / p.rcount;
+        j = e - i * p.rcount;
+      }
+    }
+    const uint64_t* x = a.rows + (p.lstart + i) * W;
+    const uint64_t* y = a.rows + (p.rstart + j) * W;
+    bool eqx = true, eqy = true;
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      const uint64_t xv = *valid ? x[q] : 0ull, yv = *valid ? y[q] : 0ull;
+      key[q] = xv | yv;
+      eqx = eqx && key[q] == xv;
+      eqy = eqy && key[q] == yv;
+    }
+    *dup = eqx || eqy;
+  } else {  // OP_STAR: Y(eps) = 1; by increasing length, Y(w) = OR over
+            // cuts with a non-empty first factor of X(u) & Y(v)
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      X[64 * q + lane] = transpose64(*valid ? a.rows[(p.lstart + e) * W + q] : 0ull);
+      Y[64 * q + lane] = (q == 0 && lane == 0) ? ~0ull : 0ull;
+    }
+    wave_sync_lds();
+    for (uint32_t l = 1; l <= a.max_len; ++l) {
+      const uint32_t lo = a.len_off[l], hi = a.len_off[l + 1];
+      for (uint32_t w = lo + lane; w < hi; w += 64) Y[w] = star_fold(X, Y, a.gt_pair, a.gt_off[w], l);
+      wave_sync_lds();
+    }
+#pragma unroll
+    for (int q = 0; q < W; ++q) key[q] = transpose64(Y[64 * q + lane]);
+  }
+}
+
+// A CONCAT item: its varying operand's rows across the lanes (right rows
+// with one left row, or left rows with one right row when the right level
+// is small), staged transposed in X for words [q_lo, q_hi), the uniform
+// operand's row in U (when stage_u).  Returns lane t's candidate index and
+// whether it is one.
+template <int W>
+__device__ __forceinline__ void concat_stage(const GenArgs& a, const PieceD& p, uint64_t li, uint32_t lane,
+                                             uint64_t* X, uint64_t* U, int q_lo, int q_hi, bool stage_u,
+                                             uint64_t* e_out, bool* valid) {
+  const uint64_t nR = p.rcount, nL = p.lcount;
+  uint64_t i, j, row, urow;
+  bool have;
+  if (!p.left_lanes) {
+    i = p.t0 + li / p.nt;
+    j = 64 * (li % p.nt) + lane;
+    have = j < nR;
+    row = p.rstart + j;
+    urow = p.lstart + i;
+  } else {
+    i = 64 * (p.t0 + li / p.nt) + lane;
+    j = li % p.nt;
+    have = i < nL;
+    row = p.lstart + i;
+    urow = p.rstart + j;
+  }
+#pragma unroll
+  for (int q = 0; q < W; ++q)
+    if (q >= q_lo && q < q_hi) X[64 * q + lane] = transpose64(have ? a.rows[row * W + q] : 0ull);
+  if (stage_u && lane < (uint32_t)W) U[lane] = a.rows[urow * W + lane];
+  const uint64_t e = i * nR + j;
+  *e_out = e;
+  *valid = have && e >= p.e0 && e < p.e1;
+}
+
+// The fold of a CONCAT item for output words [q_lo, q_hi) (X and U staged):
+// key[q] for those q.  From 8 words, cut position outer over eight of the
+// lane's words at a time, 24 independent reads per round (each word's read
+// clamped to its last cut, masked after); below, per word.
+template <int W>
+__device__ __forceinline__ void concat_fold(const GenArgs& a, const PieceD& p, uint32_t lane, const uint64_t* X,
+                                            const uint64_t* U, int q_lo, int q_hi, uint64_t (&key)[W]) {
+  if constexpr (W >= 8) {
+#pragma unroll
+    for (int q0 = 0; q0 < W; q0 += 8) {
+      if (q0 < q_lo || q0 >= q_hi) continue;
+      uint32_t first[8], last[8], cnt[8];
+      uint64_t acc[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const uint32_t w = 64u * (q0 + q) + lane;
+        first[q] = w < a.n ? a.gt_off[w] : 0u;
+        cnt[q] = w < a.n ? a.gt_off[w + 1] - first[q] : 0u;
+        last[q] = first[q] + (cnt[q] ? cnt[q] - 1 : 0u);
+        acc[q] = 0;
+      }
+      for (uint32_t c = 0; c <= a.max_len; ++c) {
+        uint32_t pr[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) pr[q] = a.gt_pair[min(first[q] + c, last[q])];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const uint32_t uu = p.left_lanes ? (pr[q] & 0xFFFFu) : (pr[q] >> 16);  // index into the uniform row
+          const uint32_t tt = p.left_lanes ? (pr[q] >> 16) : (pr[q] & 0xFFFFu);  // index into the tile
+          const uint64_t xv = X[tt];
+          const bool on = c < cnt[q] && ((U[uu >> 6] >> (uu & 63)) & 1ull);
+          acc[q] |= on ? xv : 0ull;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) key[q0 + q] = transpose64(acc[q]);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      if (q < q_lo || q >= q_hi) continue;
+      const uint32_t w = 64u * q + lane;
+      uint64_t acc = 0;
+      if (w < a.n) {
+        const uint32_t q1 = a.gt_off[w + 1];
+        for (uint32_t c = a.gt_off[w]; c < q1; ++c) {
+          const uint32_t pr = a.gt_pair[c];
+          const uint32_t uu = p.left_lanes ? (pr & 0xFFFFu) : (pr >> 16);   // index into the uniform row
+          const uint32_t tt = p.left_lanes ? (pr >> 16) : (pr & 0xFFFFu);   // index into the tile
+          if ((U[uu >> 6] >> (uu & 63)) & 1ull) acc |= X[tt];
+        }
+      }
+      key[q] = transpose64(acc);
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t piece_of(const PieceArgs& pa, uint64_t it) {
+  uint32_t k = 0;
+  while (k + 1 < pa.n && pa.p[k + 1].item0 <= it) ++k;
+  return k;
+}
+
+// kPair (from 16 words, launches of few items, where one item's latency is
+// the launch's): the two waves of a pair share each CONCAT item, each
+// staging and folding half of the words (whole groups of eight); the second hands its key words to
+// the first through LDS, which probes.  Other items are the first wave's.
+template <int W, bool kInl, bool kPair>
 __global__ __launch_bounds__(256) void gen_pieces(GenArgs a, PieceArgs pa) {
   __shared__ uint64_t lds[4][2 * 64 * W + W];
   if (a.st->stop) return;
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint64_t* X = lds[wave];       // star: X tile; concat: operand tile
-  uint64_t* Y = X + 64 * W;      // star: Y tile
-  uint64_t* U = Y + 64 * W;      // concat: the uniform operand
-  for (uint64_t it = (uint64_t)blockIdx.x * 4 + wave; it < pa.items; it += (uint64_t)gridDim.x * 4) {
-    uint32_t k = 0;
-    while (k + 1 < pa.n && pa.p[k + 1].item0 <= it) ++k;
-    const PieceD& p = pa.p[k];
-    const uint64_t li = it - p.item0;
-    uint64_t key[W];
-    bool valid = false, dup = false;
-    uint64_t e = 0;
-    if (p.op == OP_CHAR || p.op == OP_QUESTION || p.op == OP_UNION) {
-      e = p.e0 + 64 * li + lane;
-      valid = e < p.e1;
-      if (p.op == OP_CHAR) {
-        const int idx = valid ? a.char_index[p.char_off + e] : -1;
-#pragma unroll
-        for (int q = 0; q < W; ++q) key[q] = (idx >= 0 && (idx >> 6) == q) ? (1ull << (idx & 63)) : 0ull;
-      } else if (p.op == OP_QUESTION) {
-        const uint64_t* src = a.rows + (p.lstart + (valid ? e : 0)) * W;
-#pragma unroll
-        for (int q = 0; q < W; ++q) key[q] = valid ? src[q] : 0ull;
-        dup = (key[0] & 1ull) != 0;
-        key[0] |= 1ull;
+  if constexpr (!kPair) {
+    uint64_t* X = lds[wave];       // star: X tile; concat: operand tile
+    uint64_t* Y = X + 64 * W;      // star: Y tile
+    uint64_t* U = Y + 64 * W;      // concat: the uniform operand
+    for (uint64_t it = (uint64_t)blockIdx.x * 4 + wave; it < pa.items; it += (uint64_t)gridDim.x * 4) {
+      const PieceD& p = pa.p[piece_of(pa, it)];
+      const uint64_t li = it - p.item0;
+      uint64_t key[W];
+      bool valid = false, dup = false;
+      uint64_t e = 0;
+      if (p.op != OP_CONCAT) {
+        piece_simple<W>(a, p, li, lane, X, Y, key, &valid, &dup, &e);
       } else {
-        uint64_t i = 0, j = 0;
-        if (valid) {
-          if (p.same) {
-            tri_decode(e, p.lcount, &i, &j);
-          } else {
-            i = e / p.rcount;
-            j = e - i * p.rcount;
-          }
-        }
-        const uint64_t* x = a.rows + (p.lstart + i) * W;
-        const uint64_t* y = a.rows + (p.rstart + j) * W;
-        bool eqx = true, eqy = true;
-#pragma unroll
-        for (int q = 0; q < W; ++q) {
-          const uint64_t xv = valid ? x[q] : 0ull, yv = valid ? y[q] : 0ull;
-          key[q] = xv | yv;
-          eqx = eqx && key[q] == xv;
-          eqy = eqy && key[q] == yv;
-        }
-        dup = eqx || eqy;
-      }
-    } else if (p.op == OP_STAR) {
-      // Y(eps) = 1; by increasing length, Y(w) = OR over cuts with a
-      // non-empty first factor of X(u) & Y(v)
-      e = p.e0 + 64 * li + lane;
-      valid = e < p.e1;
-#pragma unroll
-      for (int q = 0; q < W; ++q) {
-        X[64 * q + lane] = transpose64(valid ? a.rows[(p.lstart + e) * W + q] : 0ull);
-        Y[64 * q + lane] = (q == 0 && lane == 0) ? ~0ull : 0ull;
-      }
-      wave_sync_lds();
-      for (uint32_t l = 1; l <= a.max_len; ++l) {
-        const uint32_t lo = a.len_off[l], hi = a.len_off[l + 1];
-        for (uint32_t w = lo + lane; w < hi; w += 64) Y[w] = star_fold(X, Y, a.gt_pair, a.gt_off[w], l);
+        concat_stage<W>(a, p, li, lane, X, U, 0, W, true, &e, &valid);
         wave_sync_lds();
+        concat_fold<W>(a, p, lane, X, U, 0, W, key);
       }
-#pragma unroll
-      for (int q = 0; q < W; ++q) key[q] = transpose64(Y[64 * q + lane]);
-    } else {  // OP_CONCAT
-      const uint64_t nR = p.rcount, nL = p.lcount;
-      uint64_t i, j;
-      if (!p.left_lanes) {  // right rows across the lanes, one left row
-        i = p.t0 + li / p.nt;
-        j = 64 * (li % p.nt) + lane;
-#pragma unroll
-        for (int q = 0; q < W; ++q) X[64 * q + lane] = transpose64(j < nR ? a.rows[(p.rstart + j) * W + q] : 0ull);
-        if (lane < (uint32_t)W) U[lane] = a.rows[(p.lstart + i) * W + lane];
-        valid = j < nR;
-      } else {  // left rows across the lanes, one right row
-        i = 64 * (p.t0 + li / p.nt) + lane;
-        j = li % p.nt;
-#pragma unroll
-        for (int q = 0; q < W; ++q) X[64 * q + lane] = transpose64(i < nL ? a.rows[(p.lstart + i) * W + q] : 0ull);
-        if (lane < (uint32_t)W) U[lane] = a.rows[(p.rstart + j) * W + lane];
-        valid = i < nL;
-      }
-      wave_sync_lds();
-      if constexpr (W >= 8) {
-        // cut position outer, eight of the lane's words inner: 24
-        // independent reads per round (each word's read clamped to its last
-        // cut, masked after)
-#pragma unroll
-        for (int q0 = 0; q0 < W; q0 += 8) {
-          uint32_t first[8], last[8], cnt[8];
-          uint64_t acc[8];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const uint32_t w = 64u * (q0 + q) + lane;
-            first[q] = w < a.n ? a.gt_off[w] : 0u;
-            cnt[q] = w < a.n ? a.gt_off[w + 1] - first[q] : 0u;
-            last[q] = first[q] + (cnt[q] ? cnt[q] - 1 : 0u);
-            acc[q] = 0;
-          }
-          for (uint32_t c = 0; c <= a.max_len; ++c) {
-            uint32_t pr[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) pr[q] = a.gt_pair[min(first[q] + c, last[q])];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              const uint32_t uu = p.left_lanes ? (pr[q] & 0xFFFFu) : (pr[q] >> 16);  // index into the uniform row
-              const uint32_t tt = p.left_lanes ? (pr[q] >> 16) : (pr[q] & 0xFFFFu);  // index into the tile
-              const uint64_t xv = X[tt];
-              const bool on = c < cnt[q] && ((U[uu >> 6] >> (uu & 63)) & 1ull);
-              acc[q] |= on ? xv : 0ull;
-            }
-          }
-#pragma unroll
-          for (int q = 0; q < 8; ++q) key[q0 + q] = transpose64(acc[q]);
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < W; ++q) {
-          const uint32_t w = 64u * q + lane;
-          uint64_t acc = 0;
-          if (w < a.n) {
-            const uint32_t q1 = a.gt_off[w + 1];
-            for (uint32_t c = a.gt_off[w]; c < q1; ++c) {
-              const uint32_t pr = a.gt_pair[c];
-              const uint32_t uu = p.left_lanes ? (pr & 0xFFFFu) : (pr >> 16);   // index into the uniform row
-              const uint32_t tt = p.left_lanes ? (pr >> 16) : (pr & 0xFFFFu);   // index into the tile
-              if ((U[uu >> 6] >> (uu & 63)) & 1ull) acc |= X[tt];
-            }
-          }
-          key[q] = transpose64(acc);
-        }
-      }
-      e = i * nR + j;
-      valid = valid && e >= p.e0 && e < p.e1;
+      filter_emit<W, kInl>(a, valid, dup, key, valid ? (uint32_t)(e - p.e0) + p.rel0 : 0u);
+      wave_sync_lds();  // the tiles are rewritten by the next item
     }
-    filter_emit<W, kInl>(a, valid, dup, key, valid ? (uint32_t)(e - p.e0) + p.rel0 : 0u);
-    wave_sync_lds();  // the tiles are rewritten by the next item
+  } else {
+    static_assert(W >= 16, "each wave of a pair folds whole groups of eight words");
+    constexpr int kHalf = W / 2;
+    const uint32_t pair = wave >> 1, half = wave & 1;
+    uint64_t* X = lds[2 * pair];
+    uint64_t* Y = X + 64 * W;
+    uint64_t* U = Y + 64 * W;
+    uint64_t* K = lds[2 * pair + 1];  // the second wave's key words, [q - kHalf][lane]
+    // every wave takes the same number of rounds (workgroup barriers inside)
+    for (uint64_t base = (uint64_t)blockIdx.x * 2; base < pa.items; base += (uint64_t)gridDim.x * 2) {
+      const uint64_t it = base + pair;
+      const bool have = it < pa.items;
+      const PieceD& p = pa.p[have ? piece_of(pa, it) : 0];
+      const uint64_t li = have ? it - p.item0 : 0;
+      const bool cat = have && p.op == OP_CONCAT;
+      uint64_t key[W];
+      bool valid = false, dup = false;
+      uint64_t e = 0;
+      if (cat) concat_stage<W>(a, p, li, lane, X, U, half * kHalf, half * kHalf + kHalf, half == 0, &e, &valid);
+      __syncthreads();
+      if (cat) {
+        concat_fold<W>(a, p, lane, X, U, half * kHalf, half * kHalf + kHalf, key);
+        if (half == 1) {
+#pragma unroll
+          for (int q = kHalf; q < W; ++q) K[64 * (q - kHalf) + lane] = key[q];
+        }
+      }
+      __syncthreads();
+      if (half == 0 && have) {
+        if (cat) {
+#pragma unroll
+          for (int q = kHalf; q < W; ++q) key[q] = K[64 * (q - kHalf) + lane];
+        } else {
+          piece_simple<W>(a, p, li, lane, X, Y, key, &valid, &dup, &e);
+        }
+        filter_emit<W, kInl>(a, valid, dup, key, valid ? (uint32_t)(e - p.e0) + p.rel0 : 0u);
+      }
+      __syncthreads();  // the tiles are rewritten in the next round
+    }
   }
 }
 
@@ -1002,6 +1085,8 @@ hipError_t launch_concat_set(int W, const GenArgs& a, const ConcatSet& cs, hipSt
   return hipGetLastError();
 }
 
+constexpr uint64_t kPairItemsMax = 1024;  // gen_pieces items up to which wide concatenations take two waves
+
 hipError_t launch_gen_pieces(int W, const GenArgs& a, const PieceArgs& p, hipStream_t s) {
   if (p.items == 0) return hipSuccess;
   if (W > kPiecesMaxW || p.n > (uint32_t)kMaxPieces) return hipErrorInvalidValue;
@@ -1015,19 +1100,32 @@ hipError_t launch_gen_pieces(int W, const GenArgs& a, const PieceArgs& p, hipStr
     if ((d.op == OP_UNION && !d.same && d.rcount == 0) || (d.op != OP_CHAR && d.lcount == 0))
       return hipErrorInvalidValue;
   }
-  const uint32_t grid = (uint32_t)std::min<uint64_t>((p.items + 3) / 4, 4096);
+  // few items (one item's latency is the launch's): from 16 words, two
+  // waves per concatenation item
+  const bool pair = W >= 16 && p.items <= kPairItemsMax;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(pair ? (p.items + 1) / 2 : (p.items + 3) / 4, 4096);
   switch (W) {
     case 1:
       if (a.inl)
-        launch_timed(gen_pieces<1, true>, dim3(grid), dim3(256), 0, s, a, p);
+        launch_timed(gen_pieces<1, true, false>, dim3(grid), dim3(256), 0, s, a, p);
       else
-        launch_timed(gen_pieces<1, false>, dim3(grid), dim3(256), 0, s, a, p);
+        launch_timed(gen_pieces<1, false, false>, dim3(grid), dim3(256), 0, s, a, p);
       break;
-    case 2: launch_timed(gen_pieces<2, false>, dim3(grid), dim3(256), 0, s, a, p); break;
-    case 4: launch_timed(gen_pieces<4, false>, dim3(grid), dim3(256), 0, s, a, p); break;
-    case 8: launch_timed(gen_pieces<8, false>, dim3(grid), dim3(256), 0, s, a, p); break;
-    case 16: launch_timed(gen_pieces<16, false>, dim3(grid), dim3(256), 0, s, a, p); break;
-    case 32: launch_timed(gen_pieces<32, false>, dim3(grid), dim3(256), 0, s, a, p); break;
+    case 2: launch_timed(gen_pieces<2, false, false>, dim3(grid), dim3(256), 0, s, a, p); break;
+    case 4: launch_timed(gen_pieces<4, false, false>, dim3(grid), dim3(256), 0, s, a, p); break;
+    case 8: launch_timed(gen_pieces<8, false, false>, dim3(grid), dim3(256), 0, s, a, p); break;
+    case 16:
+      if (pair)
+        launch_timed(gen_pieces<16, false, true>, dim3(grid), dim3(256), 0, s, a, p);
+      else
+        launch_timed(gen_pieces<16, false, false>, dim3(grid), dim3(256), 0, s, a, p);
+      break;
+    case 32:
+      if (pair)
+        launch_timed(gen_pieces<32, false, true>, dim3(grid), dim3(256), 0, s, a, p);
+      else
+        launch_timed(gen_pieces<32, false, false>, dim3(grid), dim3(256), 0, s, a, p);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
