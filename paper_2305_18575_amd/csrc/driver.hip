@@ -451,15 +451,18 @@ bool make_blocks(const rei_instance* in, uint32_t c, std::vector<Block>* out, bo
 
 // Waits until every chunk enqueued so far is accounted; the search state is
 // then in the host mirrors (h_state, h_levels), which the accounting writes
-// with the device state, its chunk count last.  The host watches that count
-// (a few microseconds sooner than the stream's completion) for at most
-// kSpinUs; a search that stopped (whose later chunks account nothing), or
-// one still running then, waits for the stream.
+// with the device state, its chunk count last.  At a level boundary
+// (drain = false) the host watches that count (a few microseconds sooner
+// than the stream's completion) for at most kSpinUs; a search that stopped
+// (whose later chunks account nothing), or one still running then, waits
+// for the stream.  drain = true waits for the stream in any case: buffers
+// may be freed next, and other work on the stream (fills, rehashes, copies)
+// may still use them.
 constexpr double kSpinUs = 2000;
-rei_status sync_state(rei_instance* in, hipStream_t s) {
+rei_status sync_state(rei_instance* in, hipStream_t s, bool drain) {
   const double t0 = now_s();
   bool seen = false;
-  for (;;) {
+  for (; !drain;) {
     const uint32_t got = __atomic_load_n(&in->h_state->chunks, __ATOMIC_ACQUIRE);
     if (got == in->chunks_enq && !__atomic_load_n(&in->h_state->stop, __ATOMIC_ACQUIRE)) {
       seen = true;
@@ -498,7 +501,7 @@ rei_status enqueue_chunk(rei_instance* in, hipStream_t s, uint32_t c, const std:
   const bool otf_level = in->otf_level != 0;
   if (!otf_level && (worst_rows() > in->rows_alloc || 2 * worst_entries() > in->slots_cap ||
                      len > in->surv_cap || words > in->bitmap_cap)) {
-    if ((r = sync_state(in, s)) != REI_OK) return r;
+    if ((r = sync_state(in, s, true)) != REI_OK) return r;
     if (in->h_state->stop) {
       *stopped = true;
       return REI_OK;
@@ -1065,7 +1068,7 @@ rei_status search_levels(rei_instance* in, hipStream_t s) {
     }
     if (!stopped && !pieces.empty() && (r = enqueue_chunk(in, s, c, pieces, &stopped)) != REI_OK) return r;
     // level boundary: the next level's blocks depend on this level's size
-    if ((r = sync_state(in, s)) != REI_OK) return r;
+    if ((r = sync_state(in, s, false)) != REI_OK) return r;
     in->lcount[c] = in->h_levels[c];
     if (in->h_state->stop) stopped = true;
     if (!stopped && blocked) {
@@ -1074,7 +1077,11 @@ rei_status search_levels(rei_instance* in, hipStream_t s) {
     }
     if (in->h_state->otf && !in->otf_level) in->otf_level = c;
   }
+  // a stopped search's last wait was on the stream; one that ran out of
+  // levels last waited on the mirrors: its launches end before the caller
+  // gets the result
   if (in->h_state->stop == STOP_ANSWER) return device_tree(in, s);
+  if (!in->h_state->stop) HIP_OK(in, hipStreamSynchronize(s));
   return REI_OK;
 }
 
