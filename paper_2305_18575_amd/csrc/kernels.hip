@@ -437,8 +437,10 @@ __device__ __forceinline__ uint32_t piece_of(const PieceArgs& pa, uint64_t it) {
 
 // kPair (from 16 words, launches of few items, where one item's latency is
 // the launch's): the two waves of a pair share each CONCAT item, each
-// staging and folding half of the words (whole groups of eight); the second hands its key words to
-// the first through LDS, which probes.  Other items are the first wave's.
+// staging and folding half of the words (whole groups of eight), and each
+// STAR item (each stages half of the words; the words of each length are
+// dealt to both); the second hands its key words to the first through LDS,
+// which probes.  Other items are the first wave's.
 template <int W, bool kInl, bool kPair>
 __global__ __launch_bounds__(256) void gen_pieces(GenArgs a, PieceArgs pa) {
   __shared__ uint64_t lds[4][2 * 64 * W + W];
@@ -479,21 +481,50 @@ __global__ __launch_bounds__(256) void gen_pieces(GenArgs a, PieceArgs pa) {
       const PieceD& p = pa.p[have ? piece_of(pa, it) : 0];
       const uint64_t li = have ? it - p.item0 : 0;
       const bool cat = have && p.op == OP_CONCAT;
+      const bool star = have && p.op == OP_STAR;
+      const int q_lo = half * kHalf, q_hi = q_lo + kHalf;  // this wave's words
       uint64_t key[W];
       bool valid = false, dup = false;
       uint64_t e = 0;
-      if (cat) concat_stage<W>(a, p, li, lane, X, U, half * kHalf, half * kHalf + kHalf, half == 0, &e, &valid);
-      __syncthreads();
-      if (cat) {
-        concat_fold<W>(a, p, lane, X, U, half * kHalf, half * kHalf + kHalf, key);
-        if (half == 1) {
+      if (cat) concat_stage<W>(a, p, li, lane, X, U, q_lo, q_hi, half == 0, &e, &valid);
+      if (star) {
+        // r* of 64 rows: each wave stages its words of X and Y
+        e = p.e0 + 64 * li + lane;
+        valid = e < p.e1;
 #pragma unroll
-          for (int q = kHalf; q < W; ++q) K[64 * (q - kHalf) + lane] = key[q];
+        for (int q = 0; q < W; ++q)
+          if (q >= q_lo && q < q_hi) {
+            X[64 * q + lane] = transpose64(valid ? a.rows[(p.lstart + e) * W + q] : 0ull);
+            Y[64 * q + lane] = (q == 0 && lane == 0) ? ~0ull : 0ull;
+          }
+      }
+      // (uniform over the workgroup: the star's barriers below are taken by
+      // all of its waves or by none)
+      const bool any_star = __syncthreads_or(star);
+      if (any_star) {
+        // Y(w) by increasing length from shorter words' Y: the words of one
+        // length dealt to both waves of the pair, a barrier per length
+        for (uint32_t l = 1; l <= a.max_len; ++l) {
+          if (star) {
+            const uint32_t lo = a.len_off[l], hi = a.len_off[l + 1];
+            for (uint32_t w = lo + lane + 64 * half; w < hi; w += 128) Y[w] = star_fold(X, Y, a.gt_pair, a.gt_off[w], l);
+          }
+          __syncthreads();
         }
+      }
+      if (cat) concat_fold<W>(a, p, lane, X, U, q_lo, q_hi, key);
+      if (star) {
+#pragma unroll
+        for (int q = 0; q < W; ++q)
+          if (q >= q_lo && q < q_hi) key[q] = transpose64(Y[64 * q + lane]);
+      }
+      if ((cat || star) && half == 1) {
+#pragma unroll
+        for (int q = kHalf; q < W; ++q) K[64 * (q - kHalf) + lane] = key[q];
       }
       __syncthreads();
       if (half == 0 && have) {
-        if (cat) {
+        if (cat || star) {
 #pragma unroll
           for (int q = kHalf; q < W; ++q) key[q] = K[64 * (q - kHalf) + lane];
         } else {
