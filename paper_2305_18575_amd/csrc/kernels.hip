@@ -372,21 +372,22 @@ __device__ __forceinline__ void concat_stage(const GenArgs& a, const PieceD& p, 
   *valid = have && e >= p.e0 && e < p.e1;
 }
 
-// The fold of a CONCAT item for output words [q_lo, q_hi) (X and U staged):
-// key[q] for those q.  From 8 words, cut position outer over eight of the
-// lane's words at a time, 24 independent reads per round (each word's read
-// clamped to its last cut, masked after); below, per word.
-template <int W>
+// The fold of a CONCAT item for output words [q_lo, q_hi) (X and U staged;
+// q_lo and q_hi multiples of kG): key[q] for those q.  From 8 words, cut
+// position outer over kG of the lane's words at a time, 3 kG independent
+// reads per round (each word's read clamped to its last cut, masked
+// after); below, per word.
+template <int W, int kG = 8>
 __device__ __forceinline__ void concat_fold(const GenArgs& a, const PieceD& p, uint32_t lane, const uint64_t* X,
                                             const uint64_t* U, int q_lo, int q_hi, uint64_t (&key)[W]) {
   if constexpr (W >= 8) {
 #pragma unroll
-    for (int q0 = 0; q0 < W; q0 += 8) {
+    for (int q0 = 0; q0 < W; q0 += kG) {
       if (q0 < q_lo || q0 >= q_hi) continue;
-      uint32_t first[8], last[8], cnt[8];
-      uint64_t acc[8];
+      uint32_t first[kG], last[kG], cnt[kG];
+      uint64_t acc[kG];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int q = 0; q < kG; ++q) {
         const uint32_t w = 64u * (q0 + q) + lane;
         first[q] = w < a.n ? a.gt_off[w] : 0u;
         cnt[q] = w < a.n ? a.gt_off[w + 1] - first[q] : 0u;
@@ -394,11 +395,11 @@ __device__ __forceinline__ void concat_fold(const GenArgs& a, const PieceD& p, u
         acc[q] = 0;
       }
       for (uint32_t c = 0; c <= a.max_len; ++c) {
-        uint32_t pr[8];
+        uint32_t pr[kG];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) pr[q] = a.gt_pair[min(first[q] + c, last[q])];
+        for (int q = 0; q < kG; ++q) pr[q] = a.gt_pair[min(first[q] + c, last[q])];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < kG; ++q) {
           const uint32_t uu = p.left_lanes ? (pr[q] & 0xFFFFu) : (pr[q] >> 16);  // index into the uniform row
           const uint32_t tt = p.left_lanes ? (pr[q] >> 16) : (pr[q] & 0xFFFFu);  // index into the tile
           const uint64_t xv = X[tt];
@@ -407,7 +408,7 @@ __device__ __forceinline__ void concat_fold(const GenArgs& a, const PieceD& p, u
         }
       }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) key[q0 + q] = transpose64(acc[q]);
+      for (int q = 0; q < kG; ++q) key[q0 + q] = transpose64(acc[q]);
     }
   } else {
 #pragma unroll
@@ -435,18 +436,18 @@ __device__ __forceinline__ uint32_t piece_of(const PieceArgs& pa, uint64_t it) {
   return k;
 }
 
-// kPair (from 16 words, launches of few items, where one item's latency is
-// the launch's): the two waves of a pair share each CONCAT item, each
-// staging and folding half of the words (whole groups of eight), and each
-// STAR item (each stages half of the words; the words of each length are
-// dealt to both); the second hands its key words to the first through LDS,
-// which probes.  Other items are the first wave's.
-template <int W, bool kInl, bool kPair>
+// kSplit (from 16 words, launches of few items, where one item's latency
+// is the launch's): kSplit waves (2 or 4) share each CONCAT item, each
+// staging and folding W / kSplit of the words, and each STAR item (each
+// stages its words; the words of each length are dealt to all of them);
+// the others hand their key words to the first through LDS, which probes.
+// Other items are the first wave's.
+template <int W, bool kInl, int kSplit>
 __global__ __launch_bounds__(256) void gen_pieces(GenArgs a, PieceArgs pa) {
   __shared__ uint64_t lds[4][2 * 64 * W + W];
   if (a.st->stop) return;
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if constexpr (!kPair) {
+  if constexpr (kSplit == 1) {
     uint64_t* X = lds[wave];       // star: X tile; concat: operand tile
     uint64_t* Y = X + 64 * W;      // star: Y tile
     uint64_t* U = Y + 64 * W;      // concat: the uniform operand
@@ -467,26 +468,28 @@ __global__ __launch_bounds__(256) void gen_pieces(GenArgs a, PieceArgs pa) {
       wave_sync_lds();  // the tiles are rewritten by the next item
     }
   } else {
-    static_assert(W >= 16, "each wave of a pair folds whole groups of eight words");
-    constexpr int kHalf = W / 2;
-    const uint32_t pair = wave >> 1, half = wave & 1;
-    uint64_t* X = lds[2 * pair];
+    constexpr int kPart = W / kSplit;          // words per wave
+    constexpr int kG = kPart < 8 ? kPart : 8;  // fold group
+    constexpr uint32_t kItems = 4 / kSplit;    // items per workgroup round
+    static_assert((kSplit == 2 || kSplit == 4) && kPart >= 4 && kPart % kG == 0, "whole fold groups per wave");
+    const uint32_t slot = wave / kSplit, part = wave % kSplit;
+    uint64_t* X = lds[kSplit * slot];
     uint64_t* Y = X + 64 * W;
     uint64_t* U = Y + 64 * W;
-    uint64_t* K = lds[2 * pair + 1];  // the second wave's key words, [q - kHalf][lane]
+    uint64_t* K = lds[kSplit * slot + 1];  // the other waves' key words, [q - kPart][lane]
+    const int q_lo = (int)part * kPart, q_hi = q_lo + kPart;  // this wave's words
     // every wave takes the same number of rounds (workgroup barriers inside)
-    for (uint64_t base = (uint64_t)blockIdx.x * 2; base < pa.items; base += (uint64_t)gridDim.x * 2) {
-      const uint64_t it = base + pair;
+    for (uint64_t base = (uint64_t)blockIdx.x * kItems; base < pa.items; base += (uint64_t)gridDim.x * kItems) {
+      const uint64_t it = base + slot;
       const bool have = it < pa.items;
       const PieceD& p = pa.p[have ? piece_of(pa, it) : 0];
       const uint64_t li = have ? it - p.item0 : 0;
       const bool cat = have && p.op == OP_CONCAT;
       const bool star = have && p.op == OP_STAR;
-      const int q_lo = half * kHalf, q_hi = q_lo + kHalf;  // this wave's words
       uint64_t key[W];
       bool valid = false, dup = false;
       uint64_t e = 0;
-      if (cat) concat_stage<W>(a, p, li, lane, X, U, q_lo, q_hi, half == 0, &e, &valid);
+      if (cat) concat_stage<W>(a, p, li, lane, X, U, q_lo, q_hi, part == 0, &e, &valid);
       if (star) {
         // r* of 64 rows: each wave stages its words of X and Y
         e = p.e0 + 64 * li + lane;
@@ -503,30 +506,32 @@ __global__ __launch_bounds__(256) void gen_pieces(GenArgs a, PieceArgs pa) {
       const bool any_star = __syncthreads_or(star);
       if (any_star) {
         // Y(w) by increasing length from shorter words' Y: the words of one
-        // length dealt to both waves of the pair, a barrier per length
+        // length dealt to the item's waves, a barrier per length
         for (uint32_t l = 1; l <= a.max_len; ++l) {
           if (star) {
             const uint32_t lo = a.len_off[l], hi = a.len_off[l + 1];
-            for (uint32_t w = lo + lane + 64 * half; w < hi; w += 128) Y[w] = star_fold(X, Y, a.gt_pair, a.gt_off[w], l);
+            for (uint32_t w = lo + lane + 64 * part; w < hi; w += 64 * kSplit)
+              Y[w] = star_fold(X, Y, a.gt_pair, a.gt_off[w], l);
           }
           __syncthreads();
         }
       }
-      if (cat) concat_fold<W>(a, p, lane, X, U, q_lo, q_hi, key);
+      if (cat) concat_fold<W, kG>(a, p, lane, X, U, q_lo, q_hi, key);
       if (star) {
 #pragma unroll
         for (int q = 0; q < W; ++q)
           if (q >= q_lo && q < q_hi) key[q] = transpose64(Y[64 * q + lane]);
       }
-      if ((cat || star) && half == 1) {
+      if ((cat || star) && part != 0) {
 #pragma unroll
-        for (int q = kHalf; q < W; ++q) K[64 * (q - kHalf) + lane] = key[q];
+        for (int q = 0; q < W; ++q)
+          if (q >= q_lo && q < q_hi) K[64 * (q - kPart) + lane] = key[q];
       }
       __syncthreads();
-      if (half == 0 && have) {
+      if (part == 0 && have) {
         if (cat || star) {
 #pragma unroll
-          for (int q = kHalf; q < W; ++q) key[q] = K[64 * (q - kHalf) + lane];
+          for (int q = kPart; q < W; ++q) key[q] = K[64 * (q - kPart) + lane];
         } else {
           piece_simple<W>(a, p, li, lane, X, Y, key, &valid, &dup, &e);
         }
@@ -1116,7 +1121,8 @@ hipError_t launch_concat_set(int W, const GenArgs& a, const ConcatSet& cs, hipSt
   return hipGetLastError();
 }
 
-constexpr uint64_t kPairItemsMax = 1024;  // gen_pieces items up to which wide concatenations take two waves
+constexpr uint64_t kPairItemsMax = 1024;  // gen_pieces items up to which a wide item takes two waves
+constexpr uint64_t kQuadItemsMax = 256;   // ... and up to which four
 
 hipError_t launch_gen_pieces(int W, const GenArgs& a, const PieceArgs& p, hipStream_t s) {
   if (p.items == 0) return hipSuccess;
@@ -1131,34 +1137,34 @@ hipError_t launch_gen_pieces(int W, const GenArgs& a, const PieceArgs& p, hipStr
     if ((d.op == OP_UNION && !d.same && d.rcount == 0) || (d.op != OP_CHAR && d.lcount == 0))
       return hipErrorInvalidValue;
   }
-  // few items (one item's latency is the launch's): from 16 words, two
-  // waves per concatenation item
-  const bool pair = W >= 16 && p.items <= kPairItemsMax;
-  const uint32_t grid = (uint32_t)std::min<uint64_t>(pair ? (p.items + 1) / 2 : (p.items + 3) / 4, 4096);
+  // few items (one item's latency is the launch's): from 16 words, two or
+  // four waves per concatenation or star item
+  const int split = W < 16 ? 1 : p.items <= kQuadItemsMax ? 4 : p.items <= kPairItemsMax ? 2 : 1;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((p.items * split + 3) / 4, 4096);
+#define REI_PIECES_SPLIT(WW)                                                                   \
+  do {                                                                                         \
+    if (split == 4)                                                                            \
+      launch_timed(gen_pieces<WW, false, 4>, dim3(grid), dim3(256), 0, s, a, p);                \
+    else if (split == 2)                                                                       \
+      launch_timed(gen_pieces<WW, false, 2>, dim3(grid), dim3(256), 0, s, a, p);                \
+    else                                                                                       \
+      launch_timed(gen_pieces<WW, false, 1>, dim3(grid), dim3(256), 0, s, a, p);                \
+  } while (0)
   switch (W) {
     case 1:
       if (a.inl)
-        launch_timed(gen_pieces<1, true, false>, dim3(grid), dim3(256), 0, s, a, p);
+        launch_timed(gen_pieces<1, true, 1>, dim3(grid), dim3(256), 0, s, a, p);
       else
-        launch_timed(gen_pieces<1, false, false>, dim3(grid), dim3(256), 0, s, a, p);
+        launch_timed(gen_pieces<1, false, 1>, dim3(grid), dim3(256), 0, s, a, p);
       break;
-    case 2: launch_timed(gen_pieces<2, false, false>, dim3(grid), dim3(256), 0, s, a, p); break;
-    case 4: launch_timed(gen_pieces<4, false, false>, dim3(grid), dim3(256), 0, s, a, p); break;
-    case 8: launch_timed(gen_pieces<8, false, false>, dim3(grid), dim3(256), 0, s, a, p); break;
-    case 16:
-      if (pair)
-        launch_timed(gen_pieces<16, false, true>, dim3(grid), dim3(256), 0, s, a, p);
-      else
-        launch_timed(gen_pieces<16, false, false>, dim3(grid), dim3(256), 0, s, a, p);
-      break;
-    case 32:
-      if (pair)
-        launch_timed(gen_pieces<32, false, true>, dim3(grid), dim3(256), 0, s, a, p);
-      else
-        launch_timed(gen_pieces<32, false, false>, dim3(grid), dim3(256), 0, s, a, p);
-      break;
+    case 2: launch_timed(gen_pieces<2, false, 1>, dim3(grid), dim3(256), 0, s, a, p); break;
+    case 4: launch_timed(gen_pieces<4, false, 1>, dim3(grid), dim3(256), 0, s, a, p); break;
+    case 8: launch_timed(gen_pieces<8, false, 1>, dim3(grid), dim3(256), 0, s, a, p); break;
+    case 16: REI_PIECES_SPLIT(16); break;
+    case 32: REI_PIECES_SPLIT(32); break;
     default: return hipErrorInvalidValue;
   }
+#undef REI_PIECES_SPLIT
   return hipGetLastError();
 }
 
