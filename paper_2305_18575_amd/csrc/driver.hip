@@ -1378,7 +1378,21 @@ rei_status batch_launch(rei_instance* const* insts, size_t n, hipStream_t s, uin
       for (BatchDesc& d : groups[g]) d.time_ticks = 0;
   // One launch per word width; the first on s, the others on side streams
   // that start after s's earlier work and that s waits for, so the groups
-  // run side by side.
+  // run side by side.  The fork is recorded before the first launch: after
+  // it, the side streams would wait for the first group to finish.
+  {
+    rei_instance* lead = nullptr;
+    int n_groups = 0;
+    for (int g = 0; g <= kBatchMaxW; g = g ? 2 * g : 1)
+      if (!groups[g].empty()) {
+        if (!lead) lead = run->members[g][0];
+        ++n_groups;
+      }
+    if (n_groups > 1) {
+      if ((r = event_acquire(lead, &run->fork)) != REI_OK) return r;
+      HIP_OK(lead, hipEventRecord(run->fork, s));
+    }
+  }
   bool first = true;
   for (int g = 0; g <= kBatchMaxW; g = g ? 2 * g : 1) {
     if (groups[g].empty()) continue;
@@ -1389,10 +1403,6 @@ rei_status batch_launch(rei_instance* const* insts, size_t n, hipStream_t s, uin
     std::memcpy(db.h, groups[g].data(), groups[g].size() * sizeof(BatchDesc));
     hipStream_t gs = s;
     if (!first) {
-      if (!run->fork) {
-        if ((r = event_acquire(in0, &run->fork)) != REI_OK) return r;
-        HIP_OK(in0, hipEventRecord(run->fork, s));
-      }
       SideStream ss;
       if ((r = side_acquire(in0, &ss)) != REI_OK) return r;
       run->sides.push_back(ss);
