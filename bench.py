@@ -52,6 +52,7 @@ PROBE_BYTES = 64
 TRAFFIC = {
     ("large", "gen_pieces"): (3415311, "profiles/large_workload_kernels.md (16-word launches of the timed and event steps)"),
     ("row1", "gen_concat"): (369546757, "profiles/table1_row1_kernels.md (launches of the timed and event steps)"),
+    ("single", "solve_batch"): (57411487, "profiles/single_workload_kernels.md (both word widths' launches of the timed and event steps)"),
 }
 
 
