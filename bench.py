@@ -386,7 +386,7 @@ def main():
     if not args.sequential and args.warmup and not args.no_tune:
         # launch shapes chosen by measurement (untimed): the per-chunk path's
         # chunk sizes and concatenation shape per word width (timed on at
-        # most 16 of the instances: the tuner solves each one 57 times), then
+        # most 16 of the instances: the tuner solves each one 60 times), then
         # the batched solver's threads per instance and hand-off size
         tuned = {"grid": rei.tune_grid(handles[:16], stream)}
         tuned.update(rei.tune_batch(handles, stream))

@@ -247,7 +247,7 @@ rei_status rei_tune_batch(rei_instance *const *insts, size_t n, void *hip_stream
 
 /* Autotuner of rei_solve's per-chunk path, by whole solves: for the
  * instances of each word width present, the first chunk of a level
- * (2^14 .. 2^18 candidates; each next chunk doubles), the largest chunk
+ * (2^14 .. 2^19 candidates; each next chunk doubles), the largest chunk
  * (2^20 .. 2^24), and the concatenation kernel's grid target (512 .. 8192
  * workgroups) and left rows per workgroup (4 .. 64), one parameter after
  * the other, each value timed as the best of three passes of rei_solve over

@@ -2231,7 +2231,7 @@ rei_status rei_tune_grid(rei_instance* const* insts, size_t n, void* hip_stream,
         return r;
       }
       // one parameter at a time, each over a few values around the defaults
-      const uint64_t firsts[] = {1ull << 14, 1ull << 15, 1ull << 16, 1ull << 17, 1ull << 18};
+      const uint64_t firsts[] = {1ull << 14, 1ull << 15, 1ull << 16, 1ull << 17, 1ull << 18, 1ull << 19};
       const uint64_t maxes[] = {1ull << 20, 1ull << 22, 1ull << 24};
       const uint32_t wgs[] = {512, 1024, 2048, 4096, 8192};
       const uint32_t xis[] = {4, 8, 16, 32, 64};
