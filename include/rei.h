@@ -222,9 +222,9 @@ size_t rei_batch_graph_outside(const rei_batch_graph *g);
 
 /* Autotuner of rei_solve_batch, by whole calls (what the caller waits for,
  * hand-offs included), each setting timed as the shortest of five calls.
- * First the launch shape: every word-width group at 256, 512, then 1024
+ * First the launch shape: every word-width group at 256, 512 and 1024
  * threads per instance (at most 512 with 8 or 16 words per language, 256
- * with 32); the fastest
+ * with 32), the three taking turns, one call each per round; the fastest
  * is kept, for each group present, for groups of its size (by power-of-two
  * size class) in a table of the process that later rei_solve_batch calls on
  * any thread use.  Without an entry, a group gets enough waves per instance

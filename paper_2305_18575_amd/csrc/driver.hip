@@ -2103,14 +2103,19 @@ rei_status rei_tune_batch(rei_instance* const* insts, size_t n, void* hip_stream
       return REI_OK;
     };
     // Launch shape: every group at one shape, whole calls timed (what the
-    // caller waits for, hand-offs included, not the launches alone).
+    // caller waits for, hand-offs included, not the launches alone); the
+    // shapes take turns, one call each per round over five rounds, so that
+    // drift during tuning favours none of them.
     double shape_s[3] = {1e300, 1e300, 1e300};
-    for (int q = 0; q < 3; ++q) {
-      g_force_threads.store(cand[q]);
-      r = time_calls(&shape_s[q]);
-      g_force_threads.store(0);
-      if (r != REI_OK) return r;
-    }
+    for (int round = 0; round < 5; ++round)
+      for (int q = 0; q < 3; ++q) {
+        g_force_threads.store(cand[q]);
+        const double t = now_s();
+        r = rei_solve_batch(insts, n, hip_stream, arena_bytes, res.data());
+        shape_s[q] = std::min(shape_s[q], now_s() - t);
+        g_force_threads.store(0);
+        if (r != REI_OK) return r;
+      }
     const int bq = (int)(std::min_element(shape_s, shape_s + 3) - shape_s);
     size_t group_n[kBatchMaxW + 1] = {0};
     for (size_t i = 0; i < n; ++i)
